@@ -1,0 +1,384 @@
+#!/usr/bin/env python3
+"""Benchmark of DB-TSDF scan integration on one MI355X.
+
+Default workload: the 200-scan sequence at 10 Hz of 64x1024-point scans fused
+into a 1024x1024x256 grid at 0.05 m (11^3 kernel, 26 direction bins). One step
+is one scan through the whole path (transform, bounds, bins, first-return
+dedup, brick bucketing, eq. 4 AND, eqs. 5-6 counter/sign), plain form: one
+scan per launch sequence, points already resident in HBM.
+
+Also reported on the same scans: the batched form (several scans per launch,
+replayed from a captured HIP graph, bit-identical), the plain form's per-scan
+latency, the served form on 32 robots with Poisson arrivals (continuous
+batching, p50/p99 arrival-to-completion latency), the dominant kernel's HBM
+roofline fraction, and the CPU oracle on the host.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "voxel-updates/s & scans/s (batched vs plain, bit-exact); p50/p99 scan latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "internal.h"):
+        with open(os.path.join(ROOT, "paper_2509_20081_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def pct(a, q):
+    return float(np.percentile(np.asarray(a, dtype=np.float64), q)) if len(a) else None
+
+
+def load_scans(cfg, n, torch):
+    from synth import scene as synth
+    t = time.time()
+    scans = list(synth.config_scans(cfg, 0, range(n)))
+    dev = [(pose, torch.from_numpy(pts).cuda()) for pose, pts in scans]
+    torch.cuda.synchronize()
+    log(f"generated {n} scans of config {cfg} in {time.time() - t:.1f}s "
+        f"({np.mean([len(p) for _, p in scans]):.0f} points/scan)")
+    return scans, dev
+
+
+def run_plain(db, torch, gdef, ks, dev, warmup, steps, tuning, profile=True):
+    g = db.Grid(gdef["dims"], gdef["voxel_size"], gdef["origin"], ks)
+    if tuning:
+        g.set_tuning(**{k: v for k, v in tuning.items() if k != "apply_blocks"})
+    n_seq = len(dev)
+    for k in range(warmup):
+        pose, pts = dev[k % n_seq]
+        g.integrate(pose, pts)
+    g.sync()
+    if profile:
+        g.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for k in range(warmup, warmup + steps):
+        pose, pts = dev[k % n_seq]
+        stats.append(g.integrate(pose, pts))
+    g.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = g.read_profile() if profile else None
+    return g, dt, stats, prof
+
+
+def run_batched(db, torch, gdef, ks, dev, warmup, steps, tuning, per_launch):
+    g = db.Grid(gdef["dims"], gdef["voxel_size"], gdef["origin"], ks)
+    if tuning:
+        g.set_tuning(**{k: v for k, v in tuning.items() if k != "apply_blocks"})
+    b = db.Batch(use_graph=True)
+    n_seq = len(dev)
+
+    def launch(ks_):
+        return b.integrate([(g, dev[k % n_seq][0], dev[k % n_seq][1]) for k in ks_])
+
+    for s in range(0, warmup, per_launch):
+        launch(range(s, min(s + per_launch, warmup)))
+    b.sync()
+    b.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for s in range(warmup, warmup + steps, per_launch):
+        stats.extend(launch(range(s, min(s + per_launch, warmup + steps))))
+    b.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = b.read_profile()
+    caps, reps = b.graph_stats()
+    return g, dt, stats, prof, (caps, reps)
+
+
+def count_traffic(db, gdef, ks, dev, warmup, steps, tuning):
+    """Untimed replay with the unique-word counters on: U_m, C_m, U_s of the timed scans."""
+    g = db.Grid(gdef["dims"], gdef["voxel_size"], gdef["origin"], ks, count_traffic=True)
+    if tuning:
+        g.set_tuning(**{k: v for k, v in tuning.items() if k != "apply_blocks"})
+    n_seq = len(dev)
+    out = []
+    for k in range(warmup + steps):
+        pose, pts = dev[k % n_seq]
+        st = g.integrate(pose, pts)
+        if k >= warmup:
+            out.append(st)
+        if k % 16 == 15:
+            g.sync()
+    g.sync()
+    res = [s.as_dict() for s in out]
+    g.close()
+    return res
+
+
+def plain_latency(db, torch, gdef, ks, dev, n, tuning):
+    g = db.Grid(gdef["dims"], gdef["voxel_size"], gdef["origin"], ks)
+    if tuning:
+        g.set_tuning(**{k: v for k, v in tuning.items() if k != "apply_blocks"})
+    lat = []
+    for k in range(n + 3):
+        pose, pts = dev[k % len(dev)]
+        t0 = time.perf_counter()
+        g.integrate(pose, pts)
+        g.sync()
+        if k >= 3:
+            lat.append((time.perf_counter() - t0) * 1e3)
+    g.close()
+    return lat
+
+
+def run_serve(db, torch, seconds, warm_s, rate_hz, n_robots, scans_per_robot, seed=5):
+    """Served form: n_robots maps of 512^3 @ 0.05 m, Poisson arrivals totalling rate_hz."""
+    from paper_2509_20081_amd.serve import Server, poisson_arrivals, run_open_loop
+    from synth import scene as synth
+    ks = db.KernelSet(kernel_size=11, binning="cube26", shadow_r2=9)
+    t = time.time()
+    robot_scans = [list(synth.config_scans(5, r, range(scans_per_robot))) for r in range(n_robots)]
+    log(f"generated {n_robots}x{scans_per_robot} served scans in {time.time() - t:.1f}s")
+    srv = Server(n_streams=2, max_batch_scans=64, use_graph=True)
+    ids = []
+    for r in range(n_robots):
+        gdef = synth.config_grid(5, r)
+        ids.append(srv.add_map(gdef["dims"], gdef["voxel_size"], gdef["origin"], ks))
+    rng = np.random.default_rng([20081, 5, seed])
+    arr = poisson_arrivals(rng, rate_hz, warm_s + seconds)
+    robots = rng.integers(0, n_robots, size=len(arr))
+    counters = [0] * n_robots
+    schedule = []
+    for toff, r in zip(arr, robots):
+        k = counters[r] % scans_per_robot
+        counters[r] += 1
+        pose, pts = robot_scans[r][k]
+        schedule.append((float(toff), ids[r], pose, pts))
+    log(f"serving {len(schedule)} scans over {warm_s + seconds:.1f}s")
+    done = run_open_loop(srv, schedule, warmup_s=warm_s)
+    meas = [c for c in done if not c["warmup"]]
+    bad = [c for c in done if c["status"] != 0]
+    lat = [(c["t_done_ns"] - c["t_arrival_ns"]) / 1e6 for c in meas]
+    if meas:
+        t_lo = min(c["t_arrival_ns"] for c in meas)
+        t_hi = max(c["t_done_ns"] for c in meas)
+        span = (t_hi - t_lo) / 1e9
+    else:
+        span = float("nan")
+    upd = sum(c["stats"]["voxel_updates"] for c in meas)
+    out = dict(workload="c5_32robots_512cube_poisson", robots=n_robots, offered_scans_per_s=rate_hz,
+               measured_s=seconds, scans=len(meas), failed=len(bad),
+               value=upd / span if span else None, unit="voxel-updates/s",
+               scans_per_s=len(meas) / span if span else None,
+               p50_ms=pct(lat, 50), p99_ms=pct(lat, 99), mean_batch_scans=float(np.mean([c["batch_scans"] for c in meas]))
+               if meas else None, scans_per_robot_replayed=scans_per_robot)
+    srv.close()
+    return out
+
+
+def cpu_baseline(gdef, scans, budget_s=15.0):
+    """The CPU oracle, single-threaded, on the first scans of the same sequence."""
+    from oracle.oracle import Oracle
+    from synth import scene as synth
+    o = Oracle(dims=gdef["dims"], voxel_size=gdef["voxel_size"], origin=gdef["origin"], **synth.KERNEL_DEFAULTS)
+    m, p = o.new_grid()
+    upd, t_tot, n = 0, 0.0, 0
+    for pose, pts in scans:
+        t0 = time.perf_counter()
+        st = o.integrate(m, p, pose, pts)
+        t_tot += time.perf_counter() - t0
+        upd += st["voxel_updates"]
+        n += 1
+        if t_tot > budget_s:
+            break
+    return dict(value=upd / t_tot, unit="voxel-updates/s", cores=1, kind="oracle",
+                sample=f"first {n} scans of the same sequence, single-threaded C oracle, {t_tot:.1f}s",
+                scans_per_s=n / t_tot)
+
+
+def copy_calibration(torch, nbytes=1 << 30):
+    """A plain device copy of known size (for scaling HBM counters of a --pmc run)."""
+    a = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copy calibration: 3 copies of {nbytes} bytes")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200, help="timed scans (plain form)")
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3))
+    ap.add_argument("--batch-scans", type=int, default=8, help="scans per batched launch")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--latency-scans", type=int, default=50)
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-warmup", type=float, default=1.0)
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-robots", type=int, default=32)
+    ap.add_argument("--serve-scans-per-robot", type=int, default=6)
+    ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--tuning", type=str, default="", help="JSON tuning to use instead of autotuning")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU sharding is not built",
+                          "n_gpus": args.gpus}))
+        return 2
+    if int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "launched with WORLD_SIZE > 1; this benchmark is single-GPU"}))
+        return 2
+
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        return 2
+    import paper_2509_20081_amd as db
+    from synth import scene as synth
+
+    if args.copy_calibration:
+        copy_calibration(torch)
+
+    cfg = args.config
+    gdef = synth.config_grid(cfg)
+    n_seq = synth.CONFIGS[cfg]["scans"]
+    scans, dev = load_scans(cfg, min(n_seq, args.warmup + args.steps), torch)
+    ks = db.KernelSet(kernel_size=11, binning="cube26", shadow_r2=9)
+    K3 = 11 ** 3
+
+    tuning = json.loads(args.tuning) if args.tuning else None
+    if tuning is None and not args.no_autotune:
+        g = db.Grid(gdef["dims"], gdef["voxel_size"], gdef["origin"], ks)
+        tuning = g.autotune(dev[:4], True)
+        g.close()
+        log(f"autotuned: {tuning}")
+    if tuning is None:
+        g = db.Grid(gdef["dims"], gdef["voxel_size"], gdef["origin"], ks)
+        tuning = g.tuning
+        g.close()
+
+    # ---- plain form (the measured value)
+    g, dt, stats, prof = run_plain(db, torch, gdef, ks, dev, args.warmup, args.steps, tuning)
+    sd = [s.as_dict() for s in stats]
+    upd = sum(s["voxel_updates"] for s in sd)
+    value = upd / dt
+    log(f"plain: {args.steps} scans in {dt * 1e3:.1f} ms -> {value / 1e9:.1f} G voxel-updates/s; profile {prof}")
+    g.close()
+    torch.cuda.empty_cache()
+
+    # ---- roofline of the dominant kernel (the brick merge / apply)
+    tr = count_traffic(db, gdef, ks, dev, args.warmup, args.steps, tuning)
+    u_m = np.array([t["u_mask"] for t in tr], dtype=np.float64)
+    c_m = np.array([t["c_mask"] for t in tr], dtype=np.float64)
+    u_s = np.array([t["u_shadow"] for t in tr], dtype=np.float64)
+    n_in = np.array([t["n_in"] for t in tr], dtype=np.float64)
+    apply_bytes = float(np.mean(4 * u_m + 4 * c_m + 8 * u_s))
+    scan_bytes = float(np.mean(12 * n_in + 4 * u_m + 4 * c_m + 8 * u_s))
+    apply_ms = prof["apply_ms"] / max(prof["applies"], 1)
+    call_ms = prof["call_ms"] / max(prof["calls"], 1)
+    achieved = apply_bytes / (apply_ms * 1e-3) / 1e9
+    kname = (f"k_apply_brick<{tuning['brick'][0]},{tuning['brick'][1]},{tuning['brick'][2]},"
+             f"{tuning['block_threads']}>" if tuning["strategy"] == "brick" else "k_apply_atomic")
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", f"traffic_c{cfg}.json")
+    if os.path.exists(tfile):
+        tj = json.load(open(tfile))
+        if tj.get("kernel_source_hash") == kernel_source_hash() and tj.get("kernel") == kname:
+            traffic = tj.get("bytes_per_launch")
+    roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
+                    traffic=traffic, kernel=kname, avg_launch_us=apply_ms * 1e3,
+                    algorithmic_bytes_per_launch=apply_bytes,
+                    per_launch="4*U_m + 4*C_m + 8*U_s of one scan (unique mask words read, changed words "
+                               "written, unique shadow words read+written)",
+                    whole_call=dict(avg_us=call_ms * 1e3, bytes=scan_bytes,
+                                    frac=scan_bytes / (call_ms * 1e-3) / 1e9 / HBM_PEAK_GBS),
+                    mean_U_m=float(u_m.mean()), mean_C_m=float(c_m.mean()), mean_U_s=float(u_s.mean()))
+    log(f"roofline: {roofline}")
+
+    # ---- batched form on the same scans
+    batched = None
+    if not args.no_batched:
+        bg, bdt, bst, bprof, (caps, reps) = run_batched(db, torch, gdef, ks, dev, args.warmup, args.steps, tuning,
+                                                          args.batch_scans)
+        bupd = sum(s.as_dict()["voxel_updates"] for s in bst)
+        batched = dict(value=bupd / bdt, unit="voxel-updates/s", scans_per_s=args.steps / bdt,
+                       scans_per_launch=args.batch_scans, ms_per_scan=bdt * 1e3 / args.steps,
+                       graph_captures=caps, graph_replays=reps, speedup_vs_plain=(bupd / bdt) / value)
+        bg.close()
+        log(f"batched: {batched}")
+        torch.cuda.empty_cache()
+
+    lat = plain_latency(db, torch, gdef, ks, dev, args.latency_scans, tuning) if args.latency_scans else []
+    latency = dict(plain_p50_ms=pct(lat, 50), plain_p99_ms=pct(lat, 99),
+                   plain_definition="integrate_scan call to sync return, one scan at a time")
+    torch.cuda.empty_cache()
+
+    served = None
+    if not args.no_serve:
+        served = run_serve(db, torch, args.serve_seconds, args.serve_warmup, args.serve_rate, args.serve_robots,
+                           args.serve_scans_per_robot)
+        latency.update(served_p50_ms=served["p50_ms"], served_p99_ms=served["p99_ms"],
+                       served_definition="scheduled arrival to observed completion, Poisson arrivals")
+        log(f"served: {served}")
+
+    cpu = None if args.no_cpu else cpu_baseline(gdef, scans[: min(len(scans), 80)])
+
+    mean_pts = float(np.mean([int(p.shape[0]) for _, p in dev]))
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "voxel-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": synth.CONFIGS[cfg]["name"], "grid": list(gdef["dims"]),
+                   "voxel_size_m": round(gdef["voxel_size"], 6), "mean_points_per_scan": mean_pts,
+                   "kernel": "K=11 (11^3), cube26 bins, r_s^2=9, T=5, H_max=65535, first-return dedup",
+                   "form": "plain: one scan per launch sequence, points resident in HBM",
+                   "tuning": tuning},
+        "scans_per_s": args.steps / dt,
+        "mean_integrated_per_scan": float(np.mean([s["n_integrated"] for s in sd])),
+        "batched": batched,
+        "latency_ms": latency,
+        "served": served,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernel_source_hash": kernel_source_hash(),
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

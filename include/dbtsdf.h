@@ -1,0 +1,401 @@
+/*
+ * dbtsdf.h - C ABI of an MI355X (gfx950) implementation of DB-TSDF scan
+ * integration: "DB-TSDF: Directional Bitmask-based Truncated Signed Distance
+ * Fields for Efficient Volumetric Mapping" (Maese, Merino, Caballero,
+ * arXiv 2509.20081).
+ *
+ * The library keeps dense voxel grids in GPU memory and fuses LiDAR scans
+ * into them (Sec. III-C): every return is transformed into the map frame with
+ * the scan pose, discarded if its K^3 neighbourhood would leave the map,
+ * assigned a direction bin (Sec. III-B, eq. 2), and its kernel is applied:
+ * a bitwise AND of the eq. 3 distance masks over the K^3 neighbourhood
+ * (eq. 4) and, inside the bin's hemispherical shadow, a saturating hit
+ * counter (eq. 5) whose threshold crossing clears the sign bit (eq. 6).
+ * Within one scan only the first return per voxel is integrated (Sec. IV-B).
+ *
+ * Data layout (Sec. III-A, eq. 1: 8 bytes per voxel). A grid is two planes of
+ * Nx*Ny*Nz uint32 words, x fastest (linear index x + Nx*(y + Ny*z)):
+ *   mask   - the 32-bit distance mask; its popcount is the truncated distance
+ *            in voxels; always of the form 2^n - 1 (all ones = never touched);
+ *   packed - hit counter h in bits 0-15, bits 16-30 zero, sign in bit 31
+ *            (1 = free, 0 = occupied).
+ * Initial state: mask 0xFFFFFFFF, packed 0x80000000 (Sec. III-A).
+ *
+ * Conventions shared by every entry point:
+ *   - No call throws; every failure is a dbtsdf_status.
+ *   - Arguments are validated before anything is enqueued; on error the grid
+ *     is unchanged.
+ *   - Device work is enqueued on the grid's HIP stream and is asynchronous;
+ *     results (grid contents, statistics) are valid after dbtsdf_sync().
+ *   - A grid must not be used from two threads at once; different grids may.
+ *   - Host pointers are only read during the call unless stated otherwise.
+ */
+#ifndef DBTSDF_H
+#define DBTSDF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DBTSDF_OK = 0,
+    DBTSDF_ERR_INVALID_ARG = 1,   /* a parameter or pointer failed validation */
+    DBTSDF_ERR_OUT_OF_MEMORY = 2, /* device or host allocation failed, or a memory budget refused it */
+    DBTSDF_ERR_DEVICE = 3,        /* a HIP call failed; the grid is poisoned */
+    DBTSDF_ERR_OUT_OF_RANGE = 4,  /* a read box or size exceeds the grid / a fixed limit */
+    DBTSDF_ERR_POISONED = 5,      /* the grid saw a device error earlier and refuses work */
+    DBTSDF_ERR_BUSY = 6           /* a server queue is full (try again later) */
+} dbtsdf_status;
+
+/* Direction binning (Sec. III-B). */
+typedef enum {
+    DBTSDF_BIN_AZEL = 0,   /* eq. 2: bins_az x bins_el azimuth/elevation bins (paper: 40 x 40) */
+    DBTSDF_BIN_CUBE26 = 1  /* 26 lattice directions: 8 azimuths x 3 elevations + 2 poles */
+} dbtsdf_binning;
+
+/* Distance measured by the eq. 3 mask. */
+typedef enum {
+    DBTSDF_DIST_L2 = 0,    /* eq. 3: n = ceil(sqrt(x^2 + y^2 + z^2)) (default) */
+    DBTSDF_DIST_L1 = 1     /* the L1 distance named in Sec. III-A: n = |x| + |y| + |z| */
+} dbtsdf_metric;
+
+/*
+ * Kernel-set parameters (Sec. III-B).
+ *   kernel_size  K, odd, 3..37 (paper: 21). With DBTSDF_DIST_L1, K <= 21 so
+ *                that every mask fits 32 bits.
+ *   binning      dbtsdf_binning.
+ *   bins_az/el   AZEL only: bins_az even and >= 2, bins_el >= 1, product <= 65536.
+ *   shadow_r2    r_s^2 in voxel^2: the shadow is {o : o.o <= r_s^2, o.u_b >= 0}
+ *                (contact voxel and planar face included); negative = no shadow
+ *                (the unsigned D-LIO distance field).
+ *   metric       dbtsdf_metric.
+ */
+typedef struct {
+    uint32_t kernel_size;
+    uint32_t binning;
+    uint32_t bins_az;
+    uint32_t bins_el;
+    int32_t shadow_r2;
+    uint32_t metric;
+} dbtsdf_kernel_params;
+
+/* Grid flags. */
+#define DBTSDF_DEDUP_FIRST 0x1u    /* integrate only the first return per voxel in a scan (Sec. IV-B) */
+#define DBTSDF_COUNT_TRAFFIC 0x2u  /* also count unique/changed mask words and unique shadow words */
+
+/*
+ * Grid parameters (Sec. III-A).
+ *   dims           Nx, Ny, Nz; each >= K and <= 2^20; Nx*Ny*Nz*8 bytes of HBM (eq. 1).
+ *   voxel_size     metres, finite and > 0.
+ *   origin         map-frame coordinate of the min corner of voxel (0,0,0), finite.
+ *   hit_threshold  T of eq. 6, 0..65535 (T = 0 or T > hit_max: the sign never flips).
+ *   hit_max        H_max of eq. 5, 1..65535 (the paper's 8-bit counter: 255).
+ *   flags          DBTSDF_DEDUP_FIRST | DBTSDF_COUNT_TRAFFIC.
+ */
+typedef struct {
+    uint32_t dims[3];
+    float voxel_size;
+    float origin[3];
+    uint32_t hit_threshold;
+    uint32_t hit_max;
+    uint32_t flags;
+} dbtsdf_grid_params;
+
+/*
+ * Per-scan statistics. voxel_updates = n_integrated * K^3 (one eq. 4 AND per
+ * kernel cell); shadow_updates = sum over integrated returns of |S(b)|.
+ * u_mask / c_mask / u_shadow are only filled with DBTSDF_COUNT_TRAFFIC: the
+ * number of distinct mask words in the union of the integrated neighbourhoods,
+ * of those whose value changed, and of distinct words in the union of the
+ * shadows. In a batch call they are per grid and reported on the first scan of
+ * that grid in the batch (zero on the others).
+ */
+typedef struct {
+    uint64_t n_in;
+    uint64_t n_invalid;       /* non-finite coordinates, or zero ray vector */
+    uint64_t n_out_of_bounds; /* K^3 neighbourhood would leave the grid */
+    uint64_t n_duplicate;     /* not first in its voxel within the scan */
+    uint64_t n_integrated;
+    uint64_t voxel_updates;
+    uint64_t shadow_updates;
+    uint64_t u_mask;
+    uint64_t c_mask;
+    uint64_t u_shadow;
+} dbtsdf_scan_stats;
+
+/* How conflicting updates to one voxel are resolved. Results are identical. */
+typedef enum {
+    DBTSDF_STRATEGY_AUTO = 0,   /* the tuned choice for this grid */
+    DBTSDF_STRATEGY_BRICK = 1,  /* returns bucketed by grid brick; one workgroup owns a brick in LDS */
+    DBTSDF_STRATEGY_ATOMIC = 2  /* one wavefront per return; 32-bit global atomics */
+} dbtsdf_strategy;
+
+/*
+ * Launch tuning of a grid. With DBTSDF_STRATEGY_BRICK, (brick, block_threads)
+ * must be one of the compiled shapes: 32x16x8 (256 or 512 threads),
+ * 32x16x16 (256, 512), 32x32x16 (512), 64x16x8 (256, 512), 32x8x8 (256),
+ * 16x16x16 (256), 16x16x8 (256); any kernel size works with any shape.
+ * apply_blocks = workgroups of the persistent apply kernel (0 = automatic).
+ * With DBTSDF_STRATEGY_ATOMIC the brick is ignored. Any valid tuning gives
+ * bit-identical grids.
+ */
+typedef struct {
+    uint32_t strategy;
+    uint32_t brick[3];
+    uint32_t block_threads;
+    uint32_t apply_blocks;
+} dbtsdf_tuning;
+
+typedef struct dbtsdf_kernel_set dbtsdf_kernel_set;
+typedef struct dbtsdf_grid dbtsdf_grid;
+typedef struct dbtsdf_batch dbtsdf_batch;
+typedef struct dbtsdf_server dbtsdf_server;
+
+/* Human-readable name of a status code (static storage). */
+const char *dbtsdf_status_string(dbtsdf_status s);
+
+/* Last error message recorded on the calling thread (static per thread; "" if none). */
+const char *dbtsdf_last_error(void);
+
+/* ---------------------------------------------------------------- kernel sets
+ * Precomputed per-bin kernels (Sec. III-B): the eq. 3 mask of every kernel
+ * cell, the shadow of every bin and the bin-centre unit vectors. Host-side.
+ * *out is owned by the caller and released with dbtsdf_kernel_set_destroy.
+ * Errors: INVALID_ARG (parameters, NULL), OUT_OF_MEMORY.
+ */
+dbtsdf_status dbtsdf_kernel_set_create(const dbtsdf_kernel_params *params, dbtsdf_kernel_set **out);
+
+/*
+ * Copy the tables out. masks: K^3 uint32 (index ((dz+R)*K + (dy+R))*K + (dx+R),
+ * R = (K-1)/2); shadow: n_bins*K^3 bytes (1 = in the shadow, same cell order);
+ * dirs: n_bins*3 doubles (bin-centre unit vectors; for AZEL, bin b has
+ * azimuth index b % bins_az and elevation index b / bins_az, azimuth from +x
+ * counter-clockwise, elevation from the nadir). Any output may be NULL.
+ * *n_bins receives the bin count (may be NULL).
+ */
+dbtsdf_status dbtsdf_kernel_set_export(const dbtsdf_kernel_set *ks, uint32_t *masks, uint8_t *shadow,
+                                       double *dirs, uint32_t *n_bins);
+
+/* Number of bins (26 or bins_az*bins_el); 0 for NULL. */
+uint32_t dbtsdf_kernel_set_n_bins(const dbtsdf_kernel_set *ks);
+
+/* Direction bin of one ray vector d (map axes), as the device computes it; -1 on NULL. */
+int32_t dbtsdf_kernel_set_bin(const dbtsdf_kernel_set *ks, float dx, float dy, float dz);
+
+void dbtsdf_kernel_set_destroy(dbtsdf_kernel_set *ks);
+
+/* --------------------------------------------------------------------- grids */
+
+/* eq. 1: bytes of voxel storage = Nx*Ny*Nz*8; 0 if params is NULL. */
+uint64_t dbtsdf_grid_bytes(const dbtsdf_grid_params *params);
+
+/*
+ * Allocate a grid on the current HIP device and fill the initial state
+ * (Sec. III-A). The grid copies the kernel tables (the kernel set may be
+ * destroyed afterwards). hip_stream is a hipStream_t (NULL = default stream)
+ * that all work on this grid is enqueued on. The grid owns its planes.
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE.
+ */
+dbtsdf_status dbtsdf_create_grid(const dbtsdf_grid_params *params, const dbtsdf_kernel_set *ks,
+                                 void *hip_stream, dbtsdf_grid **out);
+
+/*
+ * As dbtsdf_create_grid, on caller-owned device planes (each Nx*Ny*Nz uint32,
+ * 16-byte aligned, e.g. torch tensors). The planes are filled with the initial
+ * state; they must outlive the grid and are not freed by it.
+ */
+dbtsdf_status dbtsdf_create_grid_on(const dbtsdf_grid_params *params, const dbtsdf_kernel_set *ks,
+                                    void *hip_stream, void *mask_dev, void *packed_dev,
+                                    dbtsdf_grid **out);
+
+/* Device pointers of the two planes (for zero-copy views). */
+dbtsdf_status dbtsdf_grid_planes(const dbtsdf_grid *g, void **mask_dev, void **packed_dev);
+
+/* Refill the initial state (Sec. III-A) on the grid's stream. */
+dbtsdf_status dbtsdf_reset_grid(dbtsdf_grid *g);
+
+/* Read / set the launch tuning of a grid (see dbtsdf_tuning). */
+dbtsdf_status dbtsdf_get_tuning(const dbtsdf_grid *g, dbtsdf_tuning *out);
+dbtsdf_status dbtsdf_set_tuning(dbtsdf_grid *g, const dbtsdf_tuning *t);
+
+/*
+ * Fuse one scan (Sec. III-C, eqs. 2-6, Sec. IV-B dedup).
+ *   pose     16 floats, row-major 4x4 sensor->map transform (host memory; the
+ *            bottom row is ignored); must be finite.
+ *   points   n x 3 fp32 (x, y, z) in the sensor frame. points_on_device = 0:
+ *            host memory, copied to device staging before the call returns.
+ *            points_on_device = 1: device memory that must stay valid and
+ *            unmodified until dbtsdf_sync().
+ *   n        number of points; 0 is a no-op. At most 2^28 per call.
+ *   stats    NULL, or host memory that receives the statistics at the next
+ *            dbtsdf_sync() (it must stay valid until then).
+ * Non-finite and zero-range points are not errors: they are counted.
+ * Front end arithmetic is fp32, one IEEE operation per step, no contraction.
+ * Errors: INVALID_ARG, OUT_OF_RANGE (n too large), OUT_OF_MEMORY, DEVICE, POISONED.
+ */
+dbtsdf_status dbtsdf_integrate_scan(dbtsdf_grid *g, const float pose[16], const float *points, uint64_t n,
+                                    int points_on_device, dbtsdf_scan_stats *stats);
+
+/*
+ * Wait for all work on the grid's stream, deliver pending statistics.
+ * Errors: DEVICE (the grid becomes poisoned), POISONED.
+ */
+dbtsdf_status dbtsdf_sync(dbtsdf_grid *g);
+
+/*
+ * Copy the box [lo, hi) (voxel indices, lo < hi <= dims) to host memory, x
+ * fastest: mask_out and packed_out hold (hi-lo) products of uint32 each (either
+ * may be NULL). Synchronous. Errors: INVALID_ARG, OUT_OF_RANGE, DEVICE, POISONED.
+ */
+dbtsdf_status dbtsdf_read_voxels(dbtsdf_grid *g, const uint32_t lo[3], const uint32_t hi[3],
+                                 uint32_t *mask_out, uint32_t *packed_out);
+
+/*
+ * Signed truncated distance of the box [lo, hi), x fastest, host int8:
+ * (sign ? +1 : -1) * popcount(mask) (Sec. III-A); untouched voxels read +32.
+ * Synchronous. Errors as dbtsdf_read_voxels.
+ */
+dbtsdf_status dbtsdf_read_distance(dbtsdf_grid *g, const uint32_t lo[3], const uint32_t hi[3], int8_t *dist_out);
+
+/*
+ * Overwrite the whole grid from host planes (Nx*Ny*Nz uint32 each, x fastest),
+ * e.g. a checkpoint written from dbtsdf_read_voxels. Rejects (INVALID_ARG)
+ * planes that break the representation: a mask not of the form 2^n - 1, bits
+ * 16-30 of packed set, a counter above hit_max, or a sign that disagrees with
+ * the counter (sign 0 iff 1 <= T <= hit_max and h >= T). Synchronous.
+ */
+dbtsdf_status dbtsdf_write_voxels(dbtsdf_grid *g, const uint32_t *mask_in, const uint32_t *packed_in);
+
+void dbtsdf_destroy_grid(dbtsdf_grid *g);
+
+/* ---------------------------------------------------------------- profiling
+ * Device-side timing with HIP events on the work's own stream. When enabled,
+ * each integrate call records events at its start, just before the apply
+ * kernel (the per-brick eq. 4-6 merge, the dominant kernel) and at its end;
+ * read_profile synchronises the stream and returns the accumulated
+ * milliseconds and counts since profiling was (re)enabled. Graph-replayed
+ * batch calls report the whole call only (applies stays 0). Any output may be
+ * NULL. Enabling resets the totals.
+ */
+dbtsdf_status dbtsdf_set_profiling(dbtsdf_grid *g, int enable);
+dbtsdf_status dbtsdf_read_profile(dbtsdf_grid *g, double *call_ms, uint64_t *calls, double *apply_ms,
+                                  uint64_t *applies);
+
+/* ----------------------------------------------------------------- batching
+ * Many scans of many grids fused by one launch sequence: one front-end pass
+ * over all points, then one persistent apply kernel over every (grid, brick)
+ * work item, optionally replayed from a captured HIP graph. Results are
+ * identical to integrating the scans one by one in any order (the updates of
+ * eqs. 4-6 commute; dedup stays per scan).
+ *
+ * A batch context owns a HIP stream-ordered workspace and a graph cache. All
+ * grids of one call must live on the device the context was created on; the
+ * context's stream is hip_stream (NULL = default stream), which must not be
+ * used concurrently by another context.
+ */
+dbtsdf_status dbtsdf_batch_create(void *hip_stream, int use_graph, dbtsdf_batch **out);
+
+/*
+ * Enqueue n_scans scans: scan i goes into grids[i] with pose poses[16*i..],
+ * points[i] (n[i] x 3 fp32, device memory when points_on_device, else host
+ * memory copied before return), statistics into stats[i] at dbtsdf_batch_sync
+ * (stats may be NULL). The same grid may appear several times. Points on the
+ * device must stay valid until dbtsdf_batch_sync(). Total points <= 2^28.
+ */
+dbtsdf_status dbtsdf_batch_integrate(dbtsdf_batch *b, uint32_t n_scans, dbtsdf_grid *const *grids,
+                                     const float *poses, const float *const *points, const uint64_t *n,
+                                     int points_on_device, dbtsdf_scan_stats *stats);
+
+/* Wait for the batch context's stream and deliver statistics. */
+dbtsdf_status dbtsdf_batch_sync(dbtsdf_batch *b);
+
+/* Number of graph captures and graph replays so far (either may be NULL). */
+dbtsdf_status dbtsdf_batch_graph_stats(const dbtsdf_batch *b, uint64_t *captures, uint64_t *replays);
+
+/* Profiling of a batch context (see dbtsdf_set_profiling). */
+dbtsdf_status dbtsdf_batch_set_profiling(dbtsdf_batch *b, int enable);
+dbtsdf_status dbtsdf_batch_read_profile(dbtsdf_batch *b, double *call_ms, uint64_t *calls, double *apply_ms,
+                                        uint64_t *applies);
+
+void dbtsdf_batch_destroy(dbtsdf_batch *b);
+
+/* ------------------------------------------------------------------ tuning
+ * Time each candidate tuning on the grid with the given scans (device points),
+ * on a scratch copy of the grid (the grid itself is not changed), keep the
+ * fastest, and return it in *best (may be NULL). Every candidate is checked to
+ * give a bit-identical scratch grid; a mismatch returns DEVICE.
+ */
+dbtsdf_status dbtsdf_autotune(dbtsdf_grid *g, uint32_t n_scans, const float *poses,
+                              const float *const *points_dev, const uint64_t *n, dbtsdf_tuning *best);
+
+/* ----------------------------------------------------------------- serving
+ * A request loop that keeps many grids resident in HBM and fuses scans as they
+ * arrive (continuous batching): a scheduler thread takes every ready scan up
+ * to the batch limits, integrates them with one batched launch on one of
+ * n_streams streams while earlier batches are still running, and stamps each
+ * scan's completion when its batch's event fires. Scans of one map are never
+ * in flight twice at once, so per-map order is kept (results do not depend on
+ * it anyway). New maps are admitted only while their eq. 1 bytes fit in the
+ * memory budget.
+ */
+typedef struct {
+    uint32_t n_streams;          /* >= 1 concurrent batches (default 2) */
+    uint32_t max_batch_scans;    /* scans per batch (default 64) */
+    uint64_t max_batch_points;   /* points per batch (default 4M) */
+    uint64_t memory_budget;      /* bytes of grid storage admitted; 0 = free device memory minus 8 GiB */
+    uint32_t queue_capacity;     /* pending scans before submit returns BUSY (default 4096) */
+    uint32_t use_graph;          /* replay batches from captured graphs */
+} dbtsdf_server_config;
+
+typedef struct {
+    uint64_t ticket;         /* from dbtsdf_server_submit */
+    uint32_t map_id;
+    uint32_t status;         /* dbtsdf_status of the scan */
+    uint64_t t_arrival_ns;   /* as given at submit */
+    uint64_t t_launch_ns;    /* host clock when its batch was enqueued */
+    uint64_t t_done_ns;      /* host clock when its batch's completion was observed */
+    uint32_t batch_scans;    /* scans in the batch it rode in */
+    dbtsdf_scan_stats stats;
+} dbtsdf_completion;
+
+dbtsdf_status dbtsdf_server_create(const dbtsdf_server_config *cfg, dbtsdf_server **out);
+
+/* Admit a map (allocates its grid). OUT_OF_MEMORY when the budget is exceeded. */
+dbtsdf_status dbtsdf_server_add_map(dbtsdf_server *s, const dbtsdf_grid_params *params,
+                                    const dbtsdf_kernel_set *ks, uint32_t *map_id);
+
+/* Release a map's grid (waits for its in-flight work). */
+dbtsdf_status dbtsdf_server_remove_map(dbtsdf_server *s, uint32_t map_id);
+
+/* The grid of an admitted map (owned by the server), e.g. for readout after drain. */
+dbtsdf_status dbtsdf_server_map_grid(dbtsdf_server *s, uint32_t map_id, dbtsdf_grid **g);
+
+/*
+ * Queue one scan (host points, copied into pinned staging before return).
+ * t_arrival_ns is the caller's arrival stamp on the CLOCK_MONOTONIC clock
+ * (dbtsdf_now_ns). BUSY when the queue is full.
+ */
+dbtsdf_status dbtsdf_server_submit(dbtsdf_server *s, uint32_t map_id, const float pose[16], const float *points,
+                                   uint64_t n, uint64_t t_arrival_ns, uint64_t *ticket);
+
+/* Move up to max finished scans into out; *n_out receives the count. Non-blocking. */
+dbtsdf_status dbtsdf_server_poll(dbtsdf_server *s, dbtsdf_completion *out, uint32_t max, uint32_t *n_out);
+
+/* Block until every submitted scan has completed (completions stay pollable). */
+dbtsdf_status dbtsdf_server_drain(dbtsdf_server *s);
+
+/* Admitted bytes and the budget (either may be NULL). */
+dbtsdf_status dbtsdf_server_memory(const dbtsdf_server *s, uint64_t *admitted, uint64_t *budget);
+
+void dbtsdf_server_destroy(dbtsdf_server *s);
+
+/* CLOCK_MONOTONIC in nanoseconds (the server's clock). */
+uint64_t dbtsdf_now_ns(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DBTSDF_H */

@@ -1,0 +1,343 @@
+"""DB-TSDF scan integration on MI355X (gfx950): Python binding of ``libdbtsdf.so``.
+
+Thin marshalling over the C ABI declared in ``include/dbtsdf.h``; every step of
+the integration runs in the library's HIP kernels. PyTorch is used only for
+device memory (point clouds, optional grid planes) and for the stream handle.
+If the library has not been built, every entry point raises: there is no CPU
+fallback.
+
+Example::
+
+    import paper_2509_20081_amd as db
+    ks = db.KernelSet(kernel_size=11, binning="cube26", shadow_r2=9)
+    g = db.Grid((1024, 1024, 256), 0.05, origin, ks)
+    st = g.integrate(pose_4x4, points_cuda_Nx3)   # async
+    g.sync(); print(st.as_dict())
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+from ._lib import DbtsdfError  # noqa: F401
+
+__all__ = ["KernelSet", "Grid", "Batch", "Server", "DbtsdfError", "now_ns", "library_path"]
+
+_BINNING = {"azel": L.BIN_AZEL, "cube26": L.BIN_CUBE26}
+_METRIC = {"l2": L.DIST_L2, "l1": L.DIST_L1}
+_STRATEGY = {"auto": L.STRATEGY_AUTO, "brick": L.STRATEGY_BRICK, "atomic": L.STRATEGY_ATOMIC}
+_STRATEGY_NAME = {v: k for k, v in _STRATEGY.items()}
+
+
+def library_path() -> str:
+    return L.LIB_PATH
+
+
+def now_ns() -> int:
+    return int(L.lib().dbtsdf_now_ns())
+
+
+def _f32(a, shape=None) -> np.ndarray:
+    out = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    if shape is not None:
+        out = out.reshape(shape)
+    return out
+
+
+def _current_stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _points_arg(points):
+    """(pointer, n, on_device, keepalive) for a torch CUDA tensor or host array of N x 3 fp32."""
+    try:
+        import torch
+    except ImportError:  # pragma: no cover
+        torch = None
+    if torch is not None and isinstance(points, torch.Tensor):
+        if points.dtype != torch.float32 or points.dim() != 2 or points.shape[1] != 3:
+            raise ValueError("points must be an (N, 3) float32 tensor")
+        if not points.is_contiguous():
+            points = points.contiguous()
+        if points.is_cuda:
+            return C.c_void_p(points.data_ptr()), int(points.shape[0]), 1, points
+        points = points.numpy()
+    arr = _f32(points)
+    if arr.ndim != 2 or arr.shape[1] != 3:
+        raise ValueError("points must be (N, 3)")
+    return arr.ctypes.data_as(C.c_void_p), int(arr.shape[0]), 0, arr
+
+
+def _read_profile(fn, h) -> dict:
+    cm, am = C.c_double(), C.c_double()
+    cn, an = C.c_uint64(), C.c_uint64()
+    L.check(fn(h, C.byref(cm), C.byref(cn), C.byref(am), C.byref(an)), "read_profile")
+    return dict(call_ms=cm.value, calls=int(cn.value), apply_ms=am.value, applies=int(an.value))
+
+
+class Stats:
+    """Statistics of one scan; filled when the owning grid / batch is synchronised."""
+
+    def __init__(self):
+        self._c = L.ScanStats()
+
+    def as_dict(self) -> dict:
+        return self._c.as_dict()
+
+    def __getattr__(self, name):
+        if name in L.STAT_FIELDS:
+            return int(getattr(self._c, name))
+        raise AttributeError(name)
+
+    def __repr__(self):
+        return f"Stats({self.as_dict()})"
+
+
+class KernelSet:
+    """Directional kernels (Sec. III-B): eq. 3 masks, per-bin hemispherical shadows."""
+
+    def __init__(self, kernel_size: int = 11, binning: str = "cube26", bins_az: int = 40, bins_el: int = 40,
+                 shadow_r2: int = 9, metric: str = "l2"):
+        p = L.KernelParams(kernel_size, _BINNING[binning], bins_az, bins_el, shadow_r2, _METRIC[metric])
+        h = C.c_void_p()
+        L.check(L.lib().dbtsdf_kernel_set_create(C.byref(p), C.byref(h)), "kernel_set_create")
+        self._h = h
+        self.kernel_size = kernel_size
+        self.binning = binning
+        self.n_bins = int(L.lib().dbtsdf_kernel_set_n_bins(h))
+
+    def export(self):
+        """(masks[K,K,K] uint32 [dz,dy,dx], shadow[n_bins,K,K,K] uint8, dirs[n_bins,3] float64)."""
+        K = self.kernel_size
+        masks = np.zeros((K, K, K), np.uint32)
+        shadow = np.zeros((self.n_bins, K, K, K), np.uint8)
+        dirs = np.zeros((self.n_bins, 3), np.float64)
+        nb = C.c_uint32()
+        L.check(L.lib().dbtsdf_kernel_set_export(self._h, masks.ctypes.data_as(C.c_void_p),
+                                                 shadow.ctypes.data_as(C.c_void_p),
+                                                 dirs.ctypes.data_as(C.c_void_p), C.byref(nb)), "kernel_set_export")
+        return masks, shadow, dirs
+
+    def bin(self, d) -> int:
+        d = _f32(d, (3,))
+        return int(L.lib().dbtsdf_kernel_set_bin(self._h, C.c_float(d[0]), C.c_float(d[1]), C.c_float(d[2])))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and L._lib is not None:
+            L._lib.dbtsdf_kernel_set_destroy(h)
+            self._h = None
+
+
+def grid_params(dims, voxel_size, origin=(0.0, 0.0, 0.0), hit_threshold=5, hit_max=65535, dedup=True,
+                count_traffic=False) -> L.GridParams:
+    p = L.GridParams()
+    p.dims[:] = [int(d) for d in dims]
+    p.voxel_size = float(voxel_size)
+    p.origin[:] = [float(o) for o in origin]
+    p.hit_threshold = hit_threshold
+    p.hit_max = hit_max
+    p.flags = (L.DEDUP_FIRST if dedup else 0) | (L.COUNT_TRAFFIC if count_traffic else 0)
+    return p
+
+
+def grid_bytes(dims) -> int:
+    p = grid_params(dims, 1.0)
+    return int(L.lib().dbtsdf_grid_bytes(C.byref(p)))
+
+
+class Grid:
+    """A dense DB-TSDF voxel grid resident in GPU memory (Sec. III-A).
+
+    ``planes="torch"`` puts the two planes in torch-owned int32 tensors of shape
+    (Nz, Ny, Nx) (``mask_tensor``, ``packed_tensor``; reinterpret as uint32);
+    otherwise the library owns them. ``stream`` is a raw hipStream_t value; by
+    default torch's current stream.
+    """
+
+    def __init__(self, dims, voxel_size, origin, kernel_set: KernelSet, hit_threshold=5, hit_max=65535,
+                 dedup=True, count_traffic=False, planes=None, stream=None, _handle=None):
+        self.dims = tuple(int(d) for d in dims)
+        self.kernel_set = kernel_set
+        self.params = grid_params(dims, voxel_size, origin, hit_threshold, hit_max, dedup, count_traffic)
+        self._keep = []
+        self._pending = []
+        self.mask_tensor = self.packed_tensor = None
+        self._owned = _handle is None
+        if _handle is not None:
+            self._h = _handle
+            return
+        h = C.c_void_p()
+        st = _current_stream() if stream is None else C.c_void_p(stream)
+        if planes == "torch":
+            import torch
+            nx, ny, nz = self.dims
+            self.mask_tensor = torch.empty((nz, ny, nx), dtype=torch.int32, device="cuda")
+            self.packed_tensor = torch.empty((nz, ny, nx), dtype=torch.int32, device="cuda")
+            rc = L.lib().dbtsdf_create_grid_on(C.byref(self.params), kernel_set._h, st,
+                                               C.c_void_p(self.mask_tensor.data_ptr()),
+                                               C.c_void_p(self.packed_tensor.data_ptr()), C.byref(h))
+        else:
+            rc = L.lib().dbtsdf_create_grid(C.byref(self.params), kernel_set._h, st, C.byref(h))
+        L.check(rc, "create_grid")
+        self._h = h
+
+    # -- integration --------------------------------------------------------
+    def integrate(self, pose, points) -> Stats:
+        """Enqueue one scan; the returned Stats are filled at the next sync()."""
+        pose = _f32(pose, (16,))
+        ptr, n, on_dev, keep = _points_arg(points)
+        st = Stats()
+        rc = L.lib().dbtsdf_integrate_scan(self._h, pose.ctypes.data_as(C.c_void_p), ptr, n, on_dev,
+                                           C.byref(st._c))
+        L.check(rc, "integrate_scan")
+        self._pending.append((st, keep if on_dev else None))
+        return st
+
+    def sync(self) -> None:
+        L.check(L.lib().dbtsdf_sync(self._h), "sync")
+        self._pending.clear()
+
+    def reset(self) -> None:
+        L.check(L.lib().dbtsdf_reset_grid(self._h), "reset_grid")
+
+    # -- device timing ----------------------------------------------------------
+    def set_profiling(self, enable=True) -> None:
+        L.check(L.lib().dbtsdf_set_profiling(self._h, 1 if enable else 0), "set_profiling")
+
+    def read_profile(self) -> dict:
+        return _read_profile(L.lib().dbtsdf_read_profile, self._h)
+
+    # -- tuning -----------------------------------------------------------------
+    @property
+    def tuning(self) -> dict:
+        t = L.Tuning()
+        L.check(L.lib().dbtsdf_get_tuning(self._h, C.byref(t)), "get_tuning")
+        return dict(strategy=_STRATEGY_NAME[t.strategy], brick=tuple(t.brick), block_threads=t.block_threads,
+                    apply_blocks=t.apply_blocks)
+
+    def set_tuning(self, strategy="brick", brick=(32, 16, 8), block_threads=256, apply_blocks=0) -> None:
+        t = L.Tuning(_STRATEGY[strategy], (C.c_uint32 * 3)(*brick), block_threads, apply_blocks)
+        L.check(L.lib().dbtsdf_set_tuning(self._h, C.byref(t)), "set_tuning")
+
+    def autotune(self, scans, device_points) -> dict:
+        """Time candidate tunings on a scratch copy with ``scans`` [(pose, cuda points)], keep the fastest."""
+        n = len(scans)
+        poses = np.stack([_f32(p, (16,)) for p, _ in scans]).astype(np.float32)
+        ptrs = (C.c_void_p * n)(*[C.c_void_p(pts.data_ptr()) for _, pts in scans])
+        counts = (C.c_uint64 * n)(*[int(pts.shape[0]) for _, pts in scans])
+        best = L.Tuning()
+        L.check(L.lib().dbtsdf_autotune(self._h, n, poses.ctypes.data_as(C.c_void_p), ptrs, counts,
+                                        C.byref(best)), "autotune")
+        return self.tuning
+
+    # -- readout ----------------------------------------------------------------
+    def _box(self, lo, hi):
+        lo = (0, 0, 0) if lo is None else lo
+        hi = self.dims if hi is None else hi
+        lo_a = (C.c_uint32 * 3)(*[int(v) for v in lo])
+        hi_a = (C.c_uint32 * 3)(*[int(v) for v in hi])
+        shape = (int(hi[2]) - int(lo[2]), int(hi[1]) - int(lo[1]), int(hi[0]) - int(lo[0]))
+        return lo_a, hi_a, shape
+
+    def read_voxels(self, lo=None, hi=None):
+        """(mask, packed) uint32 arrays of shape (z, y, x) for the box [lo, hi)."""
+        lo_a, hi_a, shape = self._box(lo, hi)
+        mask = np.empty(shape, np.uint32)
+        packed = np.empty(shape, np.uint32)
+        L.check(L.lib().dbtsdf_read_voxels(self._h, lo_a, hi_a, mask.ctypes.data_as(C.c_void_p),
+                                           packed.ctypes.data_as(C.c_void_p)), "read_voxels")
+        return mask, packed
+
+    def read_distance(self, lo=None, hi=None):
+        lo_a, hi_a, shape = self._box(lo, hi)
+        out = np.empty(shape, np.int8)
+        L.check(L.lib().dbtsdf_read_distance(self._h, lo_a, hi_a, out.ctypes.data_as(C.c_void_p)),
+                "read_distance")
+        return out
+
+    def write_voxels(self, mask, packed) -> None:
+        m = np.ascontiguousarray(mask, dtype=np.uint32)
+        p = np.ascontiguousarray(packed, dtype=np.uint32)
+        L.check(L.lib().dbtsdf_write_voxels(self._h, m.ctypes.data_as(C.c_void_p), p.ctypes.data_as(C.c_void_p)),
+                "write_voxels")
+
+    def planes(self):
+        """Raw device pointers (mask, packed) of the planes."""
+        m, p = C.c_void_p(), C.c_void_p()
+        L.check(L.lib().dbtsdf_grid_planes(self._h, C.byref(m), C.byref(p)), "grid_planes")
+        return m.value, p.value
+
+    def close(self) -> None:
+        h = getattr(self, "_h", None)
+        if h and self._owned and L._lib is not None:
+            L._lib.dbtsdf_destroy_grid(h)
+        self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+class Batch:
+    """Batched integration: many scans of many grids per launch sequence, optionally graph-replayed."""
+
+    def __init__(self, stream=None, use_graph=True):
+        h = C.c_void_p()
+        st = C.c_void_p(stream) if stream is not None else C.c_void_p(None)
+        L.check(L.lib().dbtsdf_batch_create(st, 1 if use_graph else 0, C.byref(h)), "batch_create")
+        self._h = h
+        self._keep = []
+
+    def integrate(self, items) -> list:
+        """items: [(grid, pose, points)] with points all on the device or all on the host."""
+        n = len(items)
+        if n == 0:
+            return []
+        grids = (C.c_void_p * n)(*[g._h for g, _, _ in items])
+        poses = np.stack([_f32(p, (16,)) for _, p, _ in items]).astype(np.float32)
+        args = [_points_arg(pts) for _, _, pts in items]
+        on_dev = {a[2] for a in args}
+        if len(on_dev) != 1:
+            raise ValueError("batch points must be all on the device or all on the host")
+        ptrs = (C.c_void_p * n)(*[a[0] for a in args])
+        counts = (C.c_uint64 * n)(*[a[1] for a in args])
+        stats = (L.ScanStats * n)()
+        L.check(L.lib().dbtsdf_batch_integrate(self._h, n, grids, poses.ctypes.data_as(C.c_void_p), ptrs, counts,
+                                               on_dev.pop(), stats), "batch_integrate")
+        self._keep.append((stats, [a[3] for a in args]))
+        out = []
+        for i in range(n):
+            s = Stats()
+            s._c = stats[i]
+            out.append(s)
+        return out
+
+    def sync(self) -> None:
+        L.check(L.lib().dbtsdf_batch_sync(self._h), "batch_sync")
+        self._keep = self._keep[-4:]
+
+    def set_profiling(self, enable=True) -> None:
+        L.check(L.lib().dbtsdf_batch_set_profiling(self._h, 1 if enable else 0), "batch_set_profiling")
+
+    def read_profile(self) -> dict:
+        return _read_profile(L.lib().dbtsdf_batch_read_profile, self._h)
+
+    def graph_stats(self):
+        c, r = C.c_uint64(), C.c_uint64()
+        L.check(L.lib().dbtsdf_batch_graph_stats(self._h, C.byref(c), C.byref(r)), "batch_graph_stats")
+        return int(c.value), int(r.value)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h and L._lib is not None:
+            L._lib.dbtsdf_batch_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+from .serve import Server  # noqa: E402,F401

@@ -1,0 +1,72 @@
+"""Build ``libdbtsdf.so`` (HIP kernels + C ABI) for gfx950 with hipcc, in-tree.
+
+Front-end arithmetic must be one IEEE fp32 operation per step: the whole
+library is compiled with ``-ffp-contract=off`` and fp32 denormals kept.
+Packed-fp32 instructions are disabled.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libdbtsdf.so")
+SOURCES = ["api.cpp", "kernel_set.cpp", "server.cpp", "tune.cpp", "kernels.hip"]
+ARCH = os.environ.get("DBTSDF_OFFLOAD_ARCH", "gfx950")
+
+
+def hipcc() -> str:
+    for c in (os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc"), "hipcc"):
+        if os.path.sep not in c or os.path.exists(c):
+            return c
+    return "hipcc"
+
+
+def flags() -> list[str]:
+    return [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
+            "-ffp-contract=off", "-fno-gpu-flush-denormals-to-zero",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-I", os.path.join(os.path.dirname(HERE), "include")]
+
+
+def build(verbose: bool = False, jobs: int = 5) -> str:
+    objs = []
+    procs = []
+    for src in SOURCES:
+        path = os.path.join(CSRC, src)
+        if not os.path.exists(path):
+            continue
+        obj = os.path.join(CSRC, "_build", src + ".o")
+        os.makedirs(os.path.dirname(obj), exist_ok=True)
+        cmd = [hipcc(), *flags(), "-c", path, "-o", obj]
+        if src.endswith(".cpp"):
+            cmd[1:1] = ["-x", "hip"]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((src, subprocess.Popen(cmd)))
+        objs.append(obj)
+        if len(procs) >= jobs:
+            _wait(procs)
+    _wait(procs)
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", LIB + ".tmp", *objs]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+def _wait(procs):
+    failed = []
+    for src, p in procs:
+        if p.wait() != 0:
+            failed.append(src)
+    procs.clear()
+    if failed:
+        raise RuntimeError("hipcc failed for: " + ", ".join(failed))
+
+
+if __name__ == "__main__":
+    build(verbose="-v" in sys.argv)

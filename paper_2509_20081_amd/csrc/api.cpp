@@ -1,0 +1,936 @@
+// C ABI of the scan-integration library: validation, grids, workspaces,
+// statistics delivery, batching with captured HIP graphs, readout.
+#include <time.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <unordered_map>
+
+#include "runtime.h"
+
+using namespace dbtsdf;
+
+namespace dbtsdf {
+
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+
+dbtsdf_status check_hip(hipError_t e, const char *what, dbtsdf_grid *g) {
+    if (e == hipSuccess) return DBTSDF_OK;
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    (void)hipGetLastError();
+    if (e == hipErrorOutOfMemory) return DBTSDF_ERR_OUT_OF_MEMORY;
+    if (g) g->poisoned = true;
+    return DBTSDF_ERR_DEVICE;
+}
+
+static dbtsdf_status invalid(const std::string &msg) {
+    set_error(msg);
+    return DBTSDF_ERR_INVALID_ARG;
+}
+
+static uint32_t next_pow2(uint64_t v, uint32_t lo) {
+    uint64_t p = lo;
+    while (p < v) p <<= 1;
+    return (uint32_t)p;
+}
+
+// ------------------------------------------------------------- tables ---
+DeviceTables::~DeviceTables() {
+    for (void *p : allocs) (void)hipFree(p);
+}
+
+template <typename T>
+static hipError_t upload(DeviceTables &d, const std::vector<T> &v, const T **out) {
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, std::max<size_t>(1, v.size()) * sizeof(T));
+    if (e != hipSuccess) return e;
+    d.allocs.push_back(p);
+    if (!v.empty()) e = hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+    *out = (const T *)p;
+    return e;
+}
+
+static dbtsdf_status make_device_tables(const KernelSet &ks, std::unique_ptr<DeviceTables> &out) {
+    auto d = std::make_unique<DeviceTables>();
+    d->params = ks.p;
+    DevTables &t = d->t;
+    hipError_t e = upload(*d, ks.mask_by_q, &t.mask_by_q);
+    if (e == hipSuccess) e = upload(*d, ks.sh_start, &t.sh_start);
+    if (e == hipSuccess) e = upload(*d, ks.sh_off, &t.sh_off);
+    if (e == hipSuccess) e = upload(*d, ks.az_c, &t.az_c);
+    if (e == hipSuccess) e = upload(*d, ks.az_s, &t.az_s);
+    if (e == hipSuccess) e = upload(*d, ks.el_s2, &t.el_s2);
+    if (e == hipSuccess) e = upload(*d, ks.el_neg, &t.el_neg);
+    if (e != hipSuccess) return check_hip(e, "uploading kernel tables");
+    t.n_q = (uint32_t)ks.mask_by_q.size();
+    t.n_bins = ks.n_bins;
+    t.K = ks.K;
+    t.R = ks.R;
+    t.binning = ks.p.binning;
+    t.bins_az = ks.p.bins_az;
+    t.bins_el = ks.p.bins_el;
+    t.metric = ks.p.metric;
+    out = std::move(d);
+    return DBTSDF_OK;
+}
+
+// ---------------------------------------------------------- workspace ---
+Workspace::~Workspace() { release(); }
+
+void Workspace::drop_graphs() {
+    for (auto &kv : graphs)
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    graphs.clear();
+}
+
+void Workspace::release() {
+    drop_graphs();
+    void *ptrs[] = {d_desc, rec, pslot, hkeys, hvals, items, item_off, item_cur, entries, survivors, ctr, staging};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    d_desc = nullptr;
+    rec = nullptr;
+    pslot = nullptr;
+    hkeys = nullptr;
+    hvals = nullptr;
+    items = nullptr;
+    item_off = item_cur = entries = survivors = nullptr;
+    ctr = nullptr;
+    staging = nullptr;
+    staging_cap = 0;
+    points_cap = scans_cap = grids_cap = items_cap = entries_cap = hash_cap = 0;
+    for (RingSlot &s : ring) {
+        if (s.busy && s.ev) (void)hipEventSynchronize(s.ev);
+        deliver(s);
+        if (s.host) (void)hipHostFree(s.host);
+        if (s.ev) (void)hipEventDestroy(s.ev);
+        for (hipEvent_t &e : s.pe)
+            if (e) (void)hipEventDestroy(e);
+    }
+    ring.clear();
+}
+
+hipError_t Workspace::ensure(uint32_t n_points, uint32_t n_scans, uint32_t n_grids, uint32_t entry_factor,
+                             hipStream_t st) {
+    const uint64_t need_items = (uint64_t)entry_factor * std::max<uint32_t>(n_points, 1);
+    if (n_points <= points_cap && n_scans <= scans_cap && n_grids <= grids_cap && need_items <= items_cap &&
+        d_desc)
+        return hipSuccess;
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    deliver_all();
+    // keep the staging buffer, drop the rest
+    float *keep = staging;
+    size_t keep_cap = staging_cap;
+    staging = nullptr;
+    std::vector<RingSlot> keep_ring;
+    keep_ring.swap(ring);
+    release();
+    ring.swap(keep_ring);
+    staging = keep;
+    staging_cap = keep_cap;
+
+    points_cap = std::max(next_pow2(n_points, 4096), points_cap);
+    scans_cap = std::max(next_pow2(n_scans, 16), scans_cap);
+    grids_cap = std::max(next_pow2(n_grids, 16), grids_cap);
+    const uint64_t ic = (uint64_t)entry_factor * points_cap;
+    if (ic > 0xFFFFFFF0ull) return hipErrorInvalidValue;
+    items_cap = entries_cap = (uint32_t)ic;
+    hash_cap = next_pow2(2ull * points_cap, 8192);
+    desc_bytes = sizeof(Ctrl) + sizeof(CallInfo) + (size_t)grids_cap * sizeof(DevGrid) + (size_t)scans_cap * sizeof(DevScan);
+    const size_t ctr_words = (size_t)scans_cap * SC_N + (size_t)grids_cap * TC_N;
+    struct A {
+        void **p;
+        size_t bytes;
+    } al[] = {
+        {&d_desc, desc_bytes},
+        {(void **)&rec, (size_t)points_cap * sizeof(uint4)},
+        {(void **)&pslot, (size_t)points_cap * 4},
+        {(void **)&hkeys, (size_t)hash_cap * 8},
+        {(void **)&hvals, (size_t)hash_cap * 4},
+        {(void **)&items, (size_t)items_cap * 8},
+        {(void **)&item_off, (size_t)items_cap * 4},
+        {(void **)&item_cur, (size_t)items_cap * 4},
+        {(void **)&entries, (size_t)entries_cap * 4},
+        {(void **)&survivors, (size_t)points_cap * 4},
+        {(void **)&ctr, ctr_words * 8},
+    };
+    for (auto &a : al) {
+        e = hipMalloc(a.p, a.bytes);
+        if (e != hipSuccess) {
+            release();
+            return e;
+        }
+    }
+    e = launch_fill_u64(hkeys, kHashEmpty, hash_cap, st);
+    if (e == hipSuccess) e = launch_fill_u32(hvals, 0xFFFFFFFFu, hash_cap, st);
+    if (e == hipSuccess) e = hipMemsetAsync(d_desc, 0, desc_bytes, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return e;
+}
+
+hipError_t Workspace::ensure_staging(size_t floats, hipStream_t st) {
+    if (floats <= staging_cap && staging) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    if (staging) (void)hipFree(staging);
+    staging = nullptr;
+    size_t cap = std::max<size_t>(floats, 3 * 4096);
+    cap = std::max(cap, staging_cap * 2);
+    e = hipMalloc((void **)&staging, cap * sizeof(float));
+    staging_cap = e == hipSuccess ? cap : 0;
+    drop_graphs();
+    return e;
+}
+
+RingSlot &Workspace::next_slot(size_t bytes, std::string *err) {
+    constexpr uint32_t kRing = 16;
+    if (ring.size() < kRing) ring.resize(kRing);
+    RingSlot &s = ring[ring_next];
+    ring_next = (ring_next + 1) % kRing;
+    if (s.busy) {
+        (void)hipEventSynchronize(s.ev);
+        deliver(s);
+    }
+    if (!s.ev) (void)hipEventCreateWithFlags(&s.ev, hipEventDisableTiming);
+    for (hipEvent_t &e : s.pe)
+        if (!e) (void)hipEventCreate(&e);
+    if (s.bytes < bytes) {
+        if (s.host) (void)hipHostFree(s.host);
+        s.host = nullptr;
+        s.bytes = 0;
+        if (hipHostMalloc(&s.host, bytes, hipHostMallocDefault) != hipSuccess) {
+            if (err) *err = "pinned descriptor allocation failed";
+            s.host = nullptr;
+        } else {
+            s.bytes = bytes;
+        }
+    }
+    return s;
+}
+
+void Workspace::deliver(RingSlot &s) {
+    if (!s.busy) return;
+    const unsigned long long *c = (const unsigned long long *)((const char *)s.host + s.ctr_off);
+    for (const PendingStat &p : s.pend) {
+        dbtsdf_scan_stats st{};
+        const unsigned long long *sc = c + (size_t)p.scan * SC_N;
+        st.n_in = p.n_in;
+        st.n_invalid = sc[SC_INVALID];
+        st.n_out_of_bounds = sc[SC_OOB];
+        st.n_duplicate = sc[SC_DUP];
+        st.n_integrated = sc[SC_INT];
+        st.voxel_updates = sc[SC_INT] * p.k3;
+        st.shadow_updates = sc[SC_SHADOW];
+        if (p.traffic_grid >= 0) {
+            const unsigned long long *tc = c + (size_t)scans_cap * SC_N + (size_t)p.traffic_grid * TC_N;
+            st.u_mask = tc[TC_UMASK];
+            st.c_mask = tc[TC_CMASK];
+            st.u_shadow = tc[TC_USHADOW];
+        }
+        if (p.dst) *p.dst = st;
+    }
+    s.pend.clear();
+    if (s.prof) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, s.pe[0], s.pe[2]) == hipSuccess) {
+            prof_call_ms += ms;
+            ++prof_calls;
+        }
+        if (s.prof == 2 && hipEventElapsedTime(&ms, s.pe[1], s.pe[2]) == hipSuccess) {
+            prof_apply_ms += ms;
+            ++prof_apply;
+        }
+        s.prof = 0;
+    }
+    s.busy = false;
+}
+
+void Workspace::deliver_all() {
+    for (RingSlot &s : ring) {
+        if (!s.busy) continue;
+        (void)hipEventSynchronize(s.ev);
+        deliver(s);
+    }
+}
+
+// ------------------------------------------------------------ bricks ---
+dbtsdf_status ensure_bricks(dbtsdf_grid *g) {
+    const Tuning &t = g->tuning;
+    if (g->brick_cnt && g->brick_dims[0] == t.bx && g->brick_dims[1] == t.by && g->brick_dims[2] == t.bz)
+        return DBTSDF_OK;
+    hipError_t e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return check_hip(e, "synchronising before brick re-allocation", g);
+    if (g->brick_cnt) (void)hipFree(g->brick_cnt);
+    if (g->brick_slot) (void)hipFree(g->brick_slot);
+    g->brick_cnt = g->brick_slot = nullptr;
+    const uint32_t bd[3] = {t.bx, t.by, t.bz};
+    uint64_t nbr = 1;
+    for (int k = 0; k < 3; ++k) {
+        g->nb[k] = (g->params.dims[k] + bd[k] - 1) / bd[k];
+        nbr *= g->nb[k];
+        g->brick_dims[k] = bd[k];
+    }
+    e = hipMalloc((void **)&g->brick_cnt, nbr * 4);
+    if (e == hipSuccess) e = hipMalloc((void **)&g->brick_slot, nbr * 4);
+    if (e == hipSuccess) e = launch_fill_u32(g->brick_cnt, 0u, nbr, g->stream);
+    if (e != hipSuccess) {
+        g->brick_cnt = nullptr;
+        return check_hip(e, "allocating brick counters", g);
+    }
+    if (g->ws) g->ws->drop_graphs();
+    return DBTSDF_OK;
+}
+
+static uint32_t entry_factor(const Tuning &t, int R) {
+    const uint32_t b[3] = {t.bx, t.by, t.bz};
+    uint32_t f = 1;
+    for (int k = 0; k < 3; ++k) f *= 1u + (2u * R + b[k] - 1u) / b[k];
+    return f;
+}
+
+// ------------------------------------------------------------ enqueue ---
+static std::string graph_key(const PipeArgs &a, const Tuning &t, uint32_t cap) {
+    std::string k;
+    k.append((const char *)&a, sizeof(a));
+    k.append((const char *)&t, sizeof(t));
+    k.append((const char *)&cap, sizeof(cap));
+    return k;
+}
+
+dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &scans, bool use_graph) {
+    // drop empty scans (their statistics are all zero)
+    std::vector<ScanIn> live;
+    for (ScanIn &s : scans) {
+        if (s.n == 0) {
+            if (s.stats) *s.stats = dbtsdf_scan_stats{};
+        } else {
+            live.push_back(s);
+        }
+    }
+    if (live.empty()) return DBTSDF_OK;
+    dbtsdf_grid *g0 = live[0].grid;
+    std::vector<dbtsdf_grid *> grids;
+    std::unordered_map<dbtsdf_grid *, uint32_t> gidx;
+    uint64_t total = 0;
+    bool traffic = false;
+    for (ScanIn &s : live) {
+        dbtsdf_grid *g = s.grid;
+        if (g->poisoned) {
+            set_error("grid is poisoned by an earlier device error");
+            return DBTSDF_ERR_POISONED;
+        }
+        if (g->device != g0->device) return invalid("all grids of a batch must be on one device");
+        if (std::memcmp(&g->kparams, &g0->kparams, sizeof(g->kparams)) != 0)
+            return invalid("all grids of a batch must share the kernel parameters");
+        if (g->tuning.strategy != g0->tuning.strategy || g->tuning.bx != g0->tuning.bx ||
+            g->tuning.by != g0->tuning.by || g->tuning.bz != g0->tuning.bz || g->tuning.threads != g0->tuning.threads)
+            return invalid("all grids of a batch must share the tuning");
+        if (!gidx.count(g)) {
+            gidx[g] = (uint32_t)grids.size();
+            grids.push_back(g);
+        }
+        traffic |= (g->params.flags & DBTSDF_COUNT_TRAFFIC) != 0;
+        total += s.n;
+    }
+    if (total > kMaxPointsPerCall) {
+        set_error("too many points in one call");
+        return DBTSDF_ERR_OUT_OF_RANGE;
+    }
+    if (live.size() > kMaxScansPerCall) {
+        set_error("too many scans in one call");
+        return DBTSDF_ERR_OUT_OF_RANGE;
+    }
+    Tuning tun = g0->tuning;
+    if (traffic) tun.strategy = DBTSDF_STRATEGY_BRICK;  // unique-word counts come from the brick merge
+    if (tun.apply_blocks == 0) tun.apply_blocks = (uint32_t)apply_blocks_default(tun, g0->device);
+    for (dbtsdf_grid *g : grids) {
+        dbtsdf_status s = ensure_bricks(g);
+        if (s != DBTSDF_OK) return s;
+    }
+    const int R = g0->tables->t.R;
+    const uint32_t ef = entry_factor(tun, R);
+    hipError_t e = ws.ensure((uint32_t)total, (uint32_t)live.size(), (uint32_t)grids.size(), ef, st);
+    if (e != hipSuccess) return check_hip(e, "allocating the workspace", g0);
+
+    // descriptors, laid out as on the device: CallInfo | DevGrid[grids_cap] | DevScan[n_scans]
+    const size_t n_sc = live.size(), n_gr = grids.size();
+    const size_t scans_off = sizeof(CallInfo) + (size_t)ws.grids_cap * sizeof(DevGrid);
+    const size_t desc_bytes = scans_off + n_sc * sizeof(DevScan);
+    const size_t ctr_bytes = ((size_t)ws.scans_cap * SC_N + (size_t)ws.grids_cap * TC_N) * 8;
+    const size_t ctr_off = (desc_bytes + 255) & ~(size_t)255;
+    std::string err;
+    RingSlot &slot = ws.next_slot(ctr_off + ctr_bytes, &err);
+    if (!slot.host) {
+        set_error(err);
+        return DBTSDF_ERR_OUT_OF_MEMORY;
+    }
+    char *h = (char *)slot.host;
+    CallInfo ci{(uint32_t)total, (uint32_t)n_sc, (uint32_t)n_gr, 0};
+    std::memcpy(h, &ci, sizeof(ci));
+    DevGrid *hg = (DevGrid *)(h + sizeof(CallInfo));
+    for (size_t i = 0; i < n_gr; ++i) {
+        dbtsdf_grid *g = grids[i];
+        DevGrid d{};
+        d.mask = g->mask;
+        d.packed = g->packed;
+        d.brick_cnt = g->brick_cnt;
+        d.brick_slot = g->brick_slot;
+        d.nx = g->params.dims[0];
+        d.ny = g->params.dims[1];
+        d.nz = g->params.dims[2];
+        d.nbx = g->nb[0];
+        d.nby = g->nb[1];
+        d.nbz = g->nb[2];
+        d.T = g->params.hit_threshold;
+        d.hmax = g->params.hit_max;
+        d.traffic_slot = (uint32_t)i;
+        std::memcpy(&hg[i], &d, sizeof(d));
+    }
+    DevScan *hs = (DevScan *)(h + scans_off);
+    uint32_t begin = 0;
+    std::vector<bool> traffic_given(n_gr, false);
+    slot.pend.clear();
+    const uint64_t k3 = (uint64_t)g0->K * g0->K * g0->K;
+    for (size_t i = 0; i < n_sc; ++i) {
+        const ScanIn &s = live[i];
+        const dbtsdf_grid_params &gp = s.grid->params;
+        DevScan d{};
+        for (int r = 0; r < 3; ++r) {
+            for (int c = 0; c < 3; ++c) d.rot[3 * r + c] = s.pose[4 * r + c];
+            d.trans[r] = s.pose[4 * r + 3];
+            d.origin[r] = gp.origin[r];
+        }
+        d.inv_s = 1.0f / gp.voxel_size;
+        d.pts = s.points;
+        d.begin = begin;
+        d.n = (uint32_t)s.n;
+        d.grid = gidx[s.grid];
+        d.dedup = (gp.flags & DBTSDF_DEDUP_FIRST) ? 1u : 0u;
+        std::memcpy(&hs[i], &d, sizeof(d));
+        begin += (uint32_t)s.n;
+        PendingStat p{s.stats, (uint32_t)i, -1, s.n, k3};
+        if ((gp.flags & DBTSDF_COUNT_TRAFFIC) && !traffic_given[d.grid]) {
+            p.traffic_grid = (int32_t)d.grid;
+            traffic_given[d.grid] = true;
+        }
+        if (s.stats) slot.pend.push_back(p);
+    }
+    char *dd = (char *)ws.d_desc;
+    e = hipMemcpyAsync(dd + sizeof(Ctrl), h, desc_bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return check_hip(e, "uploading descriptors", g0);
+
+    PipeArgs a{};
+    a.ctrl = (Ctrl *)dd;
+    a.grids = (const DevGrid *)(dd + sizeof(Ctrl) + sizeof(CallInfo));
+    a.scans = (const DevScan *)(dd + sizeof(Ctrl) + scans_off);
+    a.tab = g0->tables->t;
+    a.brick[0] = tun.bx;
+    a.brick[1] = tun.by;
+    a.brick[2] = tun.bz;
+    a.hash_mask = ws.hash_cap - 1;
+    a.rec = ws.rec;
+    a.pslot = ws.pslot;
+    a.hkeys = ws.hkeys;
+    a.hvals = ws.hvals;
+    a.items = ws.items;
+    a.item_off = ws.item_off;
+    a.item_cur = ws.item_cur;
+    a.entries = ws.entries;
+    a.survivors = ws.survivors;
+    a.scan_ctr = ws.ctr;
+    a.traffic_ctr = ws.ctr + (size_t)ws.scans_cap * SC_N;
+    a.items_cap = ws.items_cap;
+    a.entries_cap = ws.entries_cap;
+    a.count_traffic = traffic ? 1u : 0u;
+
+    slot.prof = 0;
+    if (ws.profile) {
+        e = hipEventRecord(slot.pe[0], st);
+        if (e != hipSuccess) return check_hip(e, "profiling event", g0);
+        slot.prof = use_graph ? 1 : 2;
+    }
+    if (use_graph) {
+        const std::string key = graph_key(a, tun, ws.points_cap);
+        auto it = ws.graphs.find(key);
+        if (it == ws.graphs.end()) {
+            hipGraph_t graph = nullptr;
+            e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                hipError_t le = launch_pipeline(a, tun, ws.points_cap, st);
+                e = hipStreamEndCapture(st, &graph);
+                if (e == hipSuccess) e = le;
+            }
+            GraphEntry ge;
+            if (e == hipSuccess) e = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
+            if (graph) (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) return check_hip(e, "capturing the integration graph", g0);
+            it = ws.graphs.emplace(key, ge).first;
+            ++ws.captures;
+        }
+        e = hipGraphLaunch(it->second.exec, st);
+        ++ws.replays;
+        if (e == hipSuccess && slot.prof) e = hipEventRecord(slot.pe[2], st);
+    } else if (slot.prof) {
+        e = launch_pipeline(a, tun, ws.points_cap, st, slot.pe[1], slot.pe[2]);
+    } else {
+        e = launch_pipeline(a, tun, ws.points_cap, st);
+    }
+    if (e != hipSuccess) return check_hip(e, "launching the integration kernels", g0);
+
+    slot.ctr_off = ctr_off;
+    e = hipMemcpyAsync(h + ctr_off, ws.ctr, ctr_bytes, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipEventRecord(slot.ev, st);
+    if (e != hipSuccess) return check_hip(e, "queueing statistics readback", g0);
+    slot.busy = true;
+    return DBTSDF_OK;
+}
+
+}  // namespace dbtsdf
+
+// =================================================================== C ABI ===
+extern "C" {
+
+const char *dbtsdf_status_string(dbtsdf_status s) {
+    switch (s) {
+        case DBTSDF_OK: return "ok";
+        case DBTSDF_ERR_INVALID_ARG: return "invalid argument";
+        case DBTSDF_ERR_OUT_OF_MEMORY: return "out of memory";
+        case DBTSDF_ERR_DEVICE: return "device error";
+        case DBTSDF_ERR_OUT_OF_RANGE: return "out of range";
+        case DBTSDF_ERR_POISONED: return "grid poisoned by an earlier device error";
+        case DBTSDF_ERR_BUSY: return "busy";
+    }
+    return "unknown status";
+}
+
+const char *dbtsdf_last_error(void) { return g_err.c_str(); }
+
+uint64_t dbtsdf_now_ns(void) {
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (uint64_t)ts.tv_sec * 1000000000ull + (uint64_t)ts.tv_nsec;
+}
+
+// ------------------------------------------------------------ kernel sets ---
+dbtsdf_status dbtsdf_kernel_set_create(const dbtsdf_kernel_params *params, dbtsdf_kernel_set **out) {
+    if (!params || !out) return invalid("NULL argument");
+    std::string err;
+    KernelSet *ks = build_kernel_set(*params, &err);
+    if (!ks) return invalid(err);
+    *out = new dbtsdf_kernel_set();
+    (*out)->ks.reset(ks);
+    return DBTSDF_OK;
+}
+
+dbtsdf_status dbtsdf_kernel_set_export(const dbtsdf_kernel_set *k, uint32_t *masks, uint8_t *shadow, double *dirs,
+                                       uint32_t *n_bins) {
+    if (!k || !k->ks) return invalid("NULL kernel set");
+    const KernelSet &ks = *k->ks;
+    if (masks) std::memcpy(masks, ks.cell_mask.data(), ks.cell_mask.size() * 4);
+    if (shadow) std::memcpy(shadow, ks.shadow.data(), ks.shadow.size());
+    if (dirs) std::memcpy(dirs, ks.dirs.data(), ks.dirs.size() * 8);
+    if (n_bins) *n_bins = ks.n_bins;
+    return DBTSDF_OK;
+}
+
+uint32_t dbtsdf_kernel_set_n_bins(const dbtsdf_kernel_set *k) { return (k && k->ks) ? k->ks->n_bins : 0; }
+
+int32_t dbtsdf_kernel_set_bin(const dbtsdf_kernel_set *k, float dx, float dy, float dz) {
+    if (!k || !k->ks) return -1;
+    return host_bin(*k->ks, dx, dy, dz);
+}
+
+void dbtsdf_kernel_set_destroy(dbtsdf_kernel_set *k) { delete k; }
+
+// ------------------------------------------------------------------ grids ---
+uint64_t dbtsdf_grid_bytes(const dbtsdf_grid_params *p) {
+    if (!p) return 0;
+    return (uint64_t)p->dims[0] * p->dims[1] * p->dims[2] * 8ull;
+}
+
+static dbtsdf_status validate_grid_params(const dbtsdf_grid_params *p, int K) {
+    if (!p) return invalid("NULL grid params");
+    for (int k = 0; k < 3; ++k) {
+        if (p->dims[k] < (uint32_t)K || p->dims[k] > kMaxDim) return invalid("each dim must be in [K, 2^20]");
+        if (!std::isfinite(p->origin[k])) return invalid("origin must be finite");
+    }
+    const uint64_t nv = (uint64_t)p->dims[0] * p->dims[1] * p->dims[2];
+    if (nv >= (1ull << kVoxelKeyBits)) return invalid("grid has too many voxels");
+    if (!std::isfinite(p->voxel_size) || !(p->voxel_size > 0.0f)) return invalid("voxel_size must be finite and > 0");
+    if (!std::isfinite(1.0f / p->voxel_size)) return invalid("voxel_size too small");
+    if (p->hit_max < 1 || p->hit_max > 65535) return invalid("hit_max must be in 1..65535");
+    if (p->hit_threshold > 65535) return invalid("hit_threshold must be <= 65535");
+    if (p->flags & ~(DBTSDF_DEDUP_FIRST | DBTSDF_COUNT_TRAFFIC)) return invalid("unknown grid flags");
+    return DBTSDF_OK;
+}
+
+static dbtsdf_status create_grid_impl(const dbtsdf_grid_params *params, const dbtsdf_kernel_set *ks, void *stream,
+                                      void *mask_dev, void *packed_dev, dbtsdf_grid **out) {
+    if (!out) return invalid("NULL out");
+    *out = nullptr;
+    if (!ks || !ks->ks) return invalid("NULL kernel set");
+    dbtsdf_status s = validate_grid_params(params, ks->ks->K);
+    if (s != DBTSDF_OK) return s;
+    auto g = std::make_unique<dbtsdf_grid>();
+    g->params = *params;
+    g->kparams = ks->ks->p;
+    g->K = ks->ks->K;
+    g->stream = (hipStream_t)stream;
+    g->n_voxels = (uint64_t)params->dims[0] * params->dims[1] * params->dims[2];
+    hipError_t e = hipGetDevice(&g->device);
+    if (e != hipSuccess) return check_hip(e, "hipGetDevice");
+    s = make_device_tables(*ks->ks, g->tables);
+    if (s != DBTSDF_OK) return s;
+    if (mask_dev || packed_dev) {
+        if (!mask_dev || !packed_dev) return invalid("both planes must be given");
+        if (((uintptr_t)mask_dev | (uintptr_t)packed_dev) & 15u) return invalid("planes must be 16-byte aligned");
+        g->owns_planes = false;
+        g->mask = (uint32_t *)mask_dev;
+        g->packed = (uint32_t *)packed_dev;
+    } else {
+        e = hipMalloc((void **)&g->mask, g->n_voxels * 4);
+        if (e == hipSuccess) e = hipMalloc((void **)&g->packed, g->n_voxels * 4);
+        if (e != hipSuccess) {
+            if (g->mask) (void)hipFree(g->mask);
+            g->mask = nullptr;
+            (void)hipGetLastError();
+            set_error("grid planes do not fit in device memory");
+            return DBTSDF_ERR_OUT_OF_MEMORY;
+        }
+    }
+    e = launch_grid_init(g->mask, g->packed, g->n_voxels, g->stream);
+    if (e != hipSuccess) return check_hip(e, "filling the initial state");
+    e = hipEventCreateWithFlags(&g->ev, hipEventDisableTiming);
+    if (e != hipSuccess) return check_hip(e, "hipEventCreate");
+    g->tuning = Tuning{};
+    g->ws = std::make_unique<Workspace>();
+    g->ws->device = g->device;
+    s = ensure_bricks(g.get());
+    if (s != DBTSDF_OK) return s;
+    *out = g.release();
+    return DBTSDF_OK;
+}
+
+dbtsdf_status dbtsdf_create_grid(const dbtsdf_grid_params *params, const dbtsdf_kernel_set *ks, void *hip_stream,
+                                 dbtsdf_grid **out) {
+    return create_grid_impl(params, ks, hip_stream, nullptr, nullptr, out);
+}
+
+dbtsdf_status dbtsdf_create_grid_on(const dbtsdf_grid_params *params, const dbtsdf_kernel_set *ks, void *hip_stream,
+                                    void *mask_dev, void *packed_dev, dbtsdf_grid **out) {
+    if (!mask_dev || !packed_dev) return invalid("NULL plane");
+    return create_grid_impl(params, ks, hip_stream, mask_dev, packed_dev, out);
+}
+
+dbtsdf_status dbtsdf_grid_planes(const dbtsdf_grid *g, void **mask_dev, void **packed_dev) {
+    if (!g) return invalid("NULL grid");
+    if (mask_dev) *mask_dev = g->mask;
+    if (packed_dev) *packed_dev = g->packed;
+    return DBTSDF_OK;
+}
+
+dbtsdf_status dbtsdf_reset_grid(dbtsdf_grid *g) {
+    if (!g) return invalid("NULL grid");
+    if (g->poisoned) return DBTSDF_ERR_POISONED;
+    return check_hip(launch_grid_init(g->mask, g->packed, g->n_voxels, g->stream), "resetting the grid", g);
+}
+
+dbtsdf_status dbtsdf_get_tuning(const dbtsdf_grid *g, dbtsdf_tuning *out) {
+    if (!g || !out) return invalid("NULL argument");
+    out->strategy = g->tuning.strategy;
+    out->brick[0] = g->tuning.bx;
+    out->brick[1] = g->tuning.by;
+    out->brick[2] = g->tuning.bz;
+    out->block_threads = g->tuning.threads;
+    out->apply_blocks = g->tuning.apply_blocks;
+    return DBTSDF_OK;
+}
+
+dbtsdf_status dbtsdf_set_tuning(dbtsdf_grid *g, const dbtsdf_tuning *t) {
+    if (!g || !t) return invalid("NULL argument");
+    Tuning n;
+    n.strategy = t->strategy == DBTSDF_STRATEGY_AUTO ? (uint32_t)DBTSDF_STRATEGY_BRICK : t->strategy;
+    n.bx = t->brick[0];
+    n.by = t->brick[1];
+    n.bz = t->brick[2];
+    n.threads = t->block_threads;
+    n.apply_blocks = t->apply_blocks;
+    if (n.strategy == DBTSDF_STRATEGY_ATOMIC) {
+        if (n.bx == 0) {
+            n.bx = g->tuning.bx;
+            n.by = g->tuning.by;
+            n.bz = g->tuning.bz;
+        }
+        Tuning probe = n;
+        probe.strategy = DBTSDF_STRATEGY_BRICK;
+        probe.threads = 256;
+        if (!tuning_supported(probe, g->K)) return invalid("unsupported brick shape");
+        if (n.threads == 0) n.threads = 256;
+    }
+    if (!tuning_supported(n, g->K)) return invalid("unsupported tuning");
+    if (n.apply_blocks > (1u << 20)) return invalid("apply_blocks too large");
+    g->tuning = n;
+    g->ws->drop_graphs();
+    return ensure_bricks(g);
+}
+
+dbtsdf_status dbtsdf_integrate_scan(dbtsdf_grid *g, const float pose[16], const float *points, uint64_t n,
+                                    int points_on_device, dbtsdf_scan_stats *stats) {
+    if (!g || !pose) return invalid("NULL argument");
+    if (g->poisoned) {
+        set_error("grid is poisoned by an earlier device error");
+        return DBTSDF_ERR_POISONED;
+    }
+    for (int k = 0; k < 16; ++k)
+        if (!std::isfinite(pose[k])) return invalid("pose must be finite");
+    if (n > kMaxPointsPerCall) {
+        set_error("too many points in one call");
+        return DBTSDF_ERR_OUT_OF_RANGE;
+    }
+    if (n && !points) return invalid("NULL points");
+    if (n == 0) {
+        if (stats) *stats = dbtsdf_scan_stats{};
+        return DBTSDF_OK;
+    }
+    const float *dev = points;
+    if (!points_on_device) {
+        hipError_t e = g->ws->ensure_staging(3 * n, g->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(g->ws->staging, points, 12 * n, hipMemcpyHostToDevice, g->stream);
+        if (e != hipSuccess) return check_hip(e, "staging host points", g);
+        dev = g->ws->staging;
+    }
+    std::vector<ScanIn> v{ScanIn{g, pose, dev, n, stats}};
+    return enqueue_scans(*g->ws, g->stream, v, false);
+}
+
+dbtsdf_status dbtsdf_sync(dbtsdf_grid *g) {
+    if (!g) return invalid("NULL grid");
+    if (g->poisoned) return DBTSDF_ERR_POISONED;
+    hipError_t e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return check_hip(e, "synchronising the grid stream", g);
+    g->ws->deliver_all();
+    return DBTSDF_OK;
+}
+
+static dbtsdf_status check_box(const dbtsdf_grid *g, const uint32_t lo[3], const uint32_t hi[3]) {
+    if (!g || !lo || !hi) return invalid("NULL argument");
+    for (int k = 0; k < 3; ++k)
+        if (lo[k] >= hi[k] || hi[k] > g->params.dims[k]) {
+            set_error("box must satisfy lo < hi <= dims");
+            return DBTSDF_ERR_OUT_OF_RANGE;
+        }
+    return DBTSDF_OK;
+}
+
+static dbtsdf_status gather(dbtsdf_grid *g, const uint32_t lo[3], const uint32_t hi[3], const uint32_t *plane,
+                            const uint32_t *packed, void *host, size_t elem) {
+    const uint64_t n = (uint64_t)(hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]);
+    void *tmp = nullptr;
+    hipError_t e = hipMalloc(&tmp, n * elem);
+    if (e != hipSuccess) return check_hip(e, "readout buffer");
+    e = launch_gather_box(plane, packed, g->params.dims, lo, hi, tmp, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e == hipSuccess) e = hipMemcpy(host, tmp, n * elem, hipMemcpyDeviceToHost);
+    (void)hipFree(tmp);
+    return check_hip(e, "reading voxels", g);
+}
+
+dbtsdf_status dbtsdf_read_voxels(dbtsdf_grid *g, const uint32_t lo[3], const uint32_t hi[3], uint32_t *mask_out,
+                                 uint32_t *packed_out) {
+    dbtsdf_status s = check_box(g, lo, hi);
+    if (s != DBTSDF_OK) return s;
+    if (g->poisoned) return DBTSDF_ERR_POISONED;
+    if (mask_out && (s = gather(g, lo, hi, g->mask, nullptr, mask_out, 4)) != DBTSDF_OK) return s;
+    if (packed_out && (s = gather(g, lo, hi, g->packed, nullptr, packed_out, 4)) != DBTSDF_OK) return s;
+    return DBTSDF_OK;
+}
+
+dbtsdf_status dbtsdf_read_distance(dbtsdf_grid *g, const uint32_t lo[3], const uint32_t hi[3], int8_t *dist_out) {
+    dbtsdf_status s = check_box(g, lo, hi);
+    if (s != DBTSDF_OK) return s;
+    if (!dist_out) return invalid("NULL output");
+    if (g->poisoned) return DBTSDF_ERR_POISONED;
+    return gather(g, lo, hi, g->mask, g->packed, dist_out, 1);
+}
+
+dbtsdf_status dbtsdf_write_voxels(dbtsdf_grid *g, const uint32_t *mask_in, const uint32_t *packed_in) {
+    if (!g || !mask_in || !packed_in) return invalid("NULL argument");
+    if (g->poisoned) return DBTSDF_ERR_POISONED;
+    const uint32_t T = g->params.hit_threshold, H = g->params.hit_max;
+    const bool can_flip = T >= 1 && T <= H;
+    for (uint64_t i = 0; i < g->n_voxels; ++i) {
+        const uint32_t m = mask_in[i], p = packed_in[i];
+        const uint32_t h = p & 0xFFFFu;
+        const bool occupied = (p >> 31) == 0;
+        if ((m & (m + 1u)) != 0u) return invalid("mask word is not of the form 2^n - 1");
+        if (p & 0x7FFF0000u) return invalid("packed word has bits 16-30 set");
+        if (h > H) return invalid("hit counter above hit_max");
+        if (occupied != (can_flip && h >= T)) return invalid("sign disagrees with the hit counter");
+    }
+    hipError_t e = hipStreamSynchronize(g->stream);
+    if (e == hipSuccess) e = hipMemcpy(g->mask, mask_in, g->n_voxels * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(g->packed, packed_in, g->n_voxels * 4, hipMemcpyHostToDevice);
+    return check_hip(e, "writing voxels", g);
+}
+
+void dbtsdf_destroy_grid(dbtsdf_grid *g) {
+    if (!g) return;
+    (void)hipStreamSynchronize(g->stream);
+    g->ws.reset();
+    if (g->brick_cnt) (void)hipFree(g->brick_cnt);
+    if (g->brick_slot) (void)hipFree(g->brick_slot);
+    if (g->owns_planes) {
+        if (g->mask) (void)hipFree(g->mask);
+        if (g->packed) (void)hipFree(g->packed);
+    }
+    if (g->ev) (void)hipEventDestroy(g->ev);
+    delete g;
+}
+
+// -------------------------------------------------------------- profiling ---
+static dbtsdf_status read_prof(Workspace &ws, hipStream_t st, double *call_ms, uint64_t *calls, double *apply_ms,
+                               uint64_t *applies) {
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return check_hip(e, "synchronising for the profile");
+    ws.deliver_all();
+    if (call_ms) *call_ms = ws.prof_call_ms;
+    if (calls) *calls = ws.prof_calls;
+    if (apply_ms) *apply_ms = ws.prof_apply_ms;
+    if (applies) *applies = ws.prof_apply;
+    return DBTSDF_OK;
+}
+
+dbtsdf_status dbtsdf_set_profiling(dbtsdf_grid *g, int enable) {
+    if (!g) return invalid("NULL grid");
+    g->ws->profile = enable != 0;
+    g->ws->prof_call_ms = g->ws->prof_apply_ms = 0.0;
+    g->ws->prof_calls = g->ws->prof_apply = 0;
+    return DBTSDF_OK;
+}
+
+dbtsdf_status dbtsdf_read_profile(dbtsdf_grid *g, double *call_ms, uint64_t *calls, double *apply_ms,
+                                  uint64_t *applies) {
+    if (!g) return invalid("NULL grid");
+    return read_prof(*g->ws, g->stream, call_ms, calls, apply_ms, applies);
+}
+
+dbtsdf_status dbtsdf_batch_set_profiling(dbtsdf_batch *b, int enable) {
+    if (!b) return invalid("NULL batch");
+    b->ws->profile = enable != 0;
+    b->ws->prof_call_ms = b->ws->prof_apply_ms = 0.0;
+    b->ws->prof_calls = b->ws->prof_apply = 0;
+    return DBTSDF_OK;
+}
+
+dbtsdf_status dbtsdf_batch_read_profile(dbtsdf_batch *b, double *call_ms, uint64_t *calls, double *apply_ms,
+                                        uint64_t *applies) {
+    if (!b) return invalid("NULL batch");
+    return read_prof(*b->ws, b->stream, call_ms, calls, apply_ms, applies);
+}
+
+// ---------------------------------------------------------------- batches ---
+dbtsdf_status dbtsdf_batch_create(void *hip_stream, int use_graph, dbtsdf_batch **out) {
+    if (!out) return invalid("NULL out");
+    auto b = std::make_unique<dbtsdf_batch>();
+    hipError_t e = hipGetDevice(&b->device);
+    if (e != hipSuccess) return check_hip(e, "hipGetDevice");
+    b->stream = (hipStream_t)hip_stream;
+    if (!b->stream) {
+        e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return check_hip(e, "creating the batch stream");
+        b->owns_stream = true;
+    }
+    b->use_graph = use_graph != 0;
+    e = hipEventCreateWithFlags(&b->ev, hipEventDisableTiming);
+    if (e != hipSuccess) return check_hip(e, "hipEventCreate");
+    b->ws = std::make_unique<Workspace>();
+    b->ws->device = b->device;
+    *out = b.release();
+    return DBTSDF_OK;
+}
+
+dbtsdf_status dbtsdf_batch_integrate(dbtsdf_batch *b, uint32_t n_scans, dbtsdf_grid *const *grids, const float *poses,
+                                     const float *const *points, const uint64_t *n, int points_on_device,
+                                     dbtsdf_scan_stats *stats) {
+    if (!b) return invalid("NULL batch");
+    if (n_scans == 0) return DBTSDF_OK;
+    if (!grids || !poses || !points || !n) return invalid("NULL argument");
+    uint64_t total = 0;
+    for (uint32_t i = 0; i < n_scans; ++i) {
+        if (!grids[i]) return invalid("NULL grid");
+        if (grids[i]->device != b->device) return invalid("grid on another device than the batch");
+        if (grids[i]->poisoned) return DBTSDF_ERR_POISONED;
+        if (n[i] && !points[i]) return invalid("NULL points");
+        for (int k = 0; k < 16; ++k)
+            if (!std::isfinite(poses[16 * (size_t)i + k])) return invalid("pose must be finite");
+        total += n[i];
+    }
+    if (total > kMaxPointsPerCall) {
+        set_error("too many points in one call");
+        return DBTSDF_ERR_OUT_OF_RANGE;
+    }
+    std::vector<ScanIn> v(n_scans);
+    float *stage = nullptr;
+    if (!points_on_device) {
+        hipError_t e = b->ws->ensure_staging(3 * std::max<uint64_t>(total, 1), b->stream);
+        if (e != hipSuccess) return check_hip(e, "allocating point staging");
+        stage = b->ws->staging;
+    }
+    // order after earlier work on each grid's own stream
+    std::vector<dbtsdf_grid *> distinct;
+    for (uint32_t i = 0; i < n_scans; ++i)
+        if (std::find(distinct.begin(), distinct.end(), grids[i]) == distinct.end()) distinct.push_back(grids[i]);
+    for (dbtsdf_grid *g : distinct) {
+        if (g->stream == b->stream || g->external_order) continue;
+        hipError_t e = hipEventRecord(g->ev, g->stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, g->ev, 0);
+        if (e != hipSuccess) return check_hip(e, "ordering the batch after grid work", g);
+    }
+    uint64_t off = 0;
+    for (uint32_t i = 0; i < n_scans; ++i) {
+        const float *dev = points[i];
+        if (!points_on_device && n[i]) {
+            hipError_t e = hipMemcpyAsync(stage + 3 * off, points[i], 12 * n[i], hipMemcpyHostToDevice, b->stream);
+            if (e != hipSuccess) return check_hip(e, "staging host points");
+            dev = stage + 3 * off;
+        }
+        v[i] = ScanIn{grids[i], poses + 16 * (size_t)i, dev, n[i], stats ? &stats[i] : nullptr};
+        off += n[i];
+    }
+    dbtsdf_status s = enqueue_scans(*b->ws, b->stream, v, b->use_graph && b->stream != nullptr);
+    if (s != DBTSDF_OK) return s;
+    hipError_t e = hipEventRecord(b->ev, b->stream);
+    for (dbtsdf_grid *g : distinct)
+        if (e == hipSuccess && g->stream != b->stream && !g->external_order) e = hipStreamWaitEvent(g->stream, b->ev, 0);
+    return check_hip(e, "ordering grid work after the batch");
+}
+
+dbtsdf_status dbtsdf_batch_sync(dbtsdf_batch *b) {
+    if (!b) return invalid("NULL batch");
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return check_hip(e, "synchronising the batch stream");
+    b->ws->deliver_all();
+    return DBTSDF_OK;
+}
+
+dbtsdf_status dbtsdf_batch_graph_stats(const dbtsdf_batch *b, uint64_t *captures, uint64_t *replays) {
+    if (!b) return invalid("NULL batch");
+    if (captures) *captures = b->ws->captures;
+    if (replays) *replays = b->ws->replays;
+    return DBTSDF_OK;
+}
+
+void dbtsdf_batch_destroy(dbtsdf_batch *b) {
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    b->ws.reset();
+    if (b->ev) (void)hipEventDestroy(b->ev);
+    if (b->owns_stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+}  // extern "C"

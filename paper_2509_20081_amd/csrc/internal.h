@@ -1,0 +1,154 @@
+// Internal types shared by the host library and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/dbtsdf.h"
+
+namespace dbtsdf {
+
+// ---------------------------------------------------------------- limits ---
+constexpr int kMaxK = 37;                       // eq. 3 masks stay within 32 bits
+constexpr uint32_t kMaxDim = 1u << 20;          // per axis
+constexpr uint64_t kMaxPointsPerCall = 1ull << 28;
+constexpr uint64_t kMaxScansPerCall = 1ull << 20;
+constexpr int kVoxelKeyBits = 40;               // dedup key = scan << 40 | linear voxel
+constexpr uint64_t kHashEmpty = ~0ull;
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
+
+// point record word w: bits 0-15 direction bin, bits 16-17 status,
+// bit 30 set by the select pass on returns that are integrated
+constexpr uint32_t kStOk = 0, kStInvalid = 1, kStOob = 2;
+constexpr uint32_t kRecSurvivor = 1u << 30;
+
+// ------------------------------------------------------- host kernel set ---
+struct KernelSet {
+    dbtsdf_kernel_params p{};
+    int K = 0, R = 0;
+    uint32_t n_bins = 0;
+    std::vector<uint32_t> cell_mask;     // K^3, index ((dz+R)*K + (dy+R))*K + (dx+R)
+    std::vector<uint32_t> mask_by_q;     // mask by metric value q (L2: q = |o|^2, L1: q = |o|_1)
+    std::vector<uint8_t> shadow;         // n_bins * K^3 flags
+    std::vector<double> dirs;            // n_bins * 3
+    std::vector<uint32_t> sh_start;      // n_bins + 1 (CSR of shadow offsets)
+    std::vector<uint32_t> sh_off;        // packed (dx+R) | (dy+R) << 8 | (dz+R) << 16
+    // AZEL boundary tables (fp32, index k = 1..B_az/2-1 and 1..B_el-1, slot 0 unused)
+    std::vector<float> az_c, az_s, el_s2;
+    std::vector<uint32_t> el_neg;
+};
+
+KernelSet *build_kernel_set(const dbtsdf_kernel_params &p, std::string *err);
+int host_bin(const KernelSet &ks, float dx, float dy, float dz);
+
+// ---------------------------------------------------- device descriptors ---
+// Kernel tables as the device reads them (one copy per grid).
+struct DevTables {
+    const uint32_t *mask_by_q;   // n_q entries
+    const uint32_t *sh_start;    // n_bins + 1
+    const uint32_t *sh_off;      // total shadow cells
+    const float *az_c, *az_s, *el_s2;
+    const uint32_t *el_neg;
+    uint32_t n_q;
+    uint32_t n_bins;
+    int32_t K, R;
+    uint32_t binning, bins_az, bins_el, metric;
+};
+
+struct DevGrid {
+    uint32_t *mask;
+    uint32_t *packed;
+    uint32_t *brick_cnt;   // per brick: entries this call (reset by the apply pass)
+    uint32_t *brick_slot;  // per brick: work-item index this call
+    uint32_t nx, ny, nz;
+    uint32_t nbx, nby, nbz;
+    uint32_t T, hmax;
+    uint32_t traffic_slot; // index into traffic counters
+    uint32_t pad;
+};
+
+struct DevScan {
+    float rot[9];          // pose rows 0..2, columns 0..2
+    float trans[3];
+    float origin[3];
+    float inv_s;           // fl32(1 / voxel_size)
+    const float *pts;      // n x 3 fp32 on the device
+    uint32_t begin;        // offset of the scan's first point in the call
+    uint32_t n;
+    uint32_t grid;         // index into DevGrid array
+    uint32_t dedup;
+};
+
+// Per-scan counters (u64) and per-grid traffic counters.
+enum { SC_INVALID = 0, SC_OOB, SC_DUP, SC_INT, SC_SHADOW, SC_N };
+enum { TC_UMASK = 0, TC_CMASK, TC_USHADOW, TC_N };
+
+struct Ctrl {
+    uint32_t n_active;
+    uint32_t total_entries;
+    uint32_t n_survivors;
+    uint32_t pad;
+};
+
+// Sizes of the current call, read by the kernels from device memory so that a
+// captured graph can be replayed for any call that fits its capacity.
+struct CallInfo {
+    uint32_t n_points, n_scans, n_grids, pad;
+};
+
+// Everything the pipeline kernels read. Pointers into one workspace.
+struct PipeArgs {
+    const DevScan *scans;
+    const DevGrid *grids;
+    DevTables tab;
+    uint32_t brick[3];
+    uint32_t hash_mask;      // capacity - 1
+    uint4 *rec;              // per point: voxel x, y, z and the record word w
+    uint32_t *pslot;         // per point hash slot
+    unsigned long long *hkeys;
+    uint32_t *hvals;
+    unsigned long long *items;  // active (grid << 32 | brick)
+    uint32_t *item_off;
+    uint32_t *item_cur;
+    uint32_t *entries;       // point indices per work item
+    uint32_t *survivors;     // compacted survivor list (atomic strategy)
+    unsigned long long *scan_ctr;     // n_scans * SC_N
+    unsigned long long *traffic_ctr;  // n_grids * TC_N
+    Ctrl *ctrl;              // followed in memory by the CallInfo
+    uint32_t items_cap;
+    uint32_t entries_cap;
+    uint32_t count_traffic;
+};
+
+// ---------------------------------------------------------- launch config ---
+struct Tuning {
+    uint32_t strategy = DBTSDF_STRATEGY_BRICK;
+    uint32_t bx = 32, by = 16, bz = 8;
+    uint32_t threads = 256;
+    uint32_t apply_blocks = 0;
+};
+
+bool tuning_supported(const Tuning &t, int K);
+
+// Kernel launchers (kernels.hip). Return hipSuccess or the first launch error.
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, uint64_t n, hipStream_t st);
+hipError_t launch_grid_init(uint32_t *mask, uint32_t *packed, uint64_t n, hipStream_t st);
+// ev_apply (optional, pair of events) brackets the apply kernel.
+hipError_t launch_pipeline(const PipeArgs &a, const Tuning &t, uint32_t points_cap, hipStream_t st,
+                           hipEvent_t ev_apply0 = nullptr, hipEvent_t ev_apply1 = nullptr);
+hipError_t launch_read_distance(const uint32_t *mask, const uint32_t *packed, int8_t *out, uint64_t n,
+                                hipStream_t st);
+// Copy box [lo, hi) of one plane (x fastest) into out; with packed != null,
+// write the int8 signed distance instead (out is then int8_t*).
+hipError_t launch_gather_box(const uint32_t *plane, const uint32_t *packed, const uint32_t dims[3],
+                             const uint32_t lo[3], const uint32_t hi[3], void *out, hipStream_t st);
+// Number of positions where a != b (n words), added into *count.
+hipError_t launch_count_diff(const uint32_t *a, const uint32_t *b, uint64_t n, unsigned long long *count,
+                             hipStream_t st);
+int apply_blocks_default(const Tuning &t, int device);
+
+}  // namespace dbtsdf

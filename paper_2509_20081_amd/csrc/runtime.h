@@ -1,0 +1,141 @@
+// Host runtime objects behind the C ABI: grids, workspaces, batch contexts.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+struct dbtsdf_kernel_set {
+    std::unique_ptr<dbtsdf::KernelSet> ks;
+};
+
+namespace dbtsdf {
+
+void set_error(const std::string &msg);
+
+// Device copy of one kernel set.
+struct DeviceTables {
+    DevTables t{};
+    std::vector<void *> allocs;
+    dbtsdf_kernel_params params{};
+    ~DeviceTables();
+};
+
+// One call's statistics waiting for delivery.
+struct PendingStat {
+    dbtsdf_scan_stats *dst;
+    uint32_t scan;           // index into the call's scan counters
+    int32_t traffic_grid;    // grid whose traffic counters go on this scan, or -1
+    uint64_t n_in;
+    uint64_t k3;
+};
+
+struct RingSlot {
+    void *host = nullptr;    // pinned: descriptors, then counters copied back
+    size_t bytes = 0;
+    hipEvent_t ev = nullptr;
+    bool busy = false;
+    size_t ctr_off = 0;      // byte offset of the counters inside host
+    std::vector<PendingStat> pend;
+    hipEvent_t pe[3] = {nullptr, nullptr, nullptr};  // call start, apply start, apply/call end
+    int prof = 0;            // 0: none, 1: whole call, 2: call and apply kernel
+};
+
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+};
+
+// Stream-ordered scratch for integrate calls (one per grid for the plain
+// entry point, one per batch context).
+struct Workspace {
+    int device = 0;
+    uint32_t points_cap = 0, scans_cap = 0, grids_cap = 0, items_cap = 0, entries_cap = 0;
+    uint32_t hash_cap = 0;
+    void *d_desc = nullptr;          // Ctrl | CallInfo | DevGrid[grids_cap] | DevScan[scans_cap]
+    size_t desc_bytes = 0;
+    uint4 *rec = nullptr;
+    uint32_t *pslot = nullptr;
+    unsigned long long *hkeys = nullptr;
+    uint32_t *hvals = nullptr;
+    unsigned long long *items = nullptr;
+    uint32_t *item_off = nullptr, *item_cur = nullptr, *entries = nullptr, *survivors = nullptr;
+    unsigned long long *ctr = nullptr;   // scan counters then traffic counters
+    float *staging = nullptr;            // device copy of host points
+    size_t staging_cap = 0;              // floats
+    std::vector<RingSlot> ring;
+    uint32_t ring_next = 0;
+    std::map<std::string, GraphEntry> graphs;
+    uint64_t captures = 0, replays = 0;
+    bool profile = false;
+    double prof_call_ms = 0.0, prof_apply_ms = 0.0;
+    uint64_t prof_calls = 0, prof_apply = 0;
+
+    ~Workspace();
+    hipError_t ensure(uint32_t n_points, uint32_t n_scans, uint32_t n_grids, uint32_t entry_factor,
+                      hipStream_t st);
+    hipError_t ensure_staging(size_t floats, hipStream_t st);
+    RingSlot &next_slot(size_t bytes, std::string *err);
+    void deliver(RingSlot &s);
+    void deliver_all();
+    void drop_graphs();
+    void release();
+};
+
+}  // namespace dbtsdf
+
+struct dbtsdf_grid {
+    dbtsdf_grid_params params{};
+    dbtsdf_kernel_params kparams{};
+    int K = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool owns_planes = true;
+    uint32_t *mask = nullptr;
+    uint32_t *packed = nullptr;
+    uint64_t n_voxels = 0;
+    std::unique_ptr<dbtsdf::DeviceTables> tables;
+    dbtsdf::Tuning tuning;
+    uint32_t *brick_cnt = nullptr;
+    uint32_t *brick_slot = nullptr;
+    uint32_t nb[3] = {0, 0, 0};
+    uint32_t brick_dims[3] = {0, 0, 0};
+    std::unique_ptr<dbtsdf::Workspace> ws;
+    hipEvent_t ev = nullptr;
+    bool poisoned = false;
+    // set by the server, which orders all work on its grids itself: batches
+    // then skip the event handshake with the grid's own stream
+    bool external_order = false;
+};
+
+struct dbtsdf_batch {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool owns_stream = false;
+    bool use_graph = true;
+    std::unique_ptr<dbtsdf::Workspace> ws;
+    hipEvent_t ev = nullptr;
+    std::vector<dbtsdf_grid *> last_grids;
+};
+
+namespace dbtsdf {
+
+struct ScanIn {
+    dbtsdf_grid *grid;
+    const float *pose;     // 16 floats, host
+    const float *points;   // device pointer (after staging)
+    uint64_t n;
+    dbtsdf_scan_stats *stats;
+};
+
+// Validates and enqueues one call (plain or batched) on stream st using ws.
+dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &scans, bool use_graph);
+dbtsdf_status ensure_bricks(dbtsdf_grid *g);
+dbtsdf_status check_hip(hipError_t e, const char *what, dbtsdf_grid *g = nullptr);
+
+}  // namespace dbtsdf

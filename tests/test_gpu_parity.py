@@ -1,0 +1,413 @@
+"""GPU parity: the HIP library against the CPU oracle, bit for bit (tolerance 0).
+
+Every integer the method produces (masks, counters, signs, statistics) must be
+identical; the result is unique because every update commutes (Sec. III-C).
+All calls go through the C ABI via the Python binding.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import brute
+from synth import scene as synth
+from tests import parity as P
+
+pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
+
+
+@pytest.fixture(scope="module")
+def db():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2509_20081_amd as db
+    return db
+
+
+def tiny_scans(seed, K, dims, n_scans=3, n_max=200, nan_frac=0.03):
+    rng = np.random.default_rng(seed)
+    R = (K - 1) // 2
+    c = np.array(dims, dtype=np.float64) / 2.0
+    out = []
+    for _ in range(n_scans):
+        pose = synth.random_pose(rng, c - 2, c + 2)
+        n = int(rng.integers(1, n_max))
+        half = np.array(dims) / 2.0 - R + 1.5
+        pts = synth.random_cloud(rng, n, -half, half)
+        pts[rng.random(n) < nan_frac] = np.nan
+        k = int(rng.integers(0, 5))
+        if k:
+            pts = np.concatenate([pts, pts[rng.integers(0, n, size=k)]])
+        out.append((pose, pts))
+    return out
+
+
+TINY_CASES = [
+    dict(seed=1, K=3, dims=(24, 24, 24), binning="cube26", shadow_r2=1, hit_threshold=1),
+    dict(seed=2, K=5, dims=(40, 33, 29), binning="cube26", shadow_r2=4, hit_threshold=2, hit_max=3),
+    dict(seed=3, K=11, dims=(70, 45, 37), binning="cube26", shadow_r2=9, hit_threshold=5),
+    dict(seed=4, K=11, dims=(64, 64, 64), binning="azel", shadow_r2=9, hit_threshold=3, hit_max=255),
+    dict(seed=5, K=7, dims=(50, 50, 50), binning="azel", bins_az=8, bins_el=5, shadow_r2=6, metric="l1"),
+    dict(seed=6, K=11, dims=(48, 48, 48), binning="cube26", shadow_r2=16, hit_threshold=0, dedup=False),
+    dict(seed=7, K=21, dims=(60, 60, 60), binning="cube26", shadow_r2=25, hit_threshold=2),
+    dict(seed=8, K=37, dims=(80, 70, 75), binning="cube26", shadow_r2=36, hit_threshold=4),
+    dict(seed=9, K=5, dims=(30, 30, 30), binning="cube26", shadow_r2=-1),
+]
+
+TUNINGS = [
+    dict(strategy="brick", brick=(32, 16, 8), block_threads=256),
+    dict(strategy="brick", brick=(16, 16, 8), block_threads=256),
+    dict(strategy="brick", brick=(64, 16, 8), block_threads=512),
+    dict(strategy="brick", brick=(32, 8, 8), block_threads=256, apply_blocks=7),
+    dict(strategy="atomic", block_threads=256),
+]
+
+
+@pytest.mark.parametrize("case", TINY_CASES, ids=lambda c: f"seed{c['seed']}_K{c['K']}_{c['binning']}")
+@pytest.mark.parametrize("tuning", TUNINGS, ids=lambda t: f"{t['strategy']}{t.get('brick', '')}")
+def test_tiny_grids_match_oracle(db, case, tuning):
+    case = dict(case)
+    seed, K, dims = case.pop("seed"), case.pop("K"), case.pop("dims")
+    traffic = tuning["strategy"] == "brick"
+    o, g, _ = P.make_pair(dims, 1.0, (0.0, 0.0, 0.0), count_traffic=traffic, kernel_size=K, **case)
+    g.set_tuning(**tuning)
+    m, p = o.new_grid()
+    for i, (pose, pts) in enumerate(tiny_scans(seed, K, dims)):
+        ref = o.integrate(m, p, pose, pts, count_traffic=traffic)
+        st = g.integrate(pose, P.to_device(pts))
+        g.sync()
+        P.assert_stats_equal(st.as_dict(), ref, traffic=traffic, what=f"scan {i}")
+        gm, gp = P.gpu_planes(g)
+        P.assert_grids_equal(gm, gp, m, p, what=f"scan {i}")
+
+
+def test_hand_worked_scan_on_gpu(db):
+    root = os.path.dirname(os.path.abspath(__file__))
+    gold = json.load(open(os.path.join(root, "golden", "hand_worked_scan.json")))
+    ks = db.KernelSet(**{k: v for k, v in gold["kernel"].items() if k in P.KW_KERNEL})
+    gk = {k: v for k, v in gold["kernel"].items() if k in P.KW_GRID}
+    g = db.Grid(gold["grid"]["dims"], gold["grid"]["voxel_size"], gold["grid"]["origin"], ks, **gk)
+    pose = np.eye(4, dtype=np.float32)
+    pose[:3, 3] = gold["pose_translation"]
+    g.integrate(pose, np.array([gold["point"]], np.float32))
+    g.sync()
+    m, p = g.read_voxels()
+    for (x, y, z), want in gold["expect"]["mask"]:
+        assert m[z, y, x] == want
+    sh = {tuple(v) for v in gold["expect"]["shadow_voxels"]}
+    for z, y, x in np.ndindex(*p.shape):
+        want = gold["expect"]["packed_in_shadow"] if (x, y, z) in sh else gold["expect"]["packed_elsewhere"]
+        assert p[z, y, x] == want
+    d = g.read_distance()
+    for (x, y, z), want in gold["expect"]["distance"]:
+        assert d[z, y, x] == want
+    sub = g.read_distance((7, 7, 7), (10, 9, 8))
+    assert sub.shape == (1, 2, 3) and np.array_equal(sub, d[7:8, 7:9, 7:10])
+
+
+def test_edge_cases(db):
+    dims, K = (32, 32, 32), 5
+    o, g, _ = P.make_pair(dims, 1.0, (0, 0, 0), count_traffic=True, kernel_size=K, shadow_r2=4, hit_threshold=1)
+    m, p = o.new_grid()
+    eye = np.eye(4, dtype=np.float32)
+    eye[:3, 3] = 16.0
+    R = (K - 1) // 2
+    cases = [
+        np.zeros((0, 3), np.float32),                                           # empty scan
+        np.full((7, 3), np.nan, np.float32),                                    # all invalid
+        np.array([[100, 0, 0], [0, -100, 0], [0, 0, 1e30]], np.float32),        # all out of bounds
+        np.zeros((5, 3), np.float32),                                           # zero range
+        np.array([[0.25, 0.25, 0.25]], np.float32),                            # single point next to the sensor
+        np.array([[R - 16.0, 0, 0], [R - 16.0 - 0.01, 0, 0],                   # exactly R from the face / just inside the halo
+                  [dims[0] - 1 - R - 16.0 + 0.99, 0, 0], [dims[0] - R - 16.0, 0, 0]], np.float32),
+        np.repeat(np.array([[3.3, -2.2, 1.1]], np.float32), 50, axis=0),       # 50 returns in one voxel
+        np.array([[np.inf, 0, 0], [1, np.nan, 0], [2, 2, 2], [-2, -2, -2]], np.float32),
+    ]
+    for i, pts in enumerate(cases):
+        ref = o.integrate(m, p, eye, pts, count_traffic=True)
+        st = g.integrate(eye, P.to_device(pts) if len(pts) else pts)
+        g.sync()
+        P.assert_stats_equal(st.as_dict(), ref, traffic=True, what=f"case {i}")
+        gm, gp = P.gpu_planes(g)
+        P.assert_grids_equal(gm, gp, m, p, what=f"case {i}")
+
+
+def test_host_points_and_permutation(db):
+    """Host (numpy) points equal device points; any permutation of a scan gives the same grid."""
+    dims, K = (64, 64, 48), 11
+    pose, pts = next(synth.config_scans(1, 0, [0]))
+    pts = pts[:4000]
+    pose = pose.copy()
+    pose[:3, 3] = [32 * 0.1 + 0.03, 32 * 0.1 - 0.07, 24 * 0.1]
+    grids = []
+    rng = np.random.default_rng(0)
+    for order, host in ((None, False), (rng.permutation(len(pts)), False), (rng.permutation(len(pts)), True)):
+        o, g, _ = P.make_pair(dims, 0.1, (0, 0, 0), kernel_size=K, dedup=False)
+        q = pts if order is None else pts[order]
+        g.integrate(pose, q if host else P.to_device(q))
+        g.sync()
+        grids.append(P.gpu_planes(g))
+    m, p = o.new_grid()
+    o.integrate(m, p, pose, pts)
+    for gm, gp in grids:
+        P.assert_grids_equal(gm, gp, m, p, what="permutation")
+
+
+def _config_grid_pair(db, cfg, count_traffic=False):
+    gdef = synth.config_grid(cfg)
+    return P.make_pair(gdef["dims"], gdef["voxel_size"], gdef["origin"], count_traffic=count_traffic,
+                       **synth.KERNEL_DEFAULTS), gdef
+
+
+def test_config1_full_grid(db):
+    """16x1024 scan into 256^3 @ 0.1 m: whole grid against the oracle."""
+    (o, g, _), gdef = _config_grid_pair(db, 1, count_traffic=True)
+    m, p = o.new_grid()
+    for pose, pts in synth.config_scans(1, 0, [0]):
+        ref = o.integrate(m, p, pose, pts, count_traffic=True)
+        st = g.integrate(pose, P.to_device(pts))
+        g.sync()
+        P.assert_stats_equal(st.as_dict(), ref, traffic=True, what="c1")
+    gm, gp = P.gpu_planes(g)
+    P.assert_grids_equal(gm, gp, m, p, what="c1")
+    assert ref["n_integrated"] > 5000
+
+
+def test_config2_full_grid_three_scans(db):
+    """1024x1024x256 @ 0.05 m, 64x1024 scans along the trajectory: whole grid after 3 scans."""
+    (o, g, _), gdef = _config_grid_pair(db, 2, count_traffic=True)
+    m, p = o.new_grid()
+    for k, (pose, pts) in enumerate(synth.config_scans(2, 0, [0, 1, 2])):
+        ref = o.integrate(m, p, pose, pts, count_traffic=True)
+        st = g.integrate(pose, P.to_device(pts))
+        g.sync()
+        P.assert_stats_equal(st.as_dict(), ref, traffic=True, what=f"c2 scan {k}")
+    gm, gp = P.gpu_planes(g)
+    P.assert_grids_equal(gm, gp, m, p, what="c2")
+
+
+def _invariants_torch(g, T, H):
+    import torch
+    m, pk = g.mask_tensor, g.packed_tensor
+    assert int(((m & (m + 1)) != 0).sum()) == 0
+    assert int((pk & 0x7FFF0000).sum()) == 0
+    h = pk & 0xFFFF
+    assert int((h > H).sum()) == 0
+    occ = pk >= 0                                  # bit 31 clear
+    want = (h >= T) if (1 <= T <= H) else torch.zeros_like(occ)
+    assert bool(torch.equal(occ, want))
+
+
+def test_config2_bench_launch_sampled(db):
+    """The plain form as the benchmark runs it (default tuning, device points), 24 scans;
+    sampled voxels computed one by one from the closed form, plus whole-grid invariants."""
+    (o, g, _), gdef = _config_grid_pair(db, 2)
+    dims, K = gdef["dims"], 11
+    integrated = []
+    for pose, pts in synth.config_scans(2, 0, range(24)):
+        g.integrate(pose, P.to_device(pts))
+        integrated.append(P.integrated_of(o, pose, pts, dims, K))
+    g.sync()
+    rng = np.random.default_rng(2)
+    smp = P.sample_voxels(rng, dims, K, integrated)
+    sm, sp = brute.sampled_voxels(smp, dims, K, integrated, 9, 5, 65535)
+    gm, gp = P.gpu_planes(g)
+    P.assert_grids_equal(gm[smp[:, 2], smp[:, 1], smp[:, 0]], gp[smp[:, 2], smp[:, 1], smp[:, 0]], sm, sp,
+                         what="c2 sampled")
+    _invariants_torch(g, 5, 65535)
+
+
+def test_config3_sampled(db):
+    """2048x2048x512 @ 0.02 m (2^31 voxels, 17 GB): two 128x2048 scans, sampled voxels."""
+    import torch
+    gdef = synth.config_grid(3)
+    ks = db.KernelSet(kernel_size=11, binning="cube26", shadow_r2=9)
+    g = db.Grid(gdef["dims"], gdef["voxel_size"], gdef["origin"], ks, planes="torch")
+    dims, K = gdef["dims"], 11
+    integrated = []
+    for pose, pts in synth.config_scans(3, 0, [0, 1]):
+        g.integrate(pose, P.to_device(pts))
+        integrated.append(_front_end_big(pose, pts, gdef, K))
+    g.sync()
+    rng = np.random.default_rng(3)
+    smp = P.sample_voxels(rng, dims, K, integrated, n_near=2000, n_any=500)
+    sm, sp = brute.sampled_voxels(smp, dims, K, integrated, 9, 5, 65535)
+    idx = torch.from_numpy(smp[:, 2] * dims[1] * dims[0] + smp[:, 1] * dims[0] + smp[:, 0]).cuda()
+    gm = g.mask_tensor.view(-1)[idx].cpu().numpy().view(np.uint32)
+    gp = g.packed_tensor.view(-1)[idx].cpu().numpy().view(np.uint32)
+    P.assert_grids_equal(gm, gp, sm, sp, what="c3 sampled")
+    _invariants_torch(g, 5, 65535)
+    g.close()
+    del g
+    torch.cuda.empty_cache()
+
+
+def centred(cfg, map_id, side):
+    """A side^3 grid with the same centre and voxel size as the configuration's map."""
+    gdef = synth.config_grid(cfg, map_id)
+    vs = gdef["voxel_size"]
+    org = tuple(float(np.float32(o + (d - side) * vs / 2.0)) for o, d in zip(gdef["origin"], gdef["dims"]))
+    return (side, side, side), vs, org
+
+
+def _front_end_big(pose, pts, gdef, K):
+    vox, bins, status = brute.front_end(pose, pts, gdef["dims"], gdef["voxel_size"], gdef["origin"], K)
+    keep = brute.survivors(vox, status, gdef["dims"])
+    return vox[keep], bins[keep]
+
+
+def test_batch_and_graph_replays_equal_plain(db):
+    """Batched launches (with and without graphs, same grid several times, host and device
+    points) equal the plain per-scan form and the oracle; every graph replay is checked."""
+    import torch
+    maps = []
+    for mid in range(3):
+        side = min(synth.config_grid(4, mid)["dims"][0], 256)
+        dims, vs, org = centred(4, mid, side)
+        maps.append((dims, vs, org, list(synth.config_scans(4, mid, range(4)))))
+    plain, batched_g, batched_n = [], [], []
+    for dims, vs, org, scans in maps:
+        _, g, _ = P.make_pair(dims, vs, org, **synth.KERNEL_DEFAULTS)
+        for pose, pts in scans:
+            g.integrate(pose, P.to_device(pts))
+        g.sync()
+        plain.append(P.gpu_planes(g))
+    for use_graph, out in ((True, batched_g), (False, batched_n)):
+        b = db.Batch(use_graph=use_graph)
+        grids = [P.make_pair(d, vs, org, **synth.KERNEL_DEFAULTS)[1] for d, vs, org, _ in maps]
+        for rnd in range(4):              # 4 batches: one scan of every map each, plus a repeat
+            items = [(grids[i], maps[i][3][rnd][0], P.to_device(maps[i][3][rnd][1])) for i in range(3)]
+            if rnd == 3:                  # host points path
+                items = [(g_, pose, pts.cpu().numpy()) for g_, pose, pts in items]
+            b.integrate(items)
+            b.sync()
+            torch.cuda.synchronize()
+            _ = torch.ones(1024, device="cuda").sum().item()   # unrelated eager work between replays
+        out.extend(P.gpu_planes(g_) for g_ in grids)
+        if use_graph:
+            caps, reps = b.graph_stats()
+            assert reps == 4 and caps <= 2
+    for i in range(3):
+        P.assert_grids_equal(*batched_g[i], *plain[i], what=f"graph batch map {i}")
+        P.assert_grids_equal(*batched_n[i], *plain[i], what=f"batch map {i}")
+    # one more: all scans of all maps in a single launch, against the oracle
+    b = db.Batch(use_graph=True)
+    pairs = [P.make_pair(d, vs, org, **synth.KERNEL_DEFAULTS) for d, vs, org, _ in maps]
+    items = [(pairs[i][1], pose, P.to_device(pts)) for i in range(3) for pose, pts in maps[i][3]]
+    stats = b.integrate(items)
+    b.sync()
+    k = 0
+    for i, (o, g, _) in enumerate(pairs):
+        m, p = o.new_grid()
+        for pose, pts in maps[i][3]:
+            ref = o.integrate(m, p, pose, pts)
+            P.assert_stats_equal(stats[k].as_dict(), ref, what=f"batch stats {k}")
+            k += 1
+        P.assert_grids_equal(*P.gpu_planes(g), m, p, what=f"single-launch batch map {i}")
+
+
+def test_autotune_keeps_result_identical(db):
+    (o, g, _), gdef = _config_grid_pair(db, 1)
+    scans = [(pose, P.to_device(pts)) for pose, pts in synth.config_scans(1, 0, [0])]
+    tun = g.autotune(scans, True)
+    assert tun["strategy"] in ("brick", "atomic")
+    m, p = o.new_grid()
+    for pose, pts in synth.config_scans(1, 0, [0]):
+        o.integrate(m, p, pose, pts)
+        g.integrate(pose, P.to_device(pts))
+    g.sync()
+    P.assert_grids_equal(*P.gpu_planes(g), m, p, what="tuned grid")
+
+
+def test_server_mix_equals_alone(db):
+    """Scans of several robots served concurrently equal each robot's scans integrated alone."""
+    from paper_2509_20081_amd.serve import Server
+    ks = db.KernelSet(kernel_size=11, binning="cube26", shadow_r2=9)
+    robots = []
+    for rid in range(4):
+        dims, vs, org = centred(5, rid, 192)
+        robots.append((dict(voxel_size=vs, origin=org), list(synth.config_scans(5, rid, range(5)))))
+    srv = Server(n_streams=2, max_batch_scans=8)
+    ids = [srv.add_map(dims, r[0]["voxel_size"], r[0]["origin"], ks) for r in robots]
+    for k in range(5):
+        for rid, (gdef, scans) in enumerate(robots):
+            srv.submit(ids[rid], scans[k][0], scans[k][1])
+    srv.drain()
+    done = srv.poll(100)
+    assert len(done) == 20 and all(c["status"] == 0 for c in done)
+    assert all(c["t_done_ns"] >= c["t_launch_ns"] >= c["t_arrival_ns"] for c in done)
+    for rid, (gdef, scans) in enumerate(robots):
+        alone = db.Grid(dims, gdef["voxel_size"], gdef["origin"], ks)
+        for pose, pts in scans:
+            alone.integrate(pose, pts)
+        alone.sync()
+        a = alone.read_voxels()
+        view = srv.map_grid(ids[rid], dims, ks)
+        s = view.read_voxels()
+        P.assert_grids_equal(s[0], s[1], a[0], a[1], what=f"robot {rid}")
+    srv.close()
+
+
+def test_server_admission_by_memory(db):
+    from paper_2509_20081_amd.serve import Server
+    ks = db.KernelSet(kernel_size=11)
+    per_map = 128 ** 3 * 8
+    srv = Server(memory_budget=int(2.5 * per_map))
+    a = srv.try_add_map((128,) * 3, 0.05, (0, 0, 0), ks)
+    b = srv.try_add_map((128,) * 3, 0.05, (0, 0, 0), ks)
+    c = srv.try_add_map((128,) * 3, 0.05, (0, 0, 0), ks)
+    assert a is not None and b is not None and c is None
+    srv.remove_map(a)
+    assert srv.try_add_map((128,) * 3, 0.05, (0, 0, 0), ks) is not None
+    adm, bud = srv.memory()
+    assert adm == 2 * per_map and bud == int(2.5 * per_map)
+    srv.close()
+
+
+def test_readout_and_restore(db):
+    dims = (40, 40, 40)
+    o, g, ks = P.make_pair(dims, 1.0, (0, 0, 0), kernel_size=5, shadow_r2=4, hit_threshold=2)
+    for pose, pts in tiny_scans(11, 5, dims):
+        g.integrate(pose, P.to_device(pts))
+    g.sync()
+    m, p = g.read_voxels()
+    gm, gp = P.gpu_planes(g)
+    assert np.array_equal(m, gm) and np.array_equal(p, gp)
+    d = g.read_distance()
+    pc = np.vectorize(lambda v: bin(int(v)).count("1"))(m)
+    assert np.array_equal(d, np.where(p >> 31, pc, -pc))
+    g2 = db.Grid(dims, 1.0, (0, 0, 0), ks, hit_threshold=2)
+    g2.write_voxels(m, p)
+    m2, p2 = g2.read_voxels()
+    assert np.array_equal(m, m2) and np.array_equal(p, p2)
+    bad = p.copy()
+    bad.flat[0] = 0x00010000
+    with pytest.raises(db.DbtsdfError):
+        g2.write_voxels(m, bad)
+    bad = m.copy()
+    bad.flat[0] = 0x5
+    with pytest.raises(db.DbtsdfError):
+        g2.write_voxels(bad, p)
+    with pytest.raises(db.DbtsdfError):
+        g.read_voxels((0, 0, 0), (41, 1, 1))
+
+
+def test_argument_errors_leave_grid_unchanged(db):
+    dims = (24, 24, 24)
+    o, g, ks = P.make_pair(dims, 1.0, (0, 0, 0), kernel_size=5)
+    pose = np.eye(4, dtype=np.float32)
+    pose[0, 3] = np.nan
+    with pytest.raises(db.DbtsdfError):
+        g.integrate(pose, np.ones((3, 3), np.float32))
+    with pytest.raises(db.DbtsdfError):
+        db.Grid((4, 24, 24), 1.0, (0, 0, 0), ks)
+    with pytest.raises(db.DbtsdfError):
+        db.Grid(dims, 0.0, (0, 0, 0), ks)
+    with pytest.raises(db.DbtsdfError):
+        db.Grid(dims, 1.0, (0, 0, 0), ks, hit_max=0)
+    with pytest.raises(db.DbtsdfError):
+        g.set_tuning(strategy="brick", brick=(48, 16, 8))
+    gm, gp = P.gpu_planes(g)
+    assert np.all(gm == 0xFFFFFFFF) and np.all(gp == 0x80000000)

@@ -1,0 +1,95 @@
+"""Host-side checks of the C ABI library (no GPU needed).
+
+The library must load, export every entry point its header declares, and build
+kernel tables that equal, byte for byte, the ones the oracle builds on its own
+from the paper's definitions (Sec. III-B, eqs. 2-3).
+"""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.oracle import Oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dbtsdf.h")
+
+
+@pytest.fixture(scope="module")
+def db():
+    import paper_2509_20081_amd as db
+    from paper_2509_20081_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2509_20081_amd import build
+        build.build()
+    return db
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dbtsdf_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(db):
+    from paper_2509_20081_amd import _lib
+    names = declared_functions()
+    assert len(names) >= 30
+    h = C.CDLL(_lib.LIB_PATH)
+    missing = [n for n in names if not hasattr(h, n)]
+    assert not missing
+    # and the binding declares a signature for each of them
+    assert set(names) <= set(_lib.SIGNATURES)
+
+
+def test_status_strings(db):
+    from paper_2509_20081_amd import _lib
+    lib = _lib.lib()
+    for s in range(7):
+        assert lib.dbtsdf_status_string(s)
+    assert lib.dbtsdf_status_string(99) == b"unknown status"
+
+
+def test_grid_bytes_eq1(db):
+    """eq. (1): M = Nx * Ny * Nz * 8 bytes."""
+    assert db.grid_bytes((1024, 1024, 256)) == 1024 * 1024 * 256 * 8
+    assert db.grid_bytes((2048, 2048, 512)) == 2 ** 31 * 8
+
+
+@pytest.mark.parametrize("K,binning,r2,metric", [
+    (3, "cube26", 1, "l2"), (5, "cube26", 4, "l2"), (11, "cube26", 9, "l2"), (21, "cube26", 16, "l2"),
+    (11, "azel", 9, "l2"), (5, "azel", 2, "l1"), (7, "cube26", -1, "l2"), (37, "cube26", 25, "l2"),
+])
+def test_kernel_tables_match_oracle(db, K, binning, r2, metric):
+    ks = db.KernelSet(kernel_size=K, binning=binning, shadow_r2=r2, metric=metric)
+    m, s, d = ks.export()
+    o = Oracle(dims=(K, K, K), voxel_size=1.0, kernel_size=K, binning=binning, shadow_r2=r2, metric=metric)
+    om, osh, od = o.tables()
+    assert m.tobytes() == om.tobytes()
+    assert s.tobytes() == osh.tobytes()
+    assert np.allclose(d, od, rtol=0, atol=1e-15)
+
+
+def test_host_bins_match_oracle(db):
+    rng = np.random.default_rng(4)
+    dirs = rng.normal(size=(3000, 3)).astype(np.float32)
+    dirs[:50] = np.round(dirs[:50])          # axis-aligned and diagonal cases
+    dirs[50:60, :2] = 0
+    for binning in ("cube26", "azel"):
+        ks = db.KernelSet(kernel_size=5, binning=binning)
+        o = Oracle(dims=(5, 5, 5), voxel_size=1.0, kernel_size=5, binning=binning)
+        for v in dirs:
+            if not np.any(v):
+                continue
+            assert ks.bin(v) == o.bin(v)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(kernel_size=4), dict(kernel_size=1), dict(kernel_size=39), dict(kernel_size=23, metric="l1"),
+    dict(binning="azel", bins_az=41), dict(binning="azel", bins_az=0),
+])
+def test_kernel_set_validation(db, kw):
+    with pytest.raises(db.DbtsdfError):
+        db.KernelSet(**kw)
