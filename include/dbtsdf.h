@@ -108,9 +108,10 @@ typedef struct {
  * Per-scan statistics. voxel_updates = n_integrated * K^3 (one eq. 4 AND per
  * kernel cell); shadow_updates = sum over integrated returns of |S(b)|.
  * u_mask / c_mask / u_shadow are only filled with DBTSDF_COUNT_TRAFFIC: the
- * number of distinct mask words in the union of the integrated neighbourhoods,
- * of those whose value changed, and of distinct words in the union of the
- * shadows. In a batch call they are per grid and reported on the first scan of
+ * number of distinct mask words in the union of the integrated neighbourhoods
+ * (cells whose eq. 3 mask is all ones, which the AND leaves unchanged, are not
+ * counted; they only occur for K = 37), of those whose value changed, and of
+ * distinct words in the union of the shadows. In a batch call they are per grid and reported on the first scan of
  * that grid in the batch (zero on the others).
  */
 typedef struct {

@@ -71,7 +71,7 @@ typedef struct {
 typedef struct {
     uint64_t n_in, n_invalid, n_out_of_bounds, n_duplicate, n_integrated;
     uint64_t voxel_updates, shadow_updates;
-    uint64_t u_mask, c_mask, u_shadow; /* unique mask words touched / changed, unique shadow words */
+    uint64_t u_mask, c_mask, u_shadow; /* unique mask words read (kernel mask not all ones) / changed, unique shadow words */
 } orc_stats;
 
 typedef struct {
@@ -500,7 +500,9 @@ int orc_integrate(orc_ctx *c, uint32_t *mask, uint32_t *packed, const float pose
                     uint32_t g = mask[u];
                     uint32_t g2 = g & c->mask_k[cell];
                     s.voxel_updates++;
-                    if (count_traffic)
+                    /* a word whose kernel mask is all ones is left as it is by
+                       the AND and need not be read: only the others count */
+                    if (count_traffic && c->mask_k[cell] != 0xFFFFFFFFu)
                         bm_set(c->bm_touch, u);
                     if (g2 != g) {
                         mask[u] = g2;
