@@ -136,18 +136,22 @@ typedef enum {
 
 /*
  * Launch tuning of a grid. With DBTSDF_STRATEGY_BRICK, (brick, block_threads)
- * must be one of the compiled shapes: 32x16x8 (256 or 512 threads),
- * 32x16x16 (256, 512), 32x32x16 (512), 64x16x8 (256, 512), 32x8x8 (256),
- * 16x16x16 (256), 16x16x8 (256); any kernel size works with any shape.
- * apply_blocks = workgroups of the persistent apply kernel (0 = automatic).
- * With DBTSDF_STRATEGY_ATOMIC the brick is ignored. Any valid tuning gives
- * bit-identical grids.
+ * must be one of the compiled shapes: 16x8x8, 32x8x8, 64x8x8, 16x16x8,
+ * 32x16x8 (256 threads), 32x16x8, 64x16x8, 32x16x16 (512 threads); a shape is
+ * rejected when its LDS tiles cannot hold the kernel radius (only large K on
+ * the largest shapes). apply_blocks = workgroups of the persistent apply
+ * kernel (0 = as many as are resident at once).
+ * chunk = most listed points one apply work unit takes from a brick; bricks
+ * with more are split over several work units that merge with atomics
+ * (0 = default 64, 0xFFFFFFFF = never split). With DBTSDF_STRATEGY_ATOMIC the
+ * brick is ignored. Any valid tuning gives bit-identical grids.
  */
 typedef struct {
     uint32_t strategy;
     uint32_t brick[3];
     uint32_t block_threads;
     uint32_t apply_blocks;
+    uint32_t chunk;
 } dbtsdf_tuning;
 
 typedef struct dbtsdf_kernel_set dbtsdf_kernel_set;

@@ -217,10 +217,11 @@ class Grid:
         t = L.Tuning()
         L.check(L.lib().dbtsdf_get_tuning(self._h, C.byref(t)), "get_tuning")
         return dict(strategy=_STRATEGY_NAME[t.strategy], brick=tuple(t.brick), block_threads=t.block_threads,
-                    apply_blocks=t.apply_blocks)
+                    apply_blocks=t.apply_blocks, chunk=t.chunk)
 
-    def set_tuning(self, strategy="brick", brick=(32, 16, 8), block_threads=256, apply_blocks=0) -> None:
-        t = L.Tuning(_STRATEGY[strategy], (C.c_uint32 * 3)(*brick), block_threads, apply_blocks)
+    def set_tuning(self, strategy="brick", brick=(32, 16, 8), block_threads=256, apply_blocks=0, chunk=0) -> None:
+        t = L.Tuning(_STRATEGY[strategy], (C.c_uint32 * 3)(*brick), block_threads, apply_blocks,
+                     0xFFFFFFFF if chunk is None else chunk)
         L.check(L.lib().dbtsdf_set_tuning(self._h, C.byref(t)), "set_tuning")
 
     def autotune(self, scans, device_points) -> dict:

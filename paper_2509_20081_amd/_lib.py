@@ -40,7 +40,7 @@ class ScanStats(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("strategy", C.c_uint32), ("brick", C.c_uint32 * 3), ("block_threads", C.c_uint32),
-                ("apply_blocks", C.c_uint32)]
+                ("apply_blocks", C.c_uint32), ("chunk", C.c_uint32)]
 
 
 class ServerConfig(C.Structure):

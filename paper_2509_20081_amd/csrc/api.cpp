@@ -69,6 +69,7 @@ static dbtsdf_status make_device_tables(const KernelSet &ks, std::unique_ptr<Dev
     t.n_bins = ks.n_bins;
     t.K = ks.K;
     t.R = ks.R;
+    t.shadow_r2 = ks.p.shadow_r2;
     t.binning = ks.p.binning;
     t.bins_az = ks.p.bins_az;
     t.bins_el = ks.p.bins_el;
@@ -88,7 +89,7 @@ void Workspace::drop_graphs() {
 
 void Workspace::release() {
     drop_graphs();
-    void *ptrs[] = {d_desc, rec, pslot, hkeys, hvals, items, item_off, item_cur, entries, survivors, ctr, staging};
+    void *ptrs[] = {d_desc, rec, pslot, hkeys, hvals, items, item_off, item_cnt, entries, survivors, ctr, staging, rank, work};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     d_desc = nullptr;
@@ -97,7 +98,8 @@ void Workspace::release() {
     hkeys = nullptr;
     hvals = nullptr;
     items = nullptr;
-    item_off = item_cur = entries = survivors = nullptr;
+    item_off = item_cnt = entries = survivors = rank = nullptr;
+    work = nullptr;
     ctr = nullptr;
     staging = nullptr;
     staging_cap = 0;
@@ -153,8 +155,10 @@ hipError_t Workspace::ensure(uint32_t n_points, uint32_t n_scans, uint32_t n_gri
         {(void **)&hvals, (size_t)hash_cap * 4},
         {(void **)&items, (size_t)items_cap * 8},
         {(void **)&item_off, (size_t)items_cap * 4},
-        {(void **)&item_cur, (size_t)items_cap * 4},
+        {(void **)&item_cnt, (size_t)items_cap * 4},
         {(void **)&entries, (size_t)entries_cap * 4},
+        {(void **)&rank, (size_t)entries_cap * 4},
+        {(void **)&work, ((size_t)items_cap + entries_cap) * sizeof(uint2)},
         {(void **)&survivors, (size_t)points_cap * 4},
         {(void **)&ctr, ctr_words * 8},
     };
@@ -346,7 +350,7 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
     }
     Tuning tun = g0->tuning;
     if (traffic) tun.strategy = DBTSDF_STRATEGY_BRICK;  // unique-word counts come from the brick merge
-    if (tun.apply_blocks == 0) tun.apply_blocks = (uint32_t)apply_blocks_default(tun, g0->device);
+    if (tun.apply_blocks == 0) tun.apply_blocks = (uint32_t)apply_blocks_default(tun, g0->K, g0->device);
     for (dbtsdf_grid *g : grids) {
         dbtsdf_status s = ensure_bricks(g);
         if (s != DBTSDF_OK) return s;
@@ -438,7 +442,9 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
     a.hvals = ws.hvals;
     a.items = ws.items;
     a.item_off = ws.item_off;
-    a.item_cur = ws.item_cur;
+    a.item_cnt = ws.item_cnt;
+    a.rank = ws.rank;
+    a.work = ws.work;
     a.entries = ws.entries;
     a.survivors = ws.survivors;
     a.scan_ctr = ws.ctr;
@@ -446,6 +452,17 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
     a.items_cap = ws.items_cap;
     a.entries_cap = ws.entries_cap;
     a.count_traffic = traffic ? 1u : 0u;
+    {
+        const uint32_t bd[3] = {tun.bx, tun.by, tun.bz};
+        for (int k = 0; k < 3; ++k) a.span[k] = 1u + (2u * (uint32_t)R + bd[k] - 1u) / bd[k];
+    }
+    // exact unique-word counts need every brick merged by one work unit
+    a.chunk = traffic ? 0u : tun.chunk;
+    a.small_offsets = 1u;
+    for (dbtsdf_grid *g : grids) {
+        const uint64_t span = (uint64_t)R * (1ull + g->params.dims[0] + (uint64_t)g->params.dims[0] * g->params.dims[1]);
+        if (span >= (1ull << 31)) a.small_offsets = 0u;
+    }
 
     slot.prof = 0;
     if (ws.profile) {
@@ -647,6 +664,7 @@ dbtsdf_status dbtsdf_get_tuning(const dbtsdf_grid *g, dbtsdf_tuning *out) {
     out->brick[2] = g->tuning.bz;
     out->block_threads = g->tuning.threads;
     out->apply_blocks = g->tuning.apply_blocks;
+    out->chunk = g->tuning.chunk ? g->tuning.chunk : 0xFFFFFFFFu;
     return DBTSDF_OK;
 }
 
@@ -659,6 +677,7 @@ dbtsdf_status dbtsdf_set_tuning(dbtsdf_grid *g, const dbtsdf_tuning *t) {
     n.bz = t->brick[2];
     n.threads = t->block_threads;
     n.apply_blocks = t->apply_blocks;
+    n.chunk = t->chunk == 0 ? Tuning{}.chunk : (t->chunk == 0xFFFFFFFFu ? 0u : t->chunk);
     if (n.strategy == DBTSDF_STRATEGY_ATOMIC) {
         if (n.bx == 0) {
             n.bx = g->tuning.bx;

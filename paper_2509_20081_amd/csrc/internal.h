@@ -55,6 +55,7 @@ struct DevTables {
     uint32_t n_q;
     uint32_t n_bins;
     int32_t K, R;
+    int32_t shadow_r2;       // r_s^2, negative = no shadow
     uint32_t binning, bins_az, bins_el, metric;
 };
 
@@ -87,10 +88,10 @@ enum { SC_INVALID = 0, SC_OOB, SC_DUP, SC_INT, SC_SHADOW, SC_N };
 enum { TC_UMASK = 0, TC_CMASK, TC_USHADOW, TC_N };
 
 struct Ctrl {
-    uint32_t n_active;
-    uint32_t total_entries;
-    uint32_t n_survivors;
-    uint32_t pad;
+    uint32_t n_active;       // bricks touched this call (work items of the bucketing)
+    uint32_t total_entries;  // (point, brick) pairs listed
+    uint32_t n_survivors;    // integrated points (atomic strategy)
+    uint32_t n_work;         // apply work units (bricks, heavy ones split)
 };
 
 // Sizes of the current call, read by the kernels from device memory so that a
@@ -111,9 +112,11 @@ struct PipeArgs {
     unsigned long long *hkeys;
     uint32_t *hvals;
     unsigned long long *items;  // active (grid << 32 | brick)
-    uint32_t *item_off;
-    uint32_t *item_cur;
-    uint32_t *entries;       // point indices per work item
+    uint32_t *item_off;      // first entry of each active brick
+    uint32_t *item_cnt;      // entries of each active brick
+    uint32_t *entries;       // point indices, grouped by brick
+    uint32_t *rank;          // per (point, brick) pair: position in the brick's list
+    uint2 *work;             // apply work units: (item, sub | split << 31)
     uint32_t *survivors;     // compacted survivor list (atomic strategy)
     unsigned long long *scan_ctr;     // n_scans * SC_N
     unsigned long long *traffic_ctr;  // n_grids * TC_N
@@ -121,14 +124,18 @@ struct PipeArgs {
     uint32_t items_cap;
     uint32_t entries_cap;
     uint32_t count_traffic;
+    uint32_t span[3];        // most bricks a K^3 cube can touch per axis
+    uint32_t chunk;          // listed points per apply work unit (0 = never split a brick)
+    uint32_t small_offsets;  // every grid: R * (1 + Nx + Nx * Ny) < 2^31 (cell offsets fit int32)
 };
 
 // ---------------------------------------------------------- launch config ---
 struct Tuning {
     uint32_t strategy = DBTSDF_STRATEGY_BRICK;
-    uint32_t bx = 32, by = 16, bz = 8;
+    uint32_t bx = 32, by = 8, bz = 8;
     uint32_t threads = 256;
     uint32_t apply_blocks = 0;
+    uint32_t chunk = 64;     // listed points per apply work unit, 0 = never split
 };
 
 bool tuning_supported(const Tuning &t, int K);
@@ -149,6 +156,6 @@ hipError_t launch_gather_box(const uint32_t *plane, const uint32_t *packed, cons
 // Number of positions where a != b (n words), added into *count.
 hipError_t launch_count_diff(const uint32_t *a, const uint32_t *b, uint64_t n, unsigned long long *count,
                              hipStream_t st);
-int apply_blocks_default(const Tuning &t, int device);
+int apply_blocks_default(const Tuning &t, int K, int device);
 
 }  // namespace dbtsdf

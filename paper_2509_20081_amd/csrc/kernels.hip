@@ -8,11 +8,13 @@
 //              voxelisation, K^3 bounds test, direction bin (eq. 2); the
 //              first-return-per-voxel rule (Sec. IV-B) by an atomicMin of the
 //              point index into a hash table keyed by (scan, voxel)
-//   k_select   per point: survivor test; bucketing of survivors by the grid
-//              bricks their K^3 cube touches (counting pass, work-item claim)
-//   k_offsets  exclusive scan of the per-brick counts -> list offsets
-//   k_fill     per survivor: append its index to each touched brick's list;
-//              release the hash slots
+//   k_select   per (point, brick) pair: survivor test; bucketing of survivors
+//              by the grid bricks their K^3 cube touches (the counter's
+//              atomicAdd gives the pair's rank in the brick's list)
+//   k_offsets  exclusive scan of the per-brick counts -> list offsets; heavy
+//              bricks are split into several apply work units
+//   k_fill     per pair: write the point index at its rank; release the
+//              hash slots
 //   k_apply    persistent: one workgroup owns one brick at a time in LDS,
 //              stamps the eq. 3 masks of every listed point with LDS atomicAnd
 //              (eq. 4) and counts shadow hits with LDS atomicAdd, then merges
@@ -176,6 +178,7 @@ __device__ __forceinline__ uint32_t front_end(const DevScan &s, const DevGrid &g
 
 // ================================================================ passes ===
 constexpr int kPtThreads = 256;
+constexpr int kSelThreads = 1024;   // one claim atomic per block of pairs
 
 __global__ void k_reset(PipeArgs a, const CallInfo *info) {
     const uint32_t n_sc = info->n_scans * SC_N, n_tc = info->n_grids * TC_N;
@@ -188,48 +191,35 @@ __global__ void k_reset(PipeArgs a, const CallInfo *info) {
 
 __global__ __launch_bounds__(kPtThreads) void k_front(PipeArgs a, const CallInfo *info) {
     const uint32_t n = info->n_points, n_scans = info->n_scans;
-    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
-        const uint32_t i = base + threadIdx.x;
-        const bool live = i < n;
-        uint32_t s = 0, st = kStInvalid;
-        if (live) {
-            s = find_scan(a.scans, n_scans, i);
-            const DevScan &sc = a.scans[s];
-            const DevGrid &g = a.grids[sc.grid];
-            const uint32_t j = i - sc.begin;
-            const float px = sc.pts[3 * (size_t)j + 0];
-            const float py = sc.pts[3 * (size_t)j + 1];
-            const float pz = sc.pts[3 * (size_t)j + 2];
-            int vx = 0, vy = 0, vz = 0, bin = 0;
-            st = front_end(sc, g, a.tab, px, py, pz, vx, vy, vz, bin);
-            uint32_t slot = kNoSlot;
-            if (st == kStOk && sc.dedup) {
-                const unsigned long long lin =
-                    (unsigned long long)vx + (unsigned long long)g.nx * ((unsigned long long)vy + (unsigned long long)g.ny * (unsigned long long)vz);
-                const unsigned long long key = ((unsigned long long)s << kVoxelKeyBits) | lin;
-                uint32_t h = hash_of(key) & a.hash_mask;
-                for (;;) {  // the table holds >= 2x the call's points, so an empty slot exists
-                    const unsigned long long prev = atomicCAS(&a.hkeys[h], kHashEmpty, key);
-                    if (prev == kHashEmpty || prev == key) {
-                        atomicMin(&a.hvals[h], i);
-                        break;
-                    }
-                    h = (h + 1) & a.hash_mask;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t s = find_scan(a.scans, n_scans, i);
+        const DevScan &sc = a.scans[s];
+        const DevGrid &g = a.grids[sc.grid];
+        const uint32_t j = i - sc.begin;
+        const float px = sc.pts[3 * (size_t)j + 0];
+        const float py = sc.pts[3 * (size_t)j + 1];
+        const float pz = sc.pts[3 * (size_t)j + 2];
+        int vx = 0, vy = 0, vz = 0, bin = 0;
+        const uint32_t st = front_end(sc, g, a.tab, px, py, pz, vx, vy, vz, bin);
+        uint32_t slot = kNoSlot;
+        if (st == kStOk && sc.dedup) {
+            const unsigned long long lin = (unsigned long long)vx +
+                (unsigned long long)g.nx * ((unsigned long long)vy + (unsigned long long)g.ny * (unsigned long long)vz);
+            const unsigned long long key = ((unsigned long long)s << kVoxelKeyBits) | lin;
+            uint32_t h = hash_of(key) & a.hash_mask;
+            for (;;) {  // the table holds >= 2x the call's points, so an empty slot exists
+                const unsigned long long prev = atomicCAS(&a.hkeys[h], kHashEmpty, key);
+                if (prev == kHashEmpty || prev == key) {
+                    atomicMin(&a.hvals[h], i);
+                    break;
                 }
-                slot = h;
+                h = (h + 1) & a.hash_mask;
             }
-            a.rec[i] = make_uint4((uint32_t)vx, (uint32_t)vy, (uint32_t)vz, (st << 16) | (uint32_t)bin);
-            a.pslot[i] = slot;
+            slot = h;
         }
-        wave_add(a.scan_ctr, s, SC_INVALID, live && st == kStInvalid ? 1u : 0u);
-        wave_add(a.scan_ctr, s, SC_OOB, live && st == kStOob ? 1u : 0u);
+        a.rec[i] = make_uint4((uint32_t)vx, (uint32_t)vy, (uint32_t)vz, (st << 16) | (uint32_t)bin);
+        a.pslot[i] = slot;
     }
-}
-
-// brick span of the cube [c - R, c + R] along one axis with brick side 1 << sh
-__device__ __forceinline__ void span(uint32_t c, int R, uint32_t sh, uint32_t &b0, uint32_t &nb) {
-    b0 = (c - (uint32_t)R) >> sh;
-    nb = ((c + (uint32_t)R) >> sh) - b0 + 1u;
 }
 
 struct SelectOut {
@@ -244,7 +234,7 @@ __device__ __forceinline__ SelectOut select_point(const PipeArgs &a, const CallI
     SelectOut o{false, false, 0u, 0u, make_uint4(0, 0, 0, 0)};
     if (!live) return o;
     o.r = a.rec[i];
-    if ((o.r.w >> 16) != kStOk) return o;
+    if (((o.r.w >> 16) & 3u) != kStOk) return o;  // bits 16-17 only: bit 30 may already be set
     o.s = find_scan(a.scans, info->n_scans, i);
     const DevScan &sc = a.scans[o.s];
     o.surv = !sc.dedup || a.hvals[a.pslot[i]] == i;
@@ -256,49 +246,160 @@ __device__ __forceinline__ SelectOut select_point(const PipeArgs &a, const CallI
     return o;
 }
 
-__global__ __launch_bounds__(kPtThreads) void k_select_brick(PipeArgs a, const CallInfo *info) {
-    const uint32_t n = info->n_points;
-    const uint32_t shx = __builtin_ctz(a.brick[0]), shy = __builtin_ctz(a.brick[1]), shz = __builtin_ctz(a.brick[2]);
+// Exclusive prefix of v over the block; *total receives the block sum.
+template <int THREADS>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_tmp, uint32_t &total) {
+    const uint32_t w = threadIdx.x >> 6;
+    const uint32_t incl = wave_incl_scan_u32(v);
+    if (lane() == 63u) s_tmp[w] = incl;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < THREADS / 64; ++k) {
+        const uint32_t x = s_tmp[k];
+        before += (uint32_t)k < w ? x : 0u;
+        tot += x;
+    }
+    __syncthreads();
+    total = tot;
+    return before + incl - v;
+}
+
+// brick j of the (at most span[0] x span[1] x span[2]) bricks a K^3 cube touches
+__device__ __forceinline__ bool pair_brick(const PipeArgs &a, const uint4 &r, uint32_t j, const DevGrid &g,
+                                           uint32_t &id) {
     const int R = a.tab.R;
-    // uniform bound on bricks per cube, same for every lane
-    const uint32_t mx = 1u + (2u * R + a.brick[0] - 1u) / a.brick[0];
-    const uint32_t my = 1u + (2u * R + a.brick[1] - 1u) / a.brick[1];
-    const uint32_t mz = 1u + (2u * R + a.brick[2] - 1u) / a.brick[2];
+    const uint32_t mx = a.span[0], my = a.span[1];
+    const uint32_t jx = j % mx, jy = (j / mx) % my, jz = j / (mx * my);
+    const uint32_t bx = (r.x - (uint32_t)R) / a.brick[0] + jx;
+    const uint32_t by = (r.y - (uint32_t)R) / a.brick[1] + jy;
+    const uint32_t bz = (r.z - (uint32_t)R) / a.brick[2] + jz;
+    if (bx > (r.x + (uint32_t)R) / a.brick[0] || by > (r.y + (uint32_t)R) / a.brick[1] ||
+        bz > (r.z + (uint32_t)R) / a.brick[2])
+        return false;
+    id = bx + g.nbx * (by + g.nby * bz);
+    return true;
+}
+
+// One thread per point: the survivor test, then one atomicAdd per brick its
+// K^3 cube touches on that brick's counter (issued kSelUnroll at a time so
+// that they are in flight together); the returned old count is the pair's
+// rank in the brick's list. Pairs that open a brick take work-item slots,
+// one global atomic per block.
+constexpr int kSelUnroll = 6;
+
+__global__ __launch_bounds__(kSelThreads) void k_select_pairs(PipeArgs a, const CallInfo *info) {
+    __shared__ uint32_t s_tmp[kSelThreads / 64];
+    __shared__ uint32_t s_base;
+    const uint32_t n = info->n_points;
+    const uint32_t F = a.span[0] * a.span[1] * a.span[2];
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
         const uint32_t i = base + threadIdx.x;
         const SelectOut o = select_point(a, info, i, i < n);
-        uint32_t gi = 0, bx0 = 0, by0 = 0, bz0 = 0, nbx = 0, nby = 0, nbz = 0;
+        unsigned long long opened_bits = 0;   // pair j opened its brick (j < 64)
+        uint32_t n_open = 0, gi = 0;
         DevGrid g{};
         if (o.surv) {
             a.rec[i].w = o.r.w | kRecSurvivor;
             gi = a.scans[o.s].grid;
             g = a.grids[gi];
-            span(o.r.x, R, shx, bx0, nbx);
-            span(o.r.y, R, shy, by0, nby);
-            span(o.r.z, R, shz, bz0, nbz);
-        }
-        for (uint32_t jz = 0; jz < mz; ++jz)
-            for (uint32_t jy = 0; jy < my; ++jy)
-                for (uint32_t jx = 0; jx < mx; ++jx) {
-                    const bool valid = o.surv && jx < nbx && jy < nby && jz < nbz;
+            for (uint32_t j0 = 0; j0 < F; j0 += kSelUnroll) {
+                uint32_t rk[kSelUnroll];
+                bool v[kSelUnroll];
+#pragma unroll
+                for (int u = 0; u < kSelUnroll; ++u) {
                     uint32_t id = 0;
-                    bool first = false;
-                    if (valid) {
-                        id = (bx0 + jx) + g.nbx * ((by0 + jy) + g.nby * (bz0 + jz));
-                        first = atomicAdd(&g.brick_cnt[id], 1u) == 0u;
-                    }
-                    const uint32_t slot = wave_claim(&a.ctrl->n_active, first);
-                    if (first) {
-                        a.items[slot] = ((unsigned long long)gi << 32) | id;
-                        g.brick_slot[id] = slot;
+                    v[u] = j0 + u < F && pair_brick(a, o.r, j0 + u, g, id);
+                    rk[u] = v[u] ? atomicAdd(&g.brick_cnt[id], 1u) : 1u;
+                }
+#pragma unroll
+                for (int u = 0; u < kSelUnroll; ++u) {
+                    if (!v[u]) continue;
+                    a.rank[(size_t)i * F + j0 + u] = rk[u];
+                    if (rk[u] == 0u) {
+                        ++n_open;
+                        if (j0 + u < 64) opened_bits |= 1ull << (j0 + u);
                     }
                 }
-        wave_add(a.scan_ctr, o.s, SC_DUP, o.dup ? 1u : 0u);
-        wave_add(a.scan_ctr, o.s, SC_INT, o.surv ? 1u : 0u);
-        wave_add(a.scan_ctr, o.s, SC_SHADOW, o.shadow_n);
+            }
+        }
+        uint32_t total;
+        const uint32_t pos = block_excl_scan<kSelThreads>(n_open, s_tmp, total);
+        if (total) {
+            if (threadIdx.x == 0) s_base = atomicAdd(&a.ctrl->n_active, total);
+            __syncthreads();
+            uint32_t k = 0;
+            for (uint32_t j = 0; j < F && k < n_open; ++j) {
+                const bool op = j < 64 ? ((opened_bits >> j) & 1ull) != 0ull : a.rank[(size_t)i * F + j] == 0u;
+                uint32_t id = 0;
+                if (!op || !pair_brick(a, o.r, j, g, id)) continue;
+                const uint32_t slot = s_base + pos + k++;
+                a.items[slot] = ((unsigned long long)gi << 32) | id;
+                g.brick_slot[id] = slot;
+            }
+            __syncthreads();
+        }
     }
 }
 
+// Per-scan statistics from the point records (after the select pass): each
+// block reduces a contiguous run of points; a run inside one scan costs one
+// atomic per counter.
+__global__ __launch_bounds__(kPtThreads) void k_stats(PipeArgs a, const CallInfo *info, uint32_t chunk) {
+    __shared__ uint32_t s_red[SC_N][kPtThreads / 64];
+    const uint32_t n = info->n_points;
+    for (uint32_t lo = blockIdx.x * chunk; lo < n; lo += gridDim.x * chunk) {
+        const uint32_t hi = min(n, lo + chunk);
+        const uint32_t s0 = find_scan(a.scans, info->n_scans, lo);
+        const uint32_t s1 = find_scan(a.scans, info->n_scans, hi - 1);
+        if (s0 == s1) {
+            uint32_t c[SC_N] = {0u, 0u, 0u, 0u, 0u};
+            for (uint32_t i = lo + threadIdx.x; i < hi; i += kPtThreads) {
+                const uint32_t w = a.rec[i].w;
+                const uint32_t st = (w >> 16) & 3u;
+                c[SC_INVALID] += st == kStInvalid;
+                c[SC_OOB] += st == kStOob;
+                const bool surv = st == kStOk && (w & kRecSurvivor);
+                c[SC_DUP] += st == kStOk && !surv;
+                c[SC_INT] += surv;
+                if (surv) c[SC_SHADOW] += a.tab.sh_start[(w & 0xFFFFu) + 1] - a.tab.sh_start[w & 0xFFFFu];
+            }
+#pragma unroll
+            for (int f = 0; f < SC_N; ++f) {
+                const uint32_t v = wave_sum_u32(c[f]);
+                if (lane() == 0) s_red[f][threadIdx.x >> 6] = v;
+            }
+            __syncthreads();
+            if (threadIdx.x < SC_N) {
+                unsigned long long tot = 0;
+                for (int k = 0; k < kPtThreads / 64; ++k) tot += s_red[threadIdx.x][k];
+                if (tot) atomicAdd(&a.scan_ctr[(size_t)s0 * SC_N + threadIdx.x], tot);
+            }
+            __syncthreads();
+        } else {
+            for (uint32_t b0 = lo; b0 < hi; b0 += kPtThreads) {
+                const uint32_t i = b0 + threadIdx.x;
+                uint32_t w = 0, s = 0;
+                if (i < hi) {
+                    w = a.rec[i].w;
+                    s = find_scan(a.scans, info->n_scans, i);
+                }
+                const uint32_t st = i < hi ? (w >> 16) & 3u : 3u;
+                const bool surv = st == kStOk && (w & kRecSurvivor);
+                wave_add(a.scan_ctr, s, SC_INVALID, st == kStInvalid);
+                wave_add(a.scan_ctr, s, SC_OOB, st == kStOob);
+                wave_add(a.scan_ctr, s, SC_DUP, st == kStOk && !surv);
+                wave_add(a.scan_ctr, s, SC_INT, surv);
+                wave_add(a.scan_ctr, s, SC_SHADOW,
+                         surv ? a.tab.sh_start[(w & 0xFFFFu) + 1] - a.tab.sh_start[w & 0xFFFFu] : 0u);
+            }
+        }
+    }
+}
+
+// Per touched brick: list offset (exclusive scan of the counts), count, and
+// its apply work units (bricks with more than `chunk` listed points are split).
+// Resets the brick counters for the next call.
 __global__ __launch_bounds__(kPtThreads) void k_offsets(PipeArgs a) {
     const uint32_t n = a.ctrl->n_active;
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
@@ -306,155 +407,342 @@ __global__ __launch_bounds__(kPtThreads) void k_offsets(PipeArgs a) {
         uint32_t cnt = 0;
         if (t < n) {
             const unsigned long long it = a.items[t];
-            cnt = a.grids[it >> 32].brick_cnt[(uint32_t)it];
+            uint32_t *bc = a.grids[it >> 32].brick_cnt + (uint32_t)it;
+            cnt = *bc;
+            *bc = 0u;
         }
         const uint32_t incl = wave_incl_scan_u32(cnt);
         uint32_t wbase = 0;
         if (lane() == 63u) wbase = atomicAdd(&a.ctrl->total_entries, incl);
         wbase = __shfl(wbase, 63, 64);
+        const uint32_t nsub = t < n ? (a.chunk ? (cnt + a.chunk - 1u) / a.chunk : 1u) : 0u;
+        const uint32_t sincl = wave_incl_scan_u32(nsub);
+        uint32_t sbase = 0;
+        if (lane() == 63u) sbase = atomicAdd(&a.ctrl->n_work, sincl);
+        sbase = __shfl(sbase, 63, 64);
         if (t < n) {
             a.item_off[t] = wbase + incl - cnt;
-            a.item_cur[t] = 0u;
+            a.item_cnt[t] = cnt;
+            const uint32_t split = nsub > 1u ? 0x80000000u : 0u;
+            for (uint32_t k = 0; k < nsub; ++k) a.work[sbase + sincl - nsub + k] = make_uint2(t, k | split);
         }
     }
 }
 
-__global__ __launch_bounds__(kPtThreads) void k_fill(PipeArgs a, const CallInfo *info) {
+// Writes every (point, brick) pair at its rank in the brick's list, and
+// releases the dedup hash slots (every reader is done).
+__global__ __launch_bounds__(kPtThreads) void k_fill_pairs(PipeArgs a, const CallInfo *info) {
     const uint32_t n = info->n_points;
-    const uint32_t shx = __builtin_ctz(a.brick[0]), shy = __builtin_ctz(a.brick[1]), shz = __builtin_ctz(a.brick[2]);
-    const int R = a.tab.R;
+    const uint32_t F = a.span[0] * a.span[1] * a.span[2];
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const uint4 r = a.rec[i];
         const uint32_t slot = a.pslot[i];
-        if (slot != kNoSlot) {  // release the dedup slot (every reader is done)
+        if (slot != kNoSlot) {
             a.hkeys[slot] = kHashEmpty;
             a.hvals[slot] = 0xFFFFFFFFu;
         }
         if (!(r.w & kRecSurvivor)) continue;
-        const uint32_t s = find_scan(a.scans, info->n_scans, i);
-        const DevGrid g = a.grids[a.scans[s].grid];
-        uint32_t bx0, by0, bz0, nbx, nby, nbz;
-        span(r.x, R, shx, bx0, nbx);
-        span(r.y, R, shy, by0, nby);
-        span(r.z, R, shz, bz0, nbz);
-        for (uint32_t jz = 0; jz < nbz; ++jz)
-            for (uint32_t jy = 0; jy < nby; ++jy)
-                for (uint32_t jx = 0; jx < nbx; ++jx) {
-                    const uint32_t id = (bx0 + jx) + g.nbx * ((by0 + jy) + g.nby * (bz0 + jz));
-                    const uint32_t it = g.brick_slot[id];
-                    const uint32_t pos = a.item_off[it] + atomicAdd(&a.item_cur[it], 1u);
-                    a.entries[pos] = i;
-                }
+        const DevGrid &g = a.grids[a.scans[find_scan(a.scans, info->n_scans, i)].grid];
+        for (uint32_t j = 0; j < F; ++j) {
+            uint32_t id;
+            if (!pair_brick(a, r, j, g, id)) continue;
+            a.entries[a.item_off[g.brick_slot[id]] + a.rank[(size_t)i * F + j]] = i;
+        }
     }
 }
 
 // --------------------------------------------------------------- apply ---
-// One workgroup owns brick (BX, BY, BZ) of one grid at a time. LDS holds the
-// brick's AND-accumulated eq. 3 stamp and its shadow hit counts.
-template <int BX, int BY, int BZ, int THREADS>
+// One workgroup owns one brick (BX, BY, BZ) of one grid per work unit. LDS
+// holds the brick widened by twice the kernel radius on both x sides (a listed
+// point lies at most R outside the brick and its cube reaches R further, so a
+// row of K cells is never cut), as two tiles: the AND-accumulated eq. 3 stamp and the
+// shadow hit counts. The row pitch is odd so that 64 lanes on 64 different
+// rows hit 64 different banks.
+//   1. the work unit's listed points are staged in LDS with everything a row
+//      needs precomputed (one cooperative load of the list and the records);
+//   2. each lane of a wavefront takes one (y, z) row of one point's cube that
+//      lies in the brick and ANDs its K masks into the tile (the masks of a
+//      row depend on |dx| only, so R + 1 table reads serve K cells), then adds
+//      the shadow cells of the row;
+//   3. the brick interior is merged into HBM 16 bytes at a time, every load
+//      issued before the stores: mask &= stamp (store skipped when unchanged),
+//      h = min(h + count, H_max), sign cleared on the crossing (eq. 6). A brick
+//      split over several work units merges with atomics instead.
+constexpr int kStage = 512;
+constexpr int kLutMax = 3 * (kMaxK / 2) * (kMaxK / 2) + 1;
+
+// x extent of the tile: BX + 4R, made odd
+constexpr int row_pitch(int bx, int r) { return (bx + 4 * r) | 1; }
+
+// largest kernel radius whose two tiles fit in LDS next to the staging area
+constexpr int kLdsForTiles = 160 * 1024 - kStage * 16 - kLutMax * 4 - 1024;
+constexpr int max_radius(int bx, int by, int bz) {
+    int r = kMaxK / 2;
+    while (r > 0 && 2 * row_pitch(bx, r) * by * bz * 4 > kLdsForTiles) --r;
+    return r;
+}
+
+template <int BX, int BY, int BZ, int THREADS, int RR>
 __global__ __launch_bounds__(THREADS) void k_apply_brick(PipeArgs a) {
-    constexpr int V = BX * BY * BZ;
+    // RR > 0: rows unrolled for that radius; RR = 0: any radius up to the
+    // largest whose tiles fit (the tile is sized for that)
+    constexpr int RM = RR > 0 ? RR : max_radius(BX, BY, BZ);
+    if constexpr (RM <= max_radius(BX, BY, BZ)) {
+    constexpr int PX = row_pitch(BX, RM);
+    constexpr int HX = 2 * RM;                          // tile column of brick-local x = 0
+    constexpr int TILE = PX * BY * BZ;
     constexpr int WAVES = THREADS / 64;
-    __shared__ uint32_t lmask[V];
-    __shared__ uint32_t lcnt[V];
-    __shared__ uint32_t lut[3 * kMaxK * kMaxK / 4 + 8];   // mask by metric value (n_q <= 3 R^2 + 1)
-    __shared__ unsigned long long red[3 * WAVES];
+    constexpr int V = BX * BY * BZ;
+    constexpr int NQ = V / (4 * THREADS);
+    constexpr int NB = NQ < 4 ? NQ : 4;
+    static_assert(V % (4 * THREADS) == 0, "brick volume must be a multiple of 4 x threads");
+    static_assert(NQ % NB == 0, "quads per thread must split evenly");
+    static_assert(TILE % 4 == 0, "tile must hold whole 16-byte quads");
+    __shared__ __align__(16) uint32_t tmask[TILE];
+    __shared__ __align__(16) uint32_t tcnt[TILE];
+    __shared__ uint32_t lut[kLutMax];
+    __shared__ uint4 ent[kStage];
+    __shared__ uint32_t red[3 * WAVES];
 
     const DevTables &t = a.tab;
     for (uint32_t q = threadIdx.x; q < t.n_q; q += THREADS) lut[q] = t.mask_by_q[q];
-    const int R = t.R;
+    const int R = RR > 0 ? RR : t.R;
     const bool l1 = t.metric == DBTSDF_DIST_L1;
-    const uint32_t n_items = a.ctrl->n_active;
+    const bool cube = t.binning == DBTSDF_BIN_CUBE26;
+    const int r2 = t.shadow_r2;
+    const uint32_t n_work = a.ctrl->n_work;
     const uint32_t w = threadIdx.x >> 6, l = lane();
 
-    for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+    for (uint32_t wi = blockIdx.x; wi < n_work; wi += gridDim.x) {
+        const uint2 wk = a.work[wi];
+        const uint32_t item = wk.x, sub = wk.y & 0x7FFFFFFFu;
+        const bool split = (wk.y >> 31) != 0u;
         const unsigned long long it = a.items[item];
         const DevGrid g = a.grids[it >> 32];
         const uint32_t brick = (uint32_t)it;
         const uint32_t bxi = brick % g.nbx, byi = (brick / g.nbx) % g.nby, bzi = brick / (g.nbx * g.nby);
         const int x0 = (int)bxi * BX, y0 = (int)byi * BY, z0 = (int)bzi * BZ;
-        const uint32_t start = a.item_off[item];
-        const uint32_t cnt = g.brick_cnt[brick];
+        const uint32_t all = a.item_cnt[item];
+        const uint32_t start = a.item_off[item] + (split ? sub * a.chunk : 0u);
+        const uint32_t cnt = split ? min(a.chunk, all - sub * a.chunk) : all;
 
-        for (int v = threadIdx.x; v < V; v += THREADS) {
-            lmask[v] = 0xFFFFFFFFu;
-            lcnt[v] = 0u;
+        for (int q = threadIdx.x; q < TILE / 4; q += THREADS) {
+            reinterpret_cast<uint4 *>(tmask)[q] = make_uint4(~0u, ~0u, ~0u, ~0u);
+            reinterpret_cast<uint4 *>(tcnt)[q] = make_uint4(0u, 0u, 0u, 0u);
         }
-        __syncthreads();
-
-        // stamp: one wavefront per listed point
-        for (uint32_t e = w; e < cnt; e += WAVES) {
-            const uint32_t pidx = a.entries[start + e];
-            const uint4 r = a.rec[pidx];
-            const int lx = (int)r.x - x0, ly = (int)r.y - y0, lz = (int)r.z - z0;
-            const int xa = max(lx - R, 0), xb = min(lx + R, BX - 1);
-            const int ya = max(ly - R, 0), yb = min(ly + R, BY - 1);
-            const int za = max(lz - R, 0), zb = min(lz + R, BZ - 1);
-            const uint32_t wx = (uint32_t)(xb - xa + 1), wy = (uint32_t)(yb - ya + 1), wz = (uint32_t)(zb - za + 1);
-            const uint32_t rpi = 64u / wx;           // rows per wave step
-            const uint32_t xi = l % wx, ri = l / wx;
-            const bool lane_on = ri < rpi;
-            const uint32_t rows = wy * wz;
-            const uint32_t mag = ((1u << 20) + wy - 1u) / wy;  // exact r / wy for r < 2^20 / wy
-            const int ox = xa + (int)xi - lx;
-            const int xx = xa + (int)xi;
-            for (uint32_t r0 = 0; r0 < rows; r0 += rpi) {
-                const uint32_t rr = r0 + ri;
-                if (lane_on && rr < rows) {
-                    const uint32_t rz = (rr * mag) >> 20;
+        for (uint32_t base = 0; base < cnt; base += kStage) {
+            const uint32_t nb = min(cnt - base, (uint32_t)kStage);
+            __syncthreads();  // tile init done / previous round's readers done
+            for (uint32_t e = threadIdx.x; e < nb; e += THREADS) {
+                const uint4 r = a.rec[a.entries[start + base + e]];
+                const int lx = (int)r.x - x0, ly = (int)r.y - y0, lz = (int)r.z - z0;
+                const int ya = max(ly - R, 0), yb = min(ly + R, BY - 1);
+                const int za = max(lz - R, 0), zb = min(lz + R, BZ - 1);
+                const uint32_t wy = (uint32_t)(yb - ya + 1), rows = wy * (uint32_t)(zb - za + 1);
+                // x: tile column of the cube's first cell; y, z: first row and the point
+                ent[e] = make_uint4((uint32_t)(lx - R + HX) | ((uint32_t)ya << 12) | ((uint32_t)za << 22),
+                                    (uint32_t)(ly + 64) | ((uint32_t)(lz + 64) << 8) | (wy << 16) | (rows << 22),
+                                    r.w & 0xFFFFu, __float_as_uint(1.0f / (float)wy));
+            }
+            __syncthreads();
+            for (uint32_t e = w; e < nb; e += WAVES) {
+                // the entry is the same for the whole wavefront: decode it in scalars
+                const uint4 env = ent[e];
+                const uint32_t ex = __builtin_amdgcn_readfirstlane(env.x);
+                const uint32_t ey = __builtin_amdgcn_readfirstlane(env.y);
+                const uint32_t bin = __builtin_amdgcn_readfirstlane(env.z);
+                const float rwy = __uint_as_float(__builtin_amdgcn_readfirstlane(env.w));
+                const int cx = (int)(ex & 4095u), ya = (int)((ex >> 12) & 1023u), za = (int)(ex >> 22);
+                const int ly = (int)(ey & 255u) - 64, lz = (int)((ey >> 8) & 255u) - 64;
+                const uint32_t wy = (ey >> 16) & 63u, rows = ey >> 22;
+                const int code = (int)bin + (bin >= 13u ? 1 : 0);
+                const int sxv = code / 9 - 1, syv = (code / 3) % 3 - 1, szv = code % 3 - 1;
+                for (uint32_t rr = l; rr < rows; rr += 64u) {
+                    const uint32_t rz = (uint32_t)(((float)rr + 0.5f) * rwy);
                     const uint32_t ry = rr - rz * wy;
                     const int yy = ya + (int)ry, zz = za + (int)rz;
                     const int oy = yy - ly, oz = zz - lz;
-                    const uint32_t q = l1 ? (uint32_t)(abs(ox) + abs(oy) + abs(oz)) : (uint32_t)(ox * ox + oy * oy + oz * oz);
-                    atomicAnd(&lmask[xx + BX * (yy + BY * zz)], lut[q]);
+                    const int c2 = oy * oy + oz * oz;
+                    const int row = cx + PX * (yy + BY * zz);
+                    if (!l1) {
+                        if constexpr (RR > 0) {
+                            uint32_t m[RR + 1];
+#pragma unroll
+                            for (int k = 0; k <= RR; ++k) m[k] = lut[c2 + k * k];
+#pragma unroll
+                            for (int k = 0; k < 2 * RR + 1; ++k) atomicAnd(&tmask[row + k], m[k < RR ? RR - k : k - RR]);
+                        } else {
+                            for (int k = 0; k < 2 * R + 1; ++k) {
+                                const int ox = k - R;
+                                atomicAnd(&tmask[row + k], lut[c2 + ox * ox]);
+                            }
+                        }
+                    } else {
+                        const int c1 = abs(oy) + abs(oz);
+                        for (int k = 0; k < 2 * R + 1; ++k) atomicAnd(&tmask[row + k], lut[c1 + abs(k - R)]);
+                    }
+                    if (cube && c2 <= r2) {
+                        // shadow cells of the row: |dx| <= floor(sqrt(r2 - c2)) (ball) and
+                        // dx * sx >= -(dy * sy + dz * sz) (back half-space): an interval
+                        int m = 0;
+                        while ((m + 1) * (m + 1) <= r2 - c2) ++m;
+                        const int dyz = oy * syv + oz * szv;
+                        int lo = -m, hi = m;
+                        if (sxv > 0) lo = max(lo, -dyz);
+                        else if (sxv < 0) hi = min(hi, dyz);
+                        else if (dyz < 0) hi = lo - 1;
+                        lo = max(lo, -R);
+                        hi = min(hi, R);
+                        if (lo <= hi) {
+                            if constexpr (RR > 0) {
+                                const uint32_t bits = ((2u << (hi - lo)) - 1u) << (lo + RR);
+#pragma unroll
+                                for (int k = 0; k < 2 * RR + 1; ++k) atomicAdd(&tcnt[row + k], (bits >> k) & 1u);
+                            } else {
+                                for (int ox = lo; ox <= hi; ++ox) atomicAdd(&tcnt[row + ox + R], 1u);
+                            }
+                        }
+                    }
                 }
-            }
-            const uint32_t bin = r.w & 0xFFFFu;
-            const uint32_t s0 = t.sh_start[bin], s1 = t.sh_start[bin + 1];
-            for (uint32_t j = s0 + l; j < s1; j += 64u) {
-                const uint32_t off = t.sh_off[j];
-                const int sx = lx + (int)(off & 255u) - R;
-                const int sy = ly + (int)((off >> 8) & 255u) - R;
-                const int sz = lz + (int)((off >> 16) & 255u) - R;
-                if (sx >= 0 && sx < BX && sy >= 0 && sy < BY && sz >= 0 && sz < BZ)
-                    atomicAdd(&lcnt[sx + BX * (sy + BY * sz)], 1u);
+                if (!cube) {
+                    // AZEL: the bin's shadow list, clipped to the brick in y and z
+                    const int lxt = cx + R;  // tile column of the point
+                    const uint32_t s0 = t.sh_start[bin], s1 = t.sh_start[bin + 1];
+                    for (uint32_t j = s0 + l; j < s1; j += 64u) {
+                        const uint32_t off = t.sh_off[j];
+                        const int sx = lxt + (int)(off & 255u) - R;
+                        const int sy = ly + (int)((off >> 8) & 255u) - R;
+                        const int sz = lz + (int)((off >> 16) & 255u) - R;
+                        if (sy >= 0 && sy < BY && sz >= 0 && sz < BZ) atomicAdd(&tcnt[sx + PX * (sy + BY * sz)], 1u);
+                    }
+                }
             }
         }
         __syncthreads();
 
-        // merge the brick into HBM
+        // merge the brick interior into HBM, NB quads in flight per thread
         uint32_t um = 0, cm = 0, us = 0;
-        for (int v = threadIdx.x; v < V; v += THREADS) {
-            const uint32_t m = lmask[v], c = lcnt[v];
-            if (m == 0xFFFFFFFFu && c == 0u) continue;
-            const uint32_t gx = (uint32_t)(x0 + (v % BX)), gy = (uint32_t)(y0 + (v / BX) % BY), gz = (uint32_t)(z0 + v / (BX * BY));
-            if (gx >= g.nx || gy >= g.ny || gz >= g.nz) continue;
-            const size_t lin = (size_t)gx + (size_t)g.nx * ((size_t)gy + (size_t)g.ny * gz);
-            if (m != 0xFFFFFFFFu) {
-                const uint32_t old = g.mask[lin];
-                const uint32_t nw = old & m;
-                if (nw != old) {
-                    g.mask[lin] = nw;
-                    ++cm;
+        const bool vec_x = (g.nx & 3u) == 0;
+#pragma unroll
+        for (int k0 = 0; k0 < NQ; k0 += NB) {
+            uint32_t sm[NB][4], sc[NB][4];
+            uint4 om[NB], op[NB];
+            size_t lin[NB];
+            bool fast[NB], need_m[NB], need_c[NB];
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                const int q = (int)threadIdx.x + (k0 + k) * THREADS;
+                const int v = 4 * q;
+                const int xl = v % BX, yl = (v / BX) % BY, zl = v / (BX * BY);
+                const int tb = HX + xl + PX * (yl + BY * zl);
+                bool any_m = false, any_c = false;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    sm[k][j] = tmask[tb + j];
+                    sc[k][j] = tcnt[tb + j];
+                    any_m |= sm[k][j] != 0xFFFFFFFFu;
+                    any_c |= sc[k][j] != 0u;
                 }
-                ++um;
+                need_m[k] = any_m;
+                need_c[k] = any_c;
+                const uint32_t gx = (uint32_t)(x0 + xl), gy = (uint32_t)(y0 + yl), gz = (uint32_t)(z0 + zl);
+                lin[k] = (size_t)gx + (size_t)g.nx * ((size_t)gy + (size_t)g.ny * gz);
+                fast[k] = !split && vec_x && gx + 3u < g.nx && gy < g.ny && gz < g.nz;
+                if (fast[k] && any_m) om[k] = *reinterpret_cast<const uint4 *>(g.mask + lin[k]);
+                if (fast[k] && any_c) op[k] = *reinterpret_cast<const uint4 *>(g.packed + lin[k]);
             }
-            if (c) {
-                const uint32_t old = g.packed[lin];
-                const uint32_t h0 = old & 0xFFFFu;
-                const uint32_t h1 = min(h0 + c, g.hmax);
-                uint32_t sign = old & 0x80000000u;
-                if (h0 < g.T && h1 >= g.T) sign = 0u;
-                const uint32_t nw = sign | h1;
-                if (nw != old) g.packed[lin] = nw;
-                ++us;
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                if (!need_m[k] && !need_c[k]) continue;
+                if (fast[k]) {
+                    if (need_m[k]) {
+                        const uint32_t o[4] = {om[k].x, om[k].y, om[k].z, om[k].w};
+                        uint32_t nw[4];
+                        bool ch = false;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            nw[j] = o[j] & sm[k][j];
+                            um += sm[k][j] != 0xFFFFFFFFu;
+                            cm += nw[j] != o[j];
+                            ch |= nw[j] != o[j];
+                        }
+                        if (ch) *reinterpret_cast<uint4 *>(g.mask + lin[k]) = make_uint4(nw[0], nw[1], nw[2], nw[3]);
+                    }
+                    if (need_c[k]) {
+                        const uint32_t o[4] = {op[k].x, op[k].y, op[k].z, op[k].w};
+                        uint32_t nw[4];
+                        bool ch = false;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const uint32_t h0 = o[j] & 0xFFFFu;
+                            const uint32_t h1 = min(h0 + sc[k][j], g.hmax);
+                            const uint32_t sign = (h0 < g.T && h1 >= g.T) ? 0u : (o[j] & 0x80000000u);
+                            nw[j] = sc[k][j] ? (sign | h1) : o[j];
+                            us += sc[k][j] != 0u;
+                            ch |= nw[j] != o[j];
+                        }
+                        if (ch) *reinterpret_cast<uint4 *>(g.packed + lin[k]) = make_uint4(nw[0], nw[1], nw[2], nw[3]);
+                    }
+                    continue;
+                }
+                const int v = 4 * ((int)threadIdx.x + (k0 + k) * THREADS);
+                const uint32_t gx = (uint32_t)(x0 + v % BX), gy = (uint32_t)(y0 + (v / BX) % BY),
+                               gz = (uint32_t)(z0 + v / (BX * BY));
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (gx + j >= g.nx || gy >= g.ny || gz >= g.nz) continue;
+                    const size_t li = lin[k] + j;
+                    if (!split) {
+                        // grid edge or Nx not a multiple of 4: element by element
+                        if (sm[k][j] != 0xFFFFFFFFu) {
+                            const uint32_t old = g.mask[li];
+                            const uint32_t nw = old & sm[k][j];
+                            if (nw != old) {
+                                g.mask[li] = nw;
+                                ++cm;
+                            }
+                            ++um;
+                        }
+                        if (sc[k][j]) {
+                            const uint32_t old = g.packed[li];
+                            const uint32_t h0 = old & 0xFFFFu;
+                            const uint32_t h1 = min(h0 + sc[k][j], g.hmax);
+                            const uint32_t sign = (h0 < g.T && h1 >= g.T) ? 0u : (old & 0x80000000u);
+                            const uint32_t nw = sign | h1;
+                            if (nw != old) g.packed[li] = nw;
+                            ++us;
+                        }
+                    } else {
+                        // a split brick: other work units merge into the same words, so
+                        // the mask uses atomicAnd and the counter a compare-and-swap loop
+                        // (c steps of eq. 5 then d steps equal c + d steps, and eq. 6
+                        // fires once on the crossing, so the merge order does not matter)
+                        if (sm[k][j] != 0xFFFFFFFFu) {
+                            const uint32_t old = g.mask[li];
+                            if ((old & sm[k][j]) != old) atomicAnd(&g.mask[li], sm[k][j]);
+                        }
+                        if (sc[k][j]) {
+                            uint32_t old = g.packed[li];
+                            for (;;) {
+                                const uint32_t h0 = old & 0xFFFFu;
+                                const uint32_t h1 = min(h0 + sc[k][j], g.hmax);
+                                const uint32_t sign = (h0 < g.T && h1 >= g.T) ? 0u : (old & 0x80000000u);
+                                const uint32_t nw = sign | h1;
+                                if (nw == old) break;
+                                const uint32_t prev = atomicCAS(&g.packed[li], old, nw);
+                                if (prev == old) break;
+                                old = prev;
+                            }
+                        }
+                    }
+                }
             }
         }
         if (a.count_traffic) {
-            const uint32_t su = wave_sum_u32(um), sc = wave_sum_u32(cm), ss = wave_sum_u32(us);
+            const uint32_t su = wave_sum_u32(um), sc2 = wave_sum_u32(cm), ss = wave_sum_u32(us);
             if (l == 0) {
                 red[3 * w + 0] = su;
-                red[3 * w + 1] = sc;
+                red[3 * w + 1] = sc2;
                 red[3 * w + 2] = ss;
             }
             __syncthreads();
@@ -464,31 +752,44 @@ __global__ __launch_bounds__(THREADS) void k_apply_brick(PipeArgs a) {
                 if (tot) atomicAdd(&a.traffic_ctr[(size_t)g.traffic_slot * TC_N + threadIdx.x], tot);
             }
         }
-        if (threadIdx.x == 0) g.brick_cnt[brick] = 0u;  // ready for the next call
         __syncthreads();
+    }
     }
 }
 
 // ------------------------------------------------------ atomic strategy ---
-__global__ __launch_bounds__(kPtThreads) void k_select_atomic(PipeArgs a, const CallInfo *info) {
+__global__ __launch_bounds__(kSelThreads) void k_select_atomic(PipeArgs a, const CallInfo *info) {
+    __shared__ uint32_t s_tmp[kSelThreads / 64];
+    __shared__ uint32_t s_base;
     const uint32_t n = info->n_points;
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
         const uint32_t i = base + threadIdx.x;
         const SelectOut o = select_point(a, info, i, i < n);
-        const uint32_t slot = wave_claim(&a.ctrl->n_survivors, o.surv);
-        if (o.surv) a.survivors[slot] = i;
-        wave_add(a.scan_ctr, o.s, SC_DUP, o.dup ? 1u : 0u);
-        wave_add(a.scan_ctr, o.s, SC_INT, o.surv ? 1u : 0u);
-        wave_add(a.scan_ctr, o.s, SC_SHADOW, o.shadow_n);
+        if (o.surv) a.rec[i].w = o.r.w | kRecSurvivor;
+        uint32_t tot;
+        const uint32_t pos = block_excl_scan<kSelThreads>(o.surv ? 1u : 0u, s_tmp, tot);
+        if (tot) {
+            if (threadIdx.x == 0) s_base = atomicAdd(&a.ctrl->n_survivors, tot);
+            __syncthreads();
+            if (o.surv) a.survivors[s_base + pos] = i;
+            __syncthreads();
+        }
     }
 }
 
 // One wavefront per surviving point, straight into HBM: read-first atomicAnd
 // (eq. 4) and the guard-bit counter (eqs. 5-6): every add that sees a raw
 // count >= H_max is cancelled, and the add that sees T - 1 clears the sign.
-// Bits 16-30 absorb the transient overshoot of concurrent adds.
+// Bits 16-30 absorb the transient overshoot of concurrent adds. Each lane
+// issues the loads of kAtomicBatch cells before it compares any of them, so a
+// point costs a few memory round trips rather than one per cell row.
+constexpr int kAtomicBatch = 2;
+
 __global__ __launch_bounds__(kPtThreads) void k_apply_atomic(PipeArgs a, const CallInfo *info) {
+    __shared__ uint32_t lut[kLutMax];
     const DevTables &t = a.tab;
+    for (uint32_t q = threadIdx.x; q < t.n_q; q += blockDim.x) lut[q] = t.mask_by_q[q];
+    __syncthreads();
     const int K = t.K, R = t.R;
     const bool l1 = t.metric == DBTSDF_DIST_L1;
     const uint32_t n_surv = a.ctrl->n_survivors;
@@ -498,24 +799,36 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_atomic(PipeArgs a, const C
     const bool lane_on = ri < rpi;
     const uint32_t rows = (uint32_t)(K * K);
     const uint32_t mag = ((1u << 20) + wx - 1u) / wx;
+    const int ox = (int)xi - R;
     for (uint32_t e = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); e < n_surv; e += waves) {
         const uint32_t i = a.survivors[e];
         const uint4 r = a.rec[i];
         const uint32_t s = find_scan(a.scans, info->n_scans, i);
         const DevGrid g = a.grids[a.scans[s].grid];
-        const int ox = (int)xi - R;
-        for (uint32_t r0 = 0; r0 < rows; r0 += rpi) {
-            const uint32_t rr = r0 + ri;
-            if (lane_on && rr < rows) {
-                const uint32_t rz = (rr * mag) >> 20;
-                const uint32_t ry = rr - rz * wx;
-                const int oy = (int)ry - R, oz = (int)rz - R;
-                const uint32_t q = l1 ? (uint32_t)(abs(ox) + abs(oy) + abs(oz)) : (uint32_t)(ox * ox + oy * oy + oz * oz);
-                const uint32_t m = t.mask_by_q[q];
-                const size_t lin = (size_t)(r.x + ox) + (size_t)g.nx * ((size_t)(r.y + oy) + (size_t)g.ny * (size_t)(r.z + oz));
-                const uint32_t old = g.mask[lin];
-                if ((old & m) != old) atomicAnd(&g.mask[lin], m);
+        for (uint32_t r0 = 0; r0 < rows; r0 += rpi * kAtomicBatch) {
+            uint32_t old[kAtomicBatch], m[kAtomicBatch];
+            size_t lin[kAtomicBatch];
+            bool on[kAtomicBatch];
+#pragma unroll
+            for (int u = 0; u < kAtomicBatch; ++u) {
+                const uint32_t rr = r0 + (uint32_t)u * rpi + ri;
+                on[u] = lane_on && rr < rows;
+                old[u] = 0u;
+                m[u] = 0u;
+                lin[u] = 0;
+                if (on[u]) {
+                    const uint32_t rz = (rr * mag) >> 20;
+                    const uint32_t ry = rr - rz * wx;
+                    const int oy = (int)ry - R, oz = (int)rz - R;
+                    const uint32_t q = l1 ? (uint32_t)(abs(ox) + abs(oy) + abs(oz)) : (uint32_t)(ox * ox + oy * oy + oz * oz);
+                    m[u] = lut[q];
+                    lin[u] = (size_t)(r.x + ox) + (size_t)g.nx * ((size_t)(r.y + oy) + (size_t)g.ny * (size_t)(r.z + oz));
+                    old[u] = g.mask[lin[u]];
+                }
             }
+#pragma unroll
+            for (int u = 0; u < kAtomicBatch; ++u)
+                if (on[u] && (old[u] & m[u]) != old[u]) atomicAnd(&g.mask[lin[u]], m[u]);
         }
         const uint32_t bin = r.w & 0xFFFFu;
         for (uint32_t j = t.sh_start[bin] + l; j < t.sh_start[bin + 1]; j += 64u) {
@@ -528,6 +841,99 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_atomic(PipeArgs a, const C
             const uint32_t raw = old & 0x7FFFFFFFu;
             if (raw >= g.hmax) atomicSub(&g.packed[lin], 1u);
             else if (g.T >= 1u && raw == g.T - 1u) atomicAnd(&g.packed[lin], 0x7FFFFFFFu);
+        }
+    }
+}
+
+// The same per-point update with the per-cell work moved into an LDS table.
+// A cell's eq. 3 mask and its signed offset in the grid's linear order do not
+// depend on the point, so each workgroup builds (offset, mask) for the K^3
+// cells of the current grid once; a point then costs, per cell, one LDS read,
+// one load from the point's base address and the read-first atomicAnd of
+// eq. 4 where the mask loses bits. The 26 cube bins' shadows are cell lists
+// in LDS as well; their counters take the guard-bit atomics of eqs. 5-6.
+constexpr int kCellTable = 1331;        // K <= 11
+constexpr int kShadowTable = 2048;      // r_s^2 <= 9: at most 76 cells per cube bin, 26 bins
+
+__global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const CallInfo *info) {
+    __shared__ int2 cells[kCellTable];          // (offset, mask)
+    __shared__ int sh_off[kShadowTable];        // grid offsets of the shadow cells
+    const DevTables &t = a.tab;
+    const int K = t.K, R = t.R, K3 = K * K * K;
+    const uint32_t l = lane();
+    const uint32_t n_sh = t.sh_start[t.n_bins];
+
+    const uint32_t n_surv = a.ctrl->n_survivors;
+    const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+    uint32_t cur_grid = 0xFFFFFFFFu;
+    DevGrid g{};
+    // every wave of the block walks its points in lock step with the others,
+    // so the table can be rebuilt (rarely: when the grid changes) under a barrier
+    const uint32_t first = blockIdx.x * (blockDim.x >> 6);
+    for (uint32_t e0 = first; e0 < n_surv; e0 += waves) {
+        const uint32_t e = e0 + (threadIdx.x >> 6);
+        const bool live = e < n_surv;
+        uint32_t i = 0, gi = 0;
+        uint4 r = make_uint4(0, 0, 0, 0);
+        if (live) {
+            i = a.survivors[e];
+            r = a.rec[i];
+            gi = a.scans[find_scan(a.scans, info->n_scans, i)].grid;
+        }
+        // the grid of the block's first live wave decides whether to rebuild
+        const uint32_t gblk = a.scans[find_scan(a.scans, info->n_scans, a.survivors[e0])].grid;
+        if (gblk != cur_grid) {
+            __syncthreads();
+            cur_grid = gblk;
+            const DevGrid gg = a.grids[gblk];
+            for (int c = threadIdx.x; c < K3; c += blockDim.x) {
+                const int ox = c % K - R, oy = (c / K) % K - R, oz = c / (K * K) - R;
+                const uint32_t q = t.metric == DBTSDF_DIST_L1 ? (uint32_t)(abs(ox) + abs(oy) + abs(oz))
+                                                              : (uint32_t)(ox * ox + oy * oy + oz * oz);
+                cells[c] = make_int2(ox + (int)gg.nx * (oy + (int)gg.ny * oz), (int)t.mask_by_q[q]);
+            }
+            for (uint32_t j = threadIdx.x; j < n_sh; j += blockDim.x) {
+                const int pk = (int)t.sh_off[j];
+                sh_off[j] = ((pk & 255) - R) + (int)gg.nx * (((pk >> 8) & 255) - R + (int)gg.ny * (((pk >> 16) & 255) - R));
+            }
+            __syncthreads();
+        }
+        if (!live) continue;
+        g = a.grids[gi];
+        const bool same = gi == cur_grid;
+        const size_t lin = (size_t)r.x + (size_t)g.nx * ((size_t)r.y + (size_t)g.ny * (size_t)r.z);
+        uint32_t *mb = g.mask + lin;
+        uint32_t *pb = g.packed + lin;
+        for (int c = (int)l; c < K3; c += 64) {
+            int o;
+            uint32_t m;
+            if (same) {
+                const int2 cm = cells[c];
+                o = cm.x;
+                m = (uint32_t)cm.y;
+            } else {  // a wave whose point is in another grid than the table's
+                const int ox = c % K - R, oy = (c / K) % K - R, oz = c / (K * K) - R;
+                o = ox + (int)g.nx * (oy + (int)g.ny * oz);
+                const uint32_t q = t.metric == DBTSDF_DIST_L1 ? (uint32_t)(abs(ox) + abs(oy) + abs(oz))
+                                                              : (uint32_t)(ox * ox + oy * oy + oz * oz);
+                m = t.mask_by_q[q];
+            }
+            const uint32_t old = mb[o];
+            if ((old & m) != old) atomicAnd(mb + o, m);
+        }
+        const uint32_t bin = r.w & 0xFFFFu;
+        for (uint32_t j = t.sh_start[bin] + l; j < t.sh_start[bin + 1]; j += 64u) {
+            int o;
+            if (same) {
+                o = sh_off[j];
+            } else {
+                const int pk = (int)t.sh_off[j];
+                o = ((pk & 255) - R) + (int)g.nx * (((pk >> 8) & 255) - R + (int)g.ny * (((pk >> 16) & 255) - R));
+            }
+            const uint32_t ov = atomicAdd(pb + o, 1u);
+            const uint32_t raw = ov & 0x7FFFFFFFu;
+            if (raw >= g.hmax) atomicSub(pb + o, 1u);
+            else if (g.T >= 1u && raw == g.T - 1u) atomicAnd(pb + o, 0x7FFFFFFFu);
         }
     }
 }
@@ -634,23 +1040,29 @@ hipError_t launch_count_diff(const uint32_t *a, const uint32_t *b, uint64_t n, u
 }
 
 // --------------------------------------------------------- apply dispatch ---
-#define DBTSDF_BRICKS(X)     \
-    X(32, 16, 8, 256)        \
-    X(32, 16, 8, 512)        \
-    X(32, 16, 16, 256)       \
-    X(32, 16, 16, 512)       \
-    X(32, 32, 16, 512)       \
-    X(64, 16, 8, 256)        \
-    X(64, 16, 8, 512)        \
-    X(32, 8, 8, 256)         \
-    X(16, 16, 16, 256)       \
-    X(16, 16, 8, 256)
+#define DBTSDF_BRICKS(X) \
+    X(16, 8, 8, 256)     \
+    X(32, 8, 8, 256)     \
+    X(64, 8, 8, 256)     \
+    X(16, 16, 8, 256)    \
+    X(32, 16, 8, 256)    \
+    X(32, 16, 8, 512)    \
+    X(64, 16, 8, 512)    \
+    X(32, 16, 16, 512)
 
 typedef void (*apply_fn)(PipeArgs);
 
-static apply_fn find_apply(const Tuning &t) {
-#define X(BX_, BY_, BZ_, TH_) \
-    if (t.bx == BX_ && t.by == BY_ && t.bz == BZ_ && t.threads == TH_) return k_apply_brick<BX_, BY_, BZ_, TH_>;
+// kernel radius 5 (K = 11) and 10 (K = 21, the paper's size) have unrolled
+// rows; any other radius takes the generic variant
+static apply_fn find_apply(const Tuning &t, int R) {
+#define X(BX_, BY_, BZ_, TH_)                                                           \
+    if (t.bx == BX_ && t.by == BY_ && t.bz == BZ_ && t.threads == TH_) {                \
+        constexpr int mr = max_radius(BX_, BY_, BZ_);                                   \
+        if (R == 5 && 5 <= mr) return k_apply_brick<BX_, BY_, BZ_, TH_, 5>;             \
+        if (R == 10 && 10 <= mr) return k_apply_brick<BX_, BY_, BZ_, TH_, 10>;          \
+        if (R <= mr) return k_apply_brick<BX_, BY_, BZ_, TH_, 0>;                       \
+        return nullptr;                                                                 \
+    }
     DBTSDF_BRICKS(X)
 #undef X
     return nullptr;
@@ -659,19 +1071,20 @@ static apply_fn find_apply(const Tuning &t) {
 bool tuning_supported(const Tuning &t, int K) {
     if (t.strategy == DBTSDF_STRATEGY_ATOMIC) return t.threads >= 64 && t.threads <= 1024 && (t.threads % 64) == 0;
     if (t.strategy != DBTSDF_STRATEGY_BRICK) return false;
-    (void)K;
-    return find_apply(t) != nullptr;
+    return find_apply(t, (K - 1) / 2) != nullptr;
 }
 
-int apply_blocks_default(const Tuning &t, int device) {
+int apply_blocks_default(const Tuning &t, int K, int device) {
     int cus = 256;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) cus = 256;
     if (t.strategy == DBTSDF_STRATEGY_ATOMIC) return cus * 8;
-    const size_t lds = (size_t)t.bx * t.by * t.bz * 8 + 4 * 1024;
-    int per_cu = (int)((160 * 1024) / lds);
-    const int by_threads = 2048 / (int)t.threads;
-    if (per_cu > by_threads) per_cu = by_threads;
-    if (per_cu < 1) per_cu = 1;
+    // a persistent grid must be fully resident: blocks per CU from the
+    // kernel's real register and LDS use
+    int per_cu = 0;
+    apply_fn f = find_apply(t, (K - 1) / 2);
+    if (!f || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(f),
+                                                           (int)t.threads, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
     return cus * per_cu;
 }
 
@@ -679,21 +1092,33 @@ hipError_t launch_pipeline(const PipeArgs &a, const Tuning &t, uint32_t points_c
                            hipEvent_t ev_apply0, hipEvent_t ev_apply1) {
     const CallInfo *info = reinterpret_cast<const CallInfo *>(a.ctrl + 1);
     const uint32_t pb = blocks_for(points_cap, kPtThreads, 4096);
+    const uint32_t sb = blocks_for(points_cap, kSelThreads, 1024);
+    uint32_t stat_chunk = 1024;
+    while ((uint64_t)stat_chunk * 512 < points_cap) stat_chunk *= 2;
     k_reset<<<8, 256, 0, st>>>(a, info);
     k_front<<<pb, kPtThreads, 0, st>>>(a, info);
     if (t.strategy == DBTSDF_STRATEGY_ATOMIC) {
-        k_select_atomic<<<pb, kPtThreads, 0, st>>>(a, info);
+        k_select_atomic<<<sb, kSelThreads, 0, st>>>(a, info);
+        k_stats<<<blocks_for(points_cap, stat_chunk, 512), kPtThreads, 0, st>>>(a, info, stat_chunk);
         if (ev_apply0) (void)hipEventRecord(ev_apply0, st);
-        k_apply_atomic<<<t.apply_blocks, kPtThreads, 0, st>>>(a, info);
+        // the LDS cell table covers K <= 11 and cube shadows with r_s^2 <= 9;
+        // other kernel sets and grids whose offsets overflow 32 bits take the
+        // generic per-row kernel
+        const int K3 = a.tab.K * a.tab.K * a.tab.K;
+        if (a.small_offsets && K3 <= kCellTable && a.tab.n_bins == 26 && a.tab.shadow_r2 <= 9)
+            k_apply_points<<<t.apply_blocks, kPtThreads, 0, st>>>(a, info);
+        else
+            k_apply_atomic<<<t.apply_blocks, kPtThreads, 0, st>>>(a, info);
         if (ev_apply1) (void)hipEventRecord(ev_apply1, st);
         k_clear_hash<<<pb, kPtThreads, 0, st>>>(a, info);
         return hipGetLastError();
     }
-    apply_fn f = find_apply(t);
+    apply_fn f = find_apply(t, a.tab.R);
     if (!f) return hipErrorInvalidValue;
-    k_select_brick<<<pb, kPtThreads, 0, st>>>(a, info);
-    k_offsets<<<blocks_for(a.items_cap, kPtThreads, 1024), kPtThreads, 0, st>>>(a);
-    k_fill<<<pb, kPtThreads, 0, st>>>(a, info);
+    k_select_pairs<<<sb, kSelThreads, 0, st>>>(a, info);
+    k_stats<<<blocks_for(points_cap, stat_chunk, 512), kPtThreads, 0, st>>>(a, info, stat_chunk);
+    k_offsets<<<blocks_for(points_cap, kPtThreads, 256), kPtThreads, 0, st>>>(a);
+    k_fill_pairs<<<pb, kPtThreads, 0, st>>>(a, info);
     if (ev_apply0) (void)hipEventRecord(ev_apply0, st);
     hipLaunchKernelGGL(f, dim3(t.apply_blocks), dim3(t.threads), 0, st, a);
     if (ev_apply1) (void)hipEventRecord(ev_apply1, st);

@@ -64,7 +64,9 @@ struct Workspace {
     unsigned long long *hkeys = nullptr;
     uint32_t *hvals = nullptr;
     unsigned long long *items = nullptr;
-    uint32_t *item_off = nullptr, *item_cur = nullptr, *entries = nullptr, *survivors = nullptr;
+    uint32_t *item_off = nullptr, *item_cnt = nullptr, *entries = nullptr, *survivors = nullptr;
+    uint32_t *rank = nullptr;
+    uint2 *work = nullptr;
     unsigned long long *ctr = nullptr;   // scan counters then traffic counters
     float *staging = nullptr;            // device copy of host points
     size_t staging_cap = 0;              // floats

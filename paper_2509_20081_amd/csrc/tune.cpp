@@ -22,9 +22,8 @@ struct Scratch {
 };
 
 std::vector<Tuning> candidates(int K) {
-    static const uint32_t shapes[][4] = {{32, 16, 8, 256}, {32, 16, 8, 512}, {32, 16, 16, 256}, {32, 16, 16, 512},
-                                         {64, 16, 8, 256}, {64, 16, 8, 512}, {16, 16, 16, 256}, {16, 16, 8, 256},
-                                         {32, 8, 8, 256},  {32, 32, 16, 512}};
+    static const uint32_t shapes[][4] = {{16, 8, 8, 256},  {32, 8, 8, 256},  {64, 8, 8, 256},  {16, 16, 8, 256},
+                                         {32, 16, 8, 256}, {32, 16, 8, 512}, {64, 16, 8, 512}, {32, 16, 16, 512}};
     std::vector<Tuning> out;
     for (auto &s : shapes) {
         Tuning t;
@@ -96,6 +95,7 @@ extern "C" dbtsdf_status dbtsdf_autotune(dbtsdf_grid *g, uint32_t n_scans, const
         ct.brick[2] = c.bz ? c.bz : g->tuning.bz;
         ct.block_threads = c.threads;
         ct.apply_blocks = 0;
+        ct.chunk = c.chunk ? c.chunk : 0xFFFFFFFFu;
         if (dbtsdf_set_tuning(tmp, &ct) != DBTSDF_OK) continue;
         float ms = 0.0f;
         for (int rep = 0; rep < 2 && result == DBTSDF_OK; ++rep) {  // rep 0 warms up allocations
@@ -155,6 +155,7 @@ extern "C" dbtsdf_status dbtsdf_autotune(dbtsdf_grid *g, uint32_t n_scans, const
     bt.brick[2] = best_t.bz;
     bt.block_threads = best_t.threads;
     bt.apply_blocks = 0;
+    bt.chunk = best_t.chunk ? best_t.chunk : 0xFFFFFFFFu;
     rs = dbtsdf_set_tuning(g, &bt);
     if (rs != DBTSDF_OK) return rs;
     if (best) *best = bt;

@@ -57,22 +57,31 @@ TINY_CASES = [
 ]
 
 TUNINGS = [
-    dict(strategy="brick", brick=(32, 16, 8), block_threads=256),
+    dict(strategy="brick", brick=(32, 8, 8), block_threads=256),
     dict(strategy="brick", brick=(16, 16, 8), block_threads=256),
     dict(strategy="brick", brick=(64, 16, 8), block_threads=512),
-    dict(strategy="brick", brick=(32, 8, 8), block_threads=256, apply_blocks=7),
+    dict(strategy="brick", brick=(16, 8, 8), block_threads=256, apply_blocks=7),
+    dict(strategy="brick", brick=(32, 16, 8), block_threads=256, chunk=3),      # many split bricks
+    dict(strategy="brick", brick=(32, 16, 16), block_threads=512, chunk=None),  # never split
     dict(strategy="atomic", block_threads=256),
 ]
 
 
 @pytest.mark.parametrize("case", TINY_CASES, ids=lambda c: f"seed{c['seed']}_K{c['K']}_{c['binning']}")
-@pytest.mark.parametrize("tuning", TUNINGS, ids=lambda t: f"{t['strategy']}{t.get('brick', '')}")
+@pytest.mark.parametrize("tuning", TUNINGS,
+                         ids=lambda t: f"{t['strategy']}{t.get('brick', '')}_c{t.get('chunk', 'd')}")
 def test_tiny_grids_match_oracle(db, case, tuning):
     case = dict(case)
     seed, K, dims = case.pop("seed"), case.pop("K"), case.pop("dims")
-    traffic = tuning["strategy"] == "brick"
+    # unique-word counters are exact only when no brick is split over work units
+    traffic = tuning["strategy"] == "brick" and "chunk" not in tuning
     o, g, _ = P.make_pair(dims, 1.0, (0.0, 0.0, 0.0), count_traffic=traffic, kernel_size=K, **case)
-    g.set_tuning(**tuning)
+    try:
+        g.set_tuning(**tuning)
+    except db.DbtsdfError:
+        # documented: the largest brick shapes cannot hold the tiles for K = 37
+        assert K == 37 and tuning["brick"] == (32, 16, 16)
+        pytest.skip("brick shape too small in LDS for this kernel radius")
     m, p = o.new_grid()
     for i, (pose, pts) in enumerate(tiny_scans(seed, K, dims)):
         ref = o.integrate(m, p, pose, pts, count_traffic=traffic)
@@ -409,5 +418,7 @@ def test_argument_errors_leave_grid_unchanged(db):
         db.Grid(dims, 1.0, (0, 0, 0), ks, hit_max=0)
     with pytest.raises(db.DbtsdfError):
         g.set_tuning(strategy="brick", brick=(48, 16, 8))
+    with pytest.raises(db.DbtsdfError):
+        g.set_tuning(strategy="brick", brick=(32, 8, 8), block_threads=512)
     gm, gp = P.gpu_planes(g)
     assert np.all(gm == 0xFFFFFFFF) and np.all(gp == 0x80000000)
