@@ -103,7 +103,8 @@ class KernelSet:
                  shadow_r2: int = 9, metric: str = "l2"):
         p = L.KernelParams(kernel_size, _BINNING[binning], bins_az, bins_el, shadow_r2, _METRIC[metric])
         h = C.c_void_p()
-        L.check(L.lib().dbtsdf_kernel_set_create(C.byref(p), C.byref(h)), "kernel_set_create")
+        self._lib = L.lib()  # held so that destruction at interpreter exit still finds it
+        L.check(self._lib.dbtsdf_kernel_set_create(C.byref(p), C.byref(h)), "kernel_set_create")
         self._h = h
         self.kernel_size = kernel_size
         self.binning = binning
@@ -126,9 +127,9 @@ class KernelSet:
         return int(L.lib().dbtsdf_kernel_set_bin(self._h, C.c_float(d[0]), C.c_float(d[1]), C.c_float(d[2])))
 
     def __del__(self):
-        h = getattr(self, "_h", None)
-        if h and L._lib is not None:
-            L._lib.dbtsdf_kernel_set_destroy(h)
+        h, lib = getattr(self, "_h", None), getattr(self, "_lib", None)
+        if h and lib is not None:
+            lib.dbtsdf_kernel_set_destroy(h)
             self._h = None
 
 
@@ -167,6 +168,7 @@ class Grid:
         self._pending = []
         self.mask_tensor = self.packed_tensor = None
         self._owned = _handle is None
+        self._lib = L.lib()
         if _handle is not None:
             self._h = _handle
             return
@@ -273,9 +275,9 @@ class Grid:
         return m.value, p.value
 
     def close(self) -> None:
-        h = getattr(self, "_h", None)
-        if h and self._owned and L._lib is not None:
-            L._lib.dbtsdf_destroy_grid(h)
+        h, lib = getattr(self, "_h", None), getattr(self, "_lib", None)
+        if h and self._owned and lib is not None:
+            lib.dbtsdf_destroy_grid(h)
         self._h = None
 
     def __del__(self):
@@ -288,7 +290,8 @@ class Batch:
     def __init__(self, stream=None, use_graph=True):
         h = C.c_void_p()
         st = C.c_void_p(stream) if stream is not None else C.c_void_p(None)
-        L.check(L.lib().dbtsdf_batch_create(st, 1 if use_graph else 0, C.byref(h)), "batch_create")
+        self._lib = L.lib()
+        L.check(self._lib.dbtsdf_batch_create(st, 1 if use_graph else 0, C.byref(h)), "batch_create")
         self._h = h
         self._keep = []
 
@@ -332,9 +335,9 @@ class Batch:
         return int(c.value), int(r.value)
 
     def close(self):
-        h = getattr(self, "_h", None)
-        if h and L._lib is not None:
-            L._lib.dbtsdf_batch_destroy(h)
+        h, lib = getattr(self, "_h", None), getattr(self, "_lib", None)
+        if h and lib is not None:
+            lib.dbtsdf_batch_destroy(h)
         self._h = None
 
     def __del__(self):

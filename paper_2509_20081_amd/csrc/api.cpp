@@ -98,7 +98,8 @@ void Workspace::release() {
     hkeys = nullptr;
     hvals = nullptr;
     items = nullptr;
-    item_off = item_cnt = entries = survivors = rank = nullptr;
+    item_off = item_cnt = survivors = rank = nullptr;
+    entries = nullptr;
     work = nullptr;
     ctr = nullptr;
     staging = nullptr;
@@ -156,9 +157,9 @@ hipError_t Workspace::ensure(uint32_t n_points, uint32_t n_scans, uint32_t n_gri
         {(void **)&items, (size_t)items_cap * 8},
         {(void **)&item_off, (size_t)items_cap * 4},
         {(void **)&item_cnt, (size_t)items_cap * 4},
-        {(void **)&entries, (size_t)entries_cap * 4},
+        {(void **)&entries, (size_t)entries_cap * sizeof(uint4)},
         {(void **)&rank, (size_t)entries_cap * 4},
-        {(void **)&work, ((size_t)items_cap + entries_cap) * sizeof(uint2)},
+        {(void **)&work, ((size_t)items_cap + entries_cap) * sizeof(uint4)},
         {(void **)&survivors, (size_t)points_cap * 4},
         {(void **)&ctr, ctr_words * 8},
     };
@@ -192,16 +193,24 @@ hipError_t Workspace::ensure_staging(size_t floats, hipStream_t st) {
 
 RingSlot &Workspace::next_slot(size_t bytes, std::string *err) {
     constexpr uint32_t kRing = 16;
-    if (ring.size() < kRing) ring.resize(kRing);
+    if (ring.size() < kRing) {
+        // allocate every slot up front: pinned allocations are slow and must
+        // not land in the middle of a run of calls
+        ring.resize(kRing);
+        for (RingSlot &r : ring) {
+            if (!r.ev) (void)hipEventCreateWithFlags(&r.ev, hipEventDisableTiming);
+            for (hipEvent_t &e : r.pe)
+                if (!e) (void)hipEventCreate(&e);
+            const size_t want = std::max<size_t>(bytes, 64 * 1024);
+            if (!r.host && hipHostMalloc(&r.host, want, hipHostMallocDefault) == hipSuccess) r.bytes = want;
+        }
+    }
     RingSlot &s = ring[ring_next];
     ring_next = (ring_next + 1) % kRing;
     if (s.busy) {
         (void)hipEventSynchronize(s.ev);
         deliver(s);
     }
-    if (!s.ev) (void)hipEventCreateWithFlags(&s.ev, hipEventDisableTiming);
-    for (hipEvent_t &e : s.pe)
-        if (!e) (void)hipEventCreate(&e);
     if (s.bytes < bytes) {
         if (s.host) (void)hipHostFree(s.host);
         s.host = nullptr;

@@ -114,9 +114,9 @@ struct PipeArgs {
     unsigned long long *items;  // active (grid << 32 | brick)
     uint32_t *item_off;      // first entry of each active brick
     uint32_t *item_cnt;      // entries of each active brick
-    uint32_t *entries;       // point indices, grouped by brick
+    uint4 *entries;          // (voxel x, y, z, bin) of the listed points, grouped by brick
     uint32_t *rank;          // per (point, brick) pair: position in the brick's list
-    uint2 *work;             // apply work units: (item, sub | split << 31)
+    uint4 *work;             // apply work units: (brick, grid, first entry, count | split << 31)
     uint32_t *survivors;     // compacted survivor list (atomic strategy)
     unsigned long long *scan_ctr;     // n_scans * SC_N
     unsigned long long *traffic_ctr;  // n_grids * TC_N

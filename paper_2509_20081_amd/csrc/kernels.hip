@@ -178,7 +178,7 @@ __device__ __forceinline__ uint32_t front_end(const DevScan &s, const DevGrid &g
 
 // ================================================================ passes ===
 constexpr int kPtThreads = 256;
-constexpr int kSelThreads = 1024;   // one claim atomic per block of pairs
+constexpr int kSelThreads = 256;    // one claim atomic per block of points
 
 __global__ void k_reset(PipeArgs a, const CallInfo *info) {
     const uint32_t n_sc = info->n_scans * SC_N, n_tc = info->n_grids * TC_N;
@@ -421,10 +421,16 @@ __global__ __launch_bounds__(kPtThreads) void k_offsets(PipeArgs a) {
         if (lane() == 63u) sbase = atomicAdd(&a.ctrl->n_work, sincl);
         sbase = __shfl(sbase, 63, 64);
         if (t < n) {
-            a.item_off[t] = wbase + incl - cnt;
+            const unsigned long long it = a.items[t];
+            const uint32_t first = wbase + incl - cnt;
+            a.item_off[t] = first;
             a.item_cnt[t] = cnt;
             const uint32_t split = nsub > 1u ? 0x80000000u : 0u;
-            for (uint32_t k = 0; k < nsub; ++k) a.work[sbase + sincl - nsub + k] = make_uint2(t, k | split);
+            for (uint32_t k = 0; k < nsub; ++k) {
+                const uint32_t s0 = a.chunk ? k * a.chunk : 0u;
+                const uint32_t c0 = a.chunk ? min(a.chunk, cnt - s0) : cnt;
+                a.work[sbase + sincl - nsub + k] = make_uint4((uint32_t)it, (uint32_t)(it >> 32), first + s0, c0 | split);
+            }
         }
     }
 }
@@ -443,10 +449,19 @@ __global__ __launch_bounds__(kPtThreads) void k_fill_pairs(PipeArgs a, const Cal
         }
         if (!(r.w & kRecSurvivor)) continue;
         const DevGrid &g = a.grids[a.scans[find_scan(a.scans, info->n_scans, i)].grid];
-        for (uint32_t j = 0; j < F; ++j) {
-            uint32_t id;
-            if (!pair_brick(a, r, j, g, id)) continue;
-            a.entries[a.item_off[g.brick_slot[id]] + a.rank[(size_t)i * F + j]] = i;
+        for (uint32_t j0 = 0; j0 < F; j0 += kSelUnroll) {
+            uint32_t item[kSelUnroll], rk[kSelUnroll];
+            bool v[kSelUnroll];
+#pragma unroll
+            for (int u = 0; u < kSelUnroll; ++u) {  // independent loads, all in flight
+                uint32_t id = 0;
+                v[u] = j0 + u < F && pair_brick(a, r, j0 + u, g, id);
+                item[u] = v[u] ? g.brick_slot[id] : 0u;
+                rk[u] = v[u] ? a.rank[(size_t)i * F + j0 + u] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < kSelUnroll; ++u)
+                if (v[u]) a.entries[a.item_off[item[u]] + rk[u]] = make_uint4(r.x, r.y, r.z, r.w & 0xFFFFu);
         }
     }
 }
@@ -513,18 +528,36 @@ __global__ __launch_bounds__(THREADS) void k_apply_brick(PipeArgs a) {
     const uint32_t n_work = a.ctrl->n_work;
     const uint32_t w = threadIdx.x >> 6, l = lane();
 
+    // shadow ball radius, clipped to the kernel window: rows with |dy|, |dz| <= rs
+    // can hold shadow cells
+    int rs = 0;
+    while (r2 >= 0 && rs < R && (rs + 1) * (rs + 1) <= r2) ++rs;
+
     for (uint32_t wi = blockIdx.x; wi < n_work; wi += gridDim.x) {
-        const uint2 wk = a.work[wi];
-        const uint32_t item = wk.x, sub = wk.y & 0x7FFFFFFFu;
-        const bool split = (wk.y >> 31) != 0u;
-        const unsigned long long it = a.items[item];
-        const DevGrid g = a.grids[it >> 32];
-        const uint32_t brick = (uint32_t)it;
+        const uint4 wk = a.work[wi];
+        const uint32_t brick = wk.x;
+        const bool split = (wk.w >> 31) != 0u;
+        const DevGrid g = a.grids[wk.y];
         const uint32_t bxi = brick % g.nbx, byi = (brick / g.nbx) % g.nby, bzi = brick / (g.nbx * g.nby);
         const int x0 = (int)bxi * BX, y0 = (int)byi * BY, z0 = (int)bzi * BZ;
-        const uint32_t all = a.item_cnt[item];
-        const uint32_t start = a.item_off[item] + (split ? sub * a.chunk : 0u);
-        const uint32_t cnt = split ? min(a.chunk, all - sub * a.chunk) : all;
+        const uint32_t start = wk.z;
+        const uint32_t cnt = wk.w & 0x7FFFFFFFu;
+
+        // the merge's mask loads are issued now, so that staging and stamping
+        // hide their latency
+        const bool vec_x = (g.nx & 3u) == 0;
+        uint4 pm[NQ];
+        bool fastq[NQ];
+        size_t linq[NQ];
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            const int v = 4 * ((int)threadIdx.x + k * THREADS);
+            const uint32_t gx = (uint32_t)(x0 + v % BX), gy = (uint32_t)(y0 + (v / BX) % BY),
+                           gz = (uint32_t)(z0 + v / (BX * BY));
+            linq[k] = (size_t)gx + (size_t)g.nx * ((size_t)gy + (size_t)g.ny * gz);
+            fastq[k] = !split && vec_x && gx + 3u < g.nx && gy < g.ny && gz < g.nz;
+            if (fastq[k]) pm[k] = *reinterpret_cast<const uint4 *>(g.mask + linq[k]);
+        }
 
         for (int q = threadIdx.x; q < TILE / 4; q += THREADS) {
             reinterpret_cast<uint4 *>(tmask)[q] = make_uint4(~0u, ~0u, ~0u, ~0u);
@@ -534,7 +567,7 @@ __global__ __launch_bounds__(THREADS) void k_apply_brick(PipeArgs a) {
             const uint32_t nb = min(cnt - base, (uint32_t)kStage);
             __syncthreads();  // tile init done / previous round's readers done
             for (uint32_t e = threadIdx.x; e < nb; e += THREADS) {
-                const uint4 r = a.rec[a.entries[start + base + e]];
+                const uint4 r = a.entries[start + base + e];
                 const int lx = (int)r.x - x0, ly = (int)r.y - y0, lz = (int)r.z - z0;
                 const int ya = max(ly - R, 0), yb = min(ly + R, BY - 1);
                 const int za = max(lz - R, 0), zb = min(lz + R, BZ - 1);
@@ -542,7 +575,7 @@ __global__ __launch_bounds__(THREADS) void k_apply_brick(PipeArgs a) {
                 // x: tile column of the cube's first cell; y, z: first row and the point
                 ent[e] = make_uint4((uint32_t)(lx - R + HX) | ((uint32_t)ya << 12) | ((uint32_t)za << 22),
                                     (uint32_t)(ly + 64) | ((uint32_t)(lz + 64) << 8) | (wy << 16) | (rows << 22),
-                                    r.w & 0xFFFFu, __float_as_uint(1.0f / (float)wy));
+                                    r.w, __float_as_uint(1.0f / (float)wy));
             }
             __syncthreads();
             for (uint32_t e = w; e < nb; e += WAVES) {
@@ -581,26 +614,34 @@ __global__ __launch_bounds__(THREADS) void k_apply_brick(PipeArgs a) {
                         const int c1 = abs(oy) + abs(oz);
                         for (int k = 0; k < 2 * R + 1; ++k) atomicAnd(&tmask[row + k], lut[c1 + abs(k - R)]);
                     }
-                    if (cube && c2 <= r2) {
-                        // shadow cells of the row: |dx| <= floor(sqrt(r2 - c2)) (ball) and
-                        // dx * sx >= -(dy * sy + dz * sz) (back half-space): an interval
-                        int m = 0;
-                        while ((m + 1) * (m + 1) <= r2 - c2) ++m;
-                        const int dyz = oy * syv + oz * szv;
-                        int lo = -m, hi = m;
-                        if (sxv > 0) lo = max(lo, -dyz);
-                        else if (sxv < 0) hi = min(hi, dyz);
-                        else if (dyz < 0) hi = lo - 1;
-                        lo = max(lo, -R);
-                        hi = min(hi, R);
-                        if (lo <= hi) {
-                            if constexpr (RR > 0) {
-                                const uint32_t bits = ((2u << (hi - lo)) - 1u) << (lo + RR);
-#pragma unroll
-                                for (int k = 0; k < 2 * RR + 1; ++k) atomicAdd(&tcnt[row + k], (bits >> k) & 1u);
-                            } else {
-                                for (int ox = lo; ox <= hi; ++ox) atomicAdd(&tcnt[row + ox + R], 1u);
-                            }
+                }
+                if (cube && r2 >= 0) {
+                    // shadow: only the rows of the r_s ball, and only when the ball
+                    // reaches into the brick
+                    const int lxb = cx + R - HX;  // brick-local x of the point
+                    const int sya = max(ly - rs, 0), syb = min(ly + rs, BY - 1);
+                    const int sza = max(lz - rs, 0), szb = min(lz + rs, BZ - 1);
+                    if (sya <= syb && sza <= szb && lxb - rs <= BX - 1 && lxb + rs >= 0) {
+                        const int swy = syb - sya + 1;
+                        const int srows = swy * (szb - sza + 1);
+                        const float rsw = 1.0f / (float)swy;
+                        for (int sr = (int)l; sr < srows; sr += 64) {
+                            const int srz = (int)(((float)sr + 0.5f) * rsw);
+                            const int yy = sya + (sr - srz * swy), zz = sza + srz;
+                            const int oy = yy - ly, oz = zz - lz;
+                            const int c2 = oy * oy + oz * oz;
+                            if (c2 > r2) continue;
+                            int m = 0;
+                            while (m < R && (m + 1) * (m + 1) <= r2 - c2) ++m;
+                            const int dyz = oy * syv + oz * szv;
+                            int lo = -m, hi = m;
+                            if (sxv > 0) lo = max(lo, -dyz);
+                            else if (sxv < 0) hi = min(hi, dyz);
+                            else if (dyz < 0) hi = lo - 1;
+                            lo = max(lo, -lxb);
+                            hi = min(hi, BX - 1 - lxb);
+                            const int rowp = cx + R + PX * (yy + BY * zz);  // tile index of the point's column
+                            for (int ox = lo; ox <= hi; ++ox) atomicAdd(&tcnt[rowp + ox], 1u);
                         }
                     }
                 }
@@ -622,7 +663,6 @@ __global__ __launch_bounds__(THREADS) void k_apply_brick(PipeArgs a) {
 
         // merge the brick interior into HBM, NB quads in flight per thread
         uint32_t um = 0, cm = 0, us = 0;
-        const bool vec_x = (g.nx & 3u) == 0;
 #pragma unroll
         for (int k0 = 0; k0 < NQ; k0 += NB) {
             uint32_t sm[NB][4], sc[NB][4];
@@ -645,10 +685,9 @@ __global__ __launch_bounds__(THREADS) void k_apply_brick(PipeArgs a) {
                 }
                 need_m[k] = any_m;
                 need_c[k] = any_c;
-                const uint32_t gx = (uint32_t)(x0 + xl), gy = (uint32_t)(y0 + yl), gz = (uint32_t)(z0 + zl);
-                lin[k] = (size_t)gx + (size_t)g.nx * ((size_t)gy + (size_t)g.ny * gz);
-                fast[k] = !split && vec_x && gx + 3u < g.nx && gy < g.ny && gz < g.nz;
-                if (fast[k] && any_m) om[k] = *reinterpret_cast<const uint4 *>(g.mask + lin[k]);
+                lin[k] = linq[k0 + k];
+                fast[k] = fastq[k0 + k];
+                om[k] = pm[k0 + k];
                 if (fast[k] && any_c) op[k] = *reinterpret_cast<const uint4 *>(g.packed + lin[k]);
             }
 #pragma unroll

@@ -64,9 +64,10 @@ struct Workspace {
     unsigned long long *hkeys = nullptr;
     uint32_t *hvals = nullptr;
     unsigned long long *items = nullptr;
-    uint32_t *item_off = nullptr, *item_cnt = nullptr, *entries = nullptr, *survivors = nullptr;
+    uint32_t *item_off = nullptr, *item_cnt = nullptr, *survivors = nullptr;
+    uint4 *entries = nullptr;
     uint32_t *rank = nullptr;
-    uint2 *work = nullptr;
+    uint4 *work = nullptr;
     unsigned long long *ctr = nullptr;   // scan counters then traffic counters
     float *staging = nullptr;            // device copy of host points
     size_t staging_cap = 0;              // floats

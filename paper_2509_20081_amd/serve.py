@@ -20,7 +20,8 @@ class Server:
         cfg = L.ServerConfig(n_streams, max_batch_scans, max_batch_points, memory_budget, queue_capacity,
                              1 if use_graph else 0)
         h = C.c_void_p()
-        L.check(L.lib().dbtsdf_server_create(C.byref(cfg), C.byref(h)), "server_create")
+        self._lib = L.lib()
+        L.check(self._lib.dbtsdf_server_create(C.byref(cfg), C.byref(h)), "server_create")
         self._h = h
         self._kernel_sets = []
 
@@ -83,9 +84,9 @@ class Server:
         return int(a.value), int(b.value)
 
     def close(self):
-        h = getattr(self, "_h", None)
-        if h and L._lib is not None:
-            L._lib.dbtsdf_server_destroy(h)
+        h, lib = getattr(self, "_h", None), getattr(self, "_lib", None)
+        if h and lib is not None:
+            lib.dbtsdf_server_destroy(h)
         self._h = None
 
     def __del__(self):
