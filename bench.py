@@ -303,7 +303,7 @@ def main():
     call_ms = prof["call_ms"] / max(prof["calls"], 1)
     achieved = apply_bytes / (apply_ms * 1e-3) / 1e9
     kname = (f"k_apply_brick<{tuning['brick'][0]},{tuning['brick'][1]},{tuning['brick'][2]},"
-             f"{tuning['block_threads']}>" if tuning["strategy"] == "brick" else "k_apply_points")
+             f"{tuning['block_threads']}>" if tuning["strategy"] == "brick" else "k_apply_points<true>")
     traffic = None
     tfile = os.path.join(ROOT, "profiles", f"traffic_c{cfg}.json")
     if os.path.exists(tfile):

@@ -314,7 +314,7 @@ static std::string graph_key(const PipeArgs &a, const Tuning &t, uint32_t cap) {
     return k;
 }
 
-dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &scans, bool use_graph) {
+dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &scans, bool use_graph, bool plain) {
     // drop empty scans (their statistics are all zero)
     std::vector<ScanIn> live;
     for (ScanIn &s : scans) {
@@ -467,6 +467,8 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
     }
     // exact unique-word counts need every brick merged by one work unit
     a.chunk = traffic ? 0u : tun.chunk;
+    // the plain one-scan call has a kernel of its own (no per-point scan lookup)
+    a.single_scan = plain && live.size() == 1 ? 1u : 0u;
     a.small_offsets = 1u;
     for (dbtsdf_grid *g : grids) {
         const uint64_t span = (uint64_t)R * (1ull + g->params.dims[0] + (uint64_t)g->params.dims[0] * g->params.dims[1]);
@@ -732,7 +734,7 @@ dbtsdf_status dbtsdf_integrate_scan(dbtsdf_grid *g, const float pose[16], const 
         dev = g->ws->staging;
     }
     std::vector<ScanIn> v{ScanIn{g, pose, dev, n, stats}};
-    return enqueue_scans(*g->ws, g->stream, v, false);
+    return enqueue_scans(*g->ws, g->stream, v, false, true);
 }
 
 dbtsdf_status dbtsdf_sync(dbtsdf_grid *g) {
@@ -929,7 +931,7 @@ dbtsdf_status dbtsdf_batch_integrate(dbtsdf_batch *b, uint32_t n_scans, dbtsdf_g
         v[i] = ScanIn{grids[i], poses + 16 * (size_t)i, dev, n[i], stats ? &stats[i] : nullptr};
         off += n[i];
     }
-    dbtsdf_status s = enqueue_scans(*b->ws, b->stream, v, b->use_graph && b->stream != nullptr);
+    dbtsdf_status s = enqueue_scans(*b->ws, b->stream, v, b->use_graph && b->stream != nullptr, false);
     if (s != DBTSDF_OK) return s;
     hipError_t e = hipEventRecord(b->ev, b->stream);
     for (dbtsdf_grid *g : distinct)

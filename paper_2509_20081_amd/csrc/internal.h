@@ -126,7 +126,8 @@ struct PipeArgs {
     uint32_t count_traffic;
     uint32_t span[3];        // most bricks a K^3 cube can touch per axis
     uint32_t chunk;          // listed points per apply work unit (0 = never split a brick)
-    uint32_t small_offsets;  // every grid: R * (1 + Nx + Nx * Ny) < 2^31 (cell offsets fit int32)
+    uint32_t small_offsets;
+    uint32_t single_scan;    // the call holds exactly one scan (one grid)  // every grid: R * (1 + Nx + Nx * Ny) < 2^31 (cell offsets fit int32)
 };
 
 // ---------------------------------------------------------- launch config ---

@@ -894,6 +894,9 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_atomic(PipeArgs a, const C
 constexpr int kCellTable = 1331;        // K <= 11
 constexpr int kShadowTable = 2048;      // r_s^2 <= 9: at most 76 cells per cube bin, 26 bins
 
+// ONE: the call holds a single scan, so every point is in grid 0 and the
+// table is built once
+template <bool ONE>
 __global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const CallInfo *info) {
     __shared__ int2 cells[kCellTable];          // (offset, mask)
     __shared__ int sh_off[kShadowTable];        // grid offsets of the shadow cells
@@ -906,6 +909,23 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const C
     const uint32_t waves = gridDim.x * (blockDim.x >> 6);
     uint32_t cur_grid = 0xFFFFFFFFu;
     DevGrid g{};
+    auto build_table = [&](const DevGrid &gg) {
+        for (int c = threadIdx.x; c < K3; c += blockDim.x) {
+            const int ox = c % K - R, oy = (c / K) % K - R, oz = c / (K * K) - R;
+            const uint32_t q = t.metric == DBTSDF_DIST_L1 ? (uint32_t)(abs(ox) + abs(oy) + abs(oz))
+                                                          : (uint32_t)(ox * ox + oy * oy + oz * oz);
+            cells[c] = make_int2(ox + (int)gg.nx * (oy + (int)gg.ny * oz), (int)t.mask_by_q[q]);
+        }
+        for (uint32_t j = threadIdx.x; j < n_sh; j += blockDim.x) {
+            const int pk = (int)t.sh_off[j];
+            sh_off[j] = ((pk & 255) - R) + (int)gg.nx * (((pk >> 8) & 255) - R + (int)gg.ny * (((pk >> 16) & 255) - R));
+        }
+    };
+    if constexpr (ONE) {
+        g = a.grids[0];
+        build_table(g);
+        __syncthreads();
+    }
     // every wave of the block walks its points in lock step with the others,
     // so the table can be rebuilt (rarely: when the grid changes) under a barrier
     const uint32_t first = blockIdx.x * (blockDim.x >> 6);
@@ -914,32 +934,29 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const C
         const bool live = e < n_surv;
         uint32_t i = 0, gi = 0;
         uint4 r = make_uint4(0, 0, 0, 0);
-        if (live) {
+        bool same = true;
+        if constexpr (ONE) {
+            if (!live) break;
             i = a.survivors[e];
             r = a.rec[i];
-            gi = a.scans[find_scan(a.scans, info->n_scans, i)].grid;
-        }
-        // the grid of the block's first live wave decides whether to rebuild
-        const uint32_t gblk = a.scans[find_scan(a.scans, info->n_scans, a.survivors[e0])].grid;
-        if (gblk != cur_grid) {
-            __syncthreads();
-            cur_grid = gblk;
-            const DevGrid gg = a.grids[gblk];
-            for (int c = threadIdx.x; c < K3; c += blockDim.x) {
-                const int ox = c % K - R, oy = (c / K) % K - R, oz = c / (K * K) - R;
-                const uint32_t q = t.metric == DBTSDF_DIST_L1 ? (uint32_t)(abs(ox) + abs(oy) + abs(oz))
-                                                              : (uint32_t)(ox * ox + oy * oy + oz * oz);
-                cells[c] = make_int2(ox + (int)gg.nx * (oy + (int)gg.ny * oz), (int)t.mask_by_q[q]);
+        } else {
+            if (live) {
+                i = a.survivors[e];
+                r = a.rec[i];
+                gi = a.scans[find_scan(a.scans, info->n_scans, i)].grid;
             }
-            for (uint32_t j = threadIdx.x; j < n_sh; j += blockDim.x) {
-                const int pk = (int)t.sh_off[j];
-                sh_off[j] = ((pk & 255) - R) + (int)gg.nx * (((pk >> 8) & 255) - R + (int)gg.ny * (((pk >> 16) & 255) - R));
+            // the grid of the block's first live wave decides whether to rebuild
+            const uint32_t gblk = a.scans[find_scan(a.scans, info->n_scans, a.survivors[e0])].grid;
+            if (gblk != cur_grid) {
+                __syncthreads();
+                cur_grid = gblk;
+                build_table(a.grids[gblk]);
+                __syncthreads();
             }
-            __syncthreads();
+            if (!live) continue;
+            g = a.grids[gi];
+            same = gi == cur_grid;
         }
-        if (!live) continue;
-        g = a.grids[gi];
-        const bool same = gi == cur_grid;
         const size_t lin = (size_t)r.x + (size_t)g.nx * ((size_t)r.y + (size_t)g.ny * (size_t)r.z);
         uint32_t *mb = g.mask + lin;
         uint32_t *pb = g.packed + lin;
@@ -1144,8 +1161,12 @@ hipError_t launch_pipeline(const PipeArgs &a, const Tuning &t, uint32_t points_c
         // other kernel sets and grids whose offsets overflow 32 bits take the
         // generic per-row kernel
         const int K3 = a.tab.K * a.tab.K * a.tab.K;
-        if (a.small_offsets && K3 <= kCellTable && a.tab.n_bins == 26 && a.tab.shadow_r2 <= 9)
-            k_apply_points<<<t.apply_blocks, kPtThreads, 0, st>>>(a, info);
+        if (a.small_offsets && K3 <= kCellTable && a.tab.n_bins == 26 && a.tab.shadow_r2 <= 9) {
+            if (a.single_scan)
+                k_apply_points<true><<<t.apply_blocks, kPtThreads, 0, st>>>(a, info);
+            else
+                k_apply_points<false><<<t.apply_blocks, kPtThreads, 0, st>>>(a, info);
+        }
         else
             k_apply_atomic<<<t.apply_blocks, kPtThreads, 0, st>>>(a, info);
         if (ev_apply1) (void)hipEventRecord(ev_apply1, st);

@@ -137,7 +137,7 @@ struct ScanIn {
 };
 
 // Validates and enqueues one call (plain or batched) on stream st using ws.
-dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &scans, bool use_graph);
+dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &scans, bool use_graph, bool plain);
 dbtsdf_status ensure_bricks(dbtsdf_grid *g);
 dbtsdf_status check_hip(hipError_t e, const char *what, dbtsdf_grid *g = nullptr);
 
