@@ -273,8 +273,13 @@ def main():
 
     tuning = json.loads(args.tuning) if args.tuning else None
     if tuning is None and not args.no_autotune:
+        # tune on the state the timed scans meet: a grid that already holds the
+        # warm-up scans (autotune works on scratch copies of it)
         g = db.Grid(gdef["dims"], gdef["voxel_size"], gdef["origin"], ks)
-        tuning = g.autotune(dev[:4], True)
+        for pose, pts in dev[: args.warmup]:
+            g.integrate(pose, pts)
+        g.sync()
+        tuning = g.autotune(dev[args.warmup: args.warmup + 4], True)
         g.close()
         log(f"autotuned: {tuning}")
     if tuning is None:

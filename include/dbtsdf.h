@@ -129,7 +129,7 @@ typedef struct {
 
 /* How conflicting updates to one voxel are resolved. Results are identical. */
 typedef enum {
-    DBTSDF_STRATEGY_AUTO = 0,   /* the tuned choice for this grid */
+    DBTSDF_STRATEGY_AUTO = 0,   /* the default: DBTSDF_STRATEGY_ATOMIC (dbtsdf_autotune measures instead) */
     DBTSDF_STRATEGY_BRICK = 1,  /* returns bucketed by grid brick; one workgroup owns a brick in LDS */
     DBTSDF_STRATEGY_ATOMIC = 2  /* one wavefront per return; 32-bit global atomics */
 } dbtsdf_strategy;
@@ -144,7 +144,8 @@ typedef enum {
  * chunk = most listed points one apply work unit takes from a brick; bricks
  * with more are split over several work units that merge with atomics
  * (0 = default 64, 0xFFFFFFFF = never split). With DBTSDF_STRATEGY_ATOMIC the
- * brick is ignored. Any valid tuning gives bit-identical grids.
+ * brick is ignored. Any valid tuning gives bit-identical grids. A new grid
+ * starts with DBTSDF_STRATEGY_ATOMIC, brick 32x8x8, 256 threads, chunk 64.
  */
 typedef struct {
     uint32_t strategy;

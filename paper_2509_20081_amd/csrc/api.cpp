@@ -470,9 +470,11 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
     // the plain one-scan call has a kernel of its own (no per-point scan lookup)
     a.single_scan = plain && live.size() == 1 ? 1u : 0u;
     a.small_offsets = 1u;
+    a.quad_rows = 1u;
     for (dbtsdf_grid *g : grids) {
+        if (g->params.dims[0] % 4u) a.quad_rows = 0u;
         const uint64_t span = (uint64_t)R * (1ull + g->params.dims[0] + (uint64_t)g->params.dims[0] * g->params.dims[1]);
-        if (span >= (1ull << 31)) a.small_offsets = 0u;
+        if (8 * span >= (1ull << 32)) a.small_offsets = 0u;  // window byte offsets fit 32 bits
     }
 
     slot.prof = 0;
@@ -682,7 +684,7 @@ dbtsdf_status dbtsdf_get_tuning(const dbtsdf_grid *g, dbtsdf_tuning *out) {
 dbtsdf_status dbtsdf_set_tuning(dbtsdf_grid *g, const dbtsdf_tuning *t) {
     if (!g || !t) return invalid("NULL argument");
     Tuning n;
-    n.strategy = t->strategy == DBTSDF_STRATEGY_AUTO ? (uint32_t)DBTSDF_STRATEGY_BRICK : t->strategy;
+    n.strategy = t->strategy == DBTSDF_STRATEGY_AUTO ? (uint32_t)DBTSDF_STRATEGY_ATOMIC : t->strategy;
     n.bx = t->brick[0];
     n.by = t->brick[1];
     n.bz = t->brick[2];

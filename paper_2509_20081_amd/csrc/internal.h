@@ -126,13 +126,14 @@ struct PipeArgs {
     uint32_t count_traffic;
     uint32_t span[3];        // most bricks a K^3 cube can touch per axis
     uint32_t chunk;          // listed points per apply work unit (0 = never split a brick)
-    uint32_t small_offsets;
-    uint32_t single_scan;    // the call holds exactly one scan (one grid)  // every grid: R * (1 + Nx + Nx * Ny) < 2^31 (cell offsets fit int32)
+    uint32_t small_offsets;  // every grid: 8 R (1 + Nx + Nx Ny) < 2^32 (window byte offsets fit 32 bits)
+    uint32_t single_scan;    // the call holds exactly one scan (one grid)
+    uint32_t quad_rows;      // every grid: Nx % 4 == 0 (16-byte aligned grid rows)
 };
 
 // ---------------------------------------------------------- launch config ---
 struct Tuning {
-    uint32_t strategy = DBTSDF_STRATEGY_BRICK;
+    uint32_t strategy = DBTSDF_STRATEGY_ATOMIC;  // the faster form on dense LiDAR scans
     uint32_t bx = 32, by = 8, bz = 8;
     uint32_t threads = 256;
     uint32_t apply_blocks = 0;

@@ -38,6 +38,24 @@ namespace dbtsdf {
 // ============================================================== helpers ===
 __device__ __forceinline__ uint32_t lane() { return __lane_id(); }
 
+// Voxel planes are device memory. Reaching them through global-address-space
+// pointers makes the compiler emit global_* rather than flat_* instructions;
+// flat loads also count against the LDS wait counter, so every LDS read
+// after them would wait for the outstanding voxel loads too.
+typedef __attribute__((address_space(1))) uint32_t gu32;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const u32x4 gu32x4;
+__device__ __forceinline__ gu32 *glob(uint32_t *p) { return (gu32 *)p; }
+__device__ __forceinline__ void g_and(gu32 *p, uint32_t v) {
+    (void)__hip_atomic_fetch_and(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t g_add(gu32 *p, uint32_t v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void g_sub(gu32 *p, uint32_t v) {
+    (void)__hip_atomic_fetch_sub(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -797,22 +815,74 @@ __global__ __launch_bounds__(THREADS) void k_apply_brick(PipeArgs a) {
 }
 
 // ------------------------------------------------------ atomic strategy ---
+// Per-point strategy, one pass per point before the apply: survivor test,
+// compaction of the survivors into a list, the per-scan statistics, and the
+// release of the point's dedup hash slot. Only the slot's winner (the point
+// whose index the slot holds) releases it; a loser that reads the slot after
+// the release sees the empty value, which is not its index either, so its
+// answer is the same.
 __global__ __launch_bounds__(kSelThreads) void k_select_atomic(PipeArgs a, const CallInfo *info) {
     __shared__ uint32_t s_tmp[kSelThreads / 64];
     __shared__ uint32_t s_base;
+    __shared__ uint32_t s_red[SC_N][kSelThreads / 64];
     const uint32_t n = info->n_points;
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
         const uint32_t i = base + threadIdx.x;
-        const SelectOut o = select_point(a, info, i, i < n);
-        if (o.surv) a.rec[i].w = o.r.w | kRecSurvivor;
+        const bool live = i < n;
+        uint4 r = make_uint4(0u, 0u, 0u, 0u);
+        uint32_t s = 0, st = 3u;
+        bool surv = false;
+        if (live) {
+            r = a.rec[i];
+            st = (r.w >> 16) & 3u;
+            s = find_scan(a.scans, info->n_scans, i);
+            if (st == kStOk) {
+                if (a.scans[s].dedup) {
+                    const uint32_t slot = a.pslot[i];
+                    surv = a.hvals[slot] == i;
+                    if (surv) {
+                        a.hkeys[slot] = kHashEmpty;
+                        a.hvals[slot] = 0xFFFFFFFFu;
+                    }
+                } else {
+                    surv = true;
+                }
+            }
+            if (surv) a.rec[i].w = r.w | kRecSurvivor;
+        }
+        uint32_t c[SC_N];
+        c[SC_INVALID] = st == kStInvalid;
+        c[SC_OOB] = st == kStOob;
+        c[SC_DUP] = st == kStOk && !surv;
+        c[SC_INT] = surv;
+        c[SC_SHADOW] = surv ? a.tab.sh_start[(r.w & 0xFFFFu) + 1] - a.tab.sh_start[r.w & 0xFFFFu] : 0u;
+        // statistics: one atomic per counter per workgroup when all of its
+        // points are in one scan, else one per scan per wavefront
+        const uint32_t last = min(n, base + blockDim.x) - 1u;
+        const uint32_t s_lo = find_scan(a.scans, info->n_scans, base);
+        if (s_lo == find_scan(a.scans, info->n_scans, last)) {
+#pragma unroll
+            for (int f = 0; f < SC_N; ++f) {
+                const uint32_t v = wave_sum_u32(c[f]);
+                if (lane() == 0) s_red[f][threadIdx.x >> 6] = v;
+            }
+        } else {
+#pragma unroll
+            for (int f = 0; f < SC_N; ++f) wave_add(a.scan_ctr, s, (uint32_t)f, c[f]);
+        }
         uint32_t tot;
-        const uint32_t pos = block_excl_scan<kSelThreads>(o.surv ? 1u : 0u, s_tmp, tot);
+        const uint32_t pos = block_excl_scan<kSelThreads>(surv ? 1u : 0u, s_tmp, tot);  // syncs s_red too
+        if (s_lo == find_scan(a.scans, info->n_scans, last) && threadIdx.x < SC_N) {
+            unsigned long long sum = 0;
+            for (int k = 0; k < kSelThreads / 64; ++k) sum += s_red[threadIdx.x][k];
+            if (sum) atomicAdd(&a.scan_ctr[(size_t)s_lo * SC_N + threadIdx.x], sum);
+        }
         if (tot) {
             if (threadIdx.x == 0) s_base = atomicAdd(&a.ctrl->n_survivors, tot);
             __syncthreads();
-            if (o.surv) a.survivors[s_base + pos] = i;
-            __syncthreads();
+            if (surv) a.survivors[s_base + pos] = i;
         }
+        __syncthreads();  // s_red and s_base are reused by the next round
     }
 }
 
@@ -823,6 +893,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_atomic(PipeArgs a, const
 // issues the loads of kAtomicBatch cells before it compares any of them, so a
 // point costs a few memory round trips rather than one per cell row.
 constexpr int kAtomicBatch = 2;
+constexpr uint32_t kXcds = 8;           // accelerator complex dies of the MI355X
 
 __global__ __launch_bounds__(kPtThreads) void k_apply_atomic(PipeArgs a, const CallInfo *info) {
     __shared__ uint32_t lut[kLutMax];
@@ -831,15 +902,20 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_atomic(PipeArgs a, const C
     __syncthreads();
     const int K = t.K, R = t.R;
     const bool l1 = t.metric == DBTSDF_DIST_L1;
-    const uint32_t n_surv = a.ctrl->n_survivors;
-    const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+    // XCD-aware split of the survivor list, as in k_apply_points
+    const uint32_t n_all = a.ctrl->n_survivors;
+    const uint32_t n_xcd = (gridDim.x % kXcds) == 0 ? kXcds : 1u;
+    const uint32_t xcd = blockIdx.x % n_xcd, slot = blockIdx.x / n_xcd;
+    const uint32_t lo = (uint32_t)((uint64_t)n_all * xcd / n_xcd);
+    const uint32_t n_surv = (uint32_t)((uint64_t)n_all * (xcd + 1) / n_xcd);
+    const uint32_t waves = (gridDim.x / n_xcd) * (blockDim.x >> 6);
     const uint32_t l = lane();
     const uint32_t wx = (uint32_t)K, rpi = 64u / wx, xi = l % wx, ri = l / wx;
     const bool lane_on = ri < rpi;
     const uint32_t rows = (uint32_t)(K * K);
     const uint32_t mag = ((1u << 20) + wx - 1u) / wx;
     const int ox = (int)xi - R;
-    for (uint32_t e = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); e < n_surv; e += waves) {
+    for (uint32_t e = lo + slot * (blockDim.x >> 6) + (threadIdx.x >> 6); e < n_surv; e += waves) {
         const uint32_t i = a.survivors[e];
         const uint4 r = a.rec[i];
         const uint32_t s = find_scan(a.scans, info->n_scans, i);
@@ -884,123 +960,194 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_atomic(PipeArgs a, const C
     }
 }
 
-// The same per-point update with the per-cell work moved into an LDS table.
-// A cell's eq. 3 mask and its signed offset in the grid's linear order do not
-// depend on the point, so each workgroup builds (offset, mask) for the K^3
-// cells of the current grid once; a point then costs, per cell, one LDS read,
-// one load from the point's base address and the read-first atomicAnd of
-// eq. 4 where the mask loses bits. The 26 cube bins' shadows are cell lists
-// in LDS as well; their counters take the guard-bit atomics of eqs. 5-6.
-constexpr int kCellTable = 1331;        // K <= 11
+// The same per-point update, reading the window row by row in aligned
+// 16-byte quads. A window row of K cells at x in [px - R, px + R] lies in at
+// most four quads starting at x0 = (px - R) rounded down to a multiple of 4,
+// so four lanes cover a row and a wavefront covers 16 rows per load: about
+// eight vector loads per point, each lane's 16 bytes contiguous, instead of
+// K^3 / 64 dword loads whose lanes scatter over six rows. (The L1 tag lookups
+// of the scattered dword form bound the earlier version of this kernel.)
+// Each workgroup keeps, per window row (dy, dz), the row's byte offset from
+// the window's first row and dy^2 + dz^2 (|dy| + |dz| for the L1 metric) in
+// LDS, and the eq. 3 masks by distance index; a cell's mask is then one LDS
+// read. Eq. 4 is the read-first atomicAnd where the mask loses bits. The
+// cube bins' shadows are offset lists in LDS; their counters take the
+// guard-bit atomics of eqs. 5-6. Needs Nx % 4 == 0 (16-byte aligned rows).
+constexpr int kRowPad = 128;            // >= K^2 for K <= 11
+constexpr int kQuadIters = kRowPad * 4 / 64;
 constexpr int kShadowTable = 2048;      // r_s^2 <= 9: at most 76 cells per cube bin, 26 bins
+constexpr int kShadowIters = 2;         // 76 <= 2 x 64
+constexpr int kMaxPointK = 11;
 
 // ONE: the call holds a single scan, so every point is in grid 0 and the
-// table is built once
+// tables are built once
 template <bool ONE>
 __global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const CallInfo *info) {
-    __shared__ int2 cells[kCellTable];          // (offset, mask)
-    __shared__ int sh_off[kShadowTable];        // grid offsets of the shadow cells
+    __shared__ uint2 rows[kRowPad];             // (byte offset of the row from the window's first row, dy^2 + dz^2)
+    __shared__ uint32_t lut[kRowPad];           // eq. 3 mask by distance index
+    __shared__ uint32_t sh_off[kShadowTable];   // byte offsets of the shadow cells from the window's first cell
     const DevTables &t = a.tab;
-    const int K = t.K, R = t.R, K3 = K * K * K;
+    const int K = t.K, R = t.R, K2 = K * K;
+    const bool l1 = t.metric == DBTSDF_DIST_L1;
     const uint32_t l = lane();
     const uint32_t n_sh = t.sh_start[t.n_bins];
 
-    const uint32_t n_surv = a.ctrl->n_survivors;
-    const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+    // XCD-aware split: workgroups are dealt to the eight XCDs round-robin, so
+    // workgroup b runs on XCD b % 8. Each XCD takes one contiguous eighth of
+    // the survivor list (points in scan order are spatial neighbours whose
+    // windows overlap), so the mask words a neighbourhood shares are fetched
+    // into one L2 instead of eight.
+    const uint32_t n_all = a.ctrl->n_survivors;
+    const uint32_t n_xcd = (gridDim.x % kXcds) == 0 ? kXcds : 1u;
+    const uint32_t xcd = blockIdx.x % n_xcd, slot = blockIdx.x / n_xcd;
+    const uint32_t lo = (uint32_t)((uint64_t)n_all * xcd / n_xcd);
+    const uint32_t n_surv = (uint32_t)((uint64_t)n_all * (xcd + 1) / n_xcd);
+    const uint32_t wpb = blockDim.x >> 6;
+    const uint32_t waves = (gridDim.x / n_xcd) * wpb;
+    const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (uint32_t q = threadIdx.x; q < kRowPad; q += blockDim.x) lut[q] = q < t.n_q ? t.mask_by_q[q] : 0u;
     uint32_t cur_grid = 0xFFFFFFFFu;
-    DevGrid g{};
-    auto build_table = [&](const DevGrid &gg) {
-        for (int c = threadIdx.x; c < K3; c += blockDim.x) {
-            const int ox = c % K - R, oy = (c / K) % K - R, oz = c / (K * K) - R;
-            const uint32_t q = t.metric == DBTSDF_DIST_L1 ? (uint32_t)(abs(ox) + abs(oy) + abs(oz))
-                                                          : (uint32_t)(ox * ox + oy * oy + oz * oz);
-            cells[c] = make_int2(ox + (int)gg.nx * (oy + (int)gg.ny * oz), (int)t.mask_by_q[q]);
+    auto build_tables = [&](const DevGrid &gg) {
+        for (int c = threadIdx.x; c < kRowPad; c += blockDim.x) {
+            const int oy = c % K, oz = c / K;
+            const int dy = oy - R, dz = oz - R;
+            rows[c] = c < K2 ? make_uint2(4u * gg.nx * ((uint32_t)oy + gg.ny * (uint32_t)oz),
+                                          l1 ? (uint32_t)(abs(dy) + abs(dz)) : (uint32_t)(dy * dy + dz * dz))
+                             : make_uint2(0u, 0u);
         }
         for (uint32_t j = threadIdx.x; j < n_sh; j += blockDim.x) {
-            const int pk = (int)t.sh_off[j];
-            sh_off[j] = ((pk & 255) - R) + (int)gg.nx * (((pk >> 8) & 255) - R + (int)gg.ny * (((pk >> 16) & 255) - R));
+            const uint32_t pk = t.sh_off[j];
+            sh_off[j] = 4u * ((pk & 255u) + gg.nx * (((pk >> 8) & 255u) + gg.ny * ((pk >> 16) & 255u)));
         }
     };
     if constexpr (ONE) {
-        g = a.grids[0];
-        build_table(g);
+        build_tables(a.grids[0]);
         __syncthreads();
+    } else {
+        __syncthreads();  // lut
     }
+    const uint32_t qd = l & 3u;      // the lane's quad within a row
+    const uint32_t rsub = l >> 2;    // the lane's row within a pass of 16 rows
     // every wave of the block walks its points in lock step with the others,
-    // so the table can be rebuilt (rarely: when the grid changes) under a barrier
-    const uint32_t first = blockIdx.x * (blockDim.x >> 6);
+    // so the tables can be rebuilt (rarely: when the grid changes) under a barrier
+    const uint32_t first = lo + slot * wpb;
     for (uint32_t e0 = first; e0 < n_surv; e0 += waves) {
-        const uint32_t e = e0 + (threadIdx.x >> 6);
+        const uint32_t e = e0 + wid;
         const bool live = e < n_surv;
-        uint32_t i = 0, gi = 0;
-        uint4 r = make_uint4(0, 0, 0, 0);
+        uint32_t gi = 0;
         bool same = true;
         if constexpr (ONE) {
             if (!live) break;
-            i = a.survivors[e];
-            r = a.rec[i];
         } else {
-            if (live) {
-                i = a.survivors[e];
-                r = a.rec[i];
-                gi = a.scans[find_scan(a.scans, info->n_scans, i)].grid;
-            }
+            if (live) gi = a.scans[find_scan(a.scans, info->n_scans, a.survivors[e])].grid;
             // the grid of the block's first live wave decides whether to rebuild
             const uint32_t gblk = a.scans[find_scan(a.scans, info->n_scans, a.survivors[e0])].grid;
             if (gblk != cur_grid) {
                 __syncthreads();
                 cur_grid = gblk;
-                build_table(a.grids[gblk]);
+                build_tables(a.grids[gblk]);
                 __syncthreads();
             }
             if (!live) continue;
-            g = a.grids[gi];
             same = gi == cur_grid;
         }
-        const size_t lin = (size_t)r.x + (size_t)g.nx * ((size_t)r.y + (size_t)g.ny * (size_t)r.z);
-        uint32_t *mb = g.mask + lin;
-        uint32_t *pb = g.packed + lin;
-        for (int c = (int)l; c < K3; c += 64) {
-            int o;
-            uint32_t m;
-            if (same) {
-                const int2 cm = cells[c];
-                o = cm.x;
-                m = (uint32_t)cm.y;
-            } else {  // a wave whose point is in another grid than the table's
-                const int ox = c % K - R, oy = (c / K) % K - R, oz = c / (K * K) - R;
-                o = ox + (int)g.nx * (oy + (int)g.ny * oz);
-                const uint32_t q = t.metric == DBTSDF_DIST_L1 ? (uint32_t)(abs(ox) + abs(oy) + abs(oz))
-                                                              : (uint32_t)(ox * ox + oy * oy + oz * oz);
-                m = t.mask_by_q[q];
+        const DevGrid g = a.grids[gi];
+        const uint4 r = a.rec[a.survivors[e]];
+        if (same) {
+            // x0: first quad of the window rows; the front end admitted only
+            // points whose whole window lies in the grid, and Nx % 4 == 0 keeps
+            // every quad that meets the window inside its grid row
+            const uint32_t x0 = (r.x - (uint32_t)R) & ~3u;
+            const size_t row0 = (size_t)g.nx * ((size_t)(r.y - R) + (size_t)g.ny * (size_t)(r.z - R));
+            const char __attribute__((address_space(1))) *mbase =
+                reinterpret_cast<const char __attribute__((address_space(1))) *>(glob(g.mask) + row0 + x0);
+            const int xl = (int)(x0 + 4u * qd) - (int)r.x;  // dx of the lane's first cell
+            const bool qon = x0 + 4u * qd <= r.x + (uint32_t)R;
+            uint32_t dq[4];
+            bool in[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int dx = xl + j;
+                in[j] = dx >= -R && dx <= R;
+                dq[j] = l1 ? (uint32_t)abs(dx) : (uint32_t)(dx * dx);
             }
-            const uint32_t old = mb[o];
-            if ((old & m) != old) atomicAnd(mb + o, m);
-        }
-        const uint32_t bin = r.w & 0xFFFFu;
-        for (uint32_t j = t.sh_start[bin] + l; j < t.sh_start[bin + 1]; j += 64u) {
-            int o;
-            if (same) {
-                o = sh_off[j];
-            } else {
-                const int pk = (int)t.sh_off[j];
-                o = ((pk & 255) - R) + (int)g.nx * (((pk >> 8) & 255) - R + (int)g.ny * (((pk >> 16) & 255) - R));
+            uint32_t roff[kQuadIters];
+            u32x4 old[kQuadIters];
+#pragma unroll
+            for (int k = 0; k < kQuadIters; ++k) roff[k] = rows[rsub + 16u * k].x;
+#pragma unroll
+            for (int k = 0; k < kQuadIters; ++k) {
+                const bool on = qon && (int)(rsub + 16u * k) < K2;
+                old[k] = on ? *reinterpret_cast<gu32x4 *>(mbase + roff[k] + 16u * qd) : u32x4{0u, 0u, 0u, 0u};
             }
-            const uint32_t ov = atomicAdd(pb + o, 1u);
-            const uint32_t raw = ov & 0x7FFFFFFFu;
-            if (raw >= g.hmax) atomicSub(pb + o, 1u);
-            else if (g.T >= 1u && raw == g.T - 1u) atomicAnd(pb + o, 0x7FFFFFFFu);
-        }
-    }
-}
-
-__global__ __launch_bounds__(kPtThreads) void k_clear_hash(PipeArgs a, const CallInfo *info) {
-    const uint32_t n = info->n_points;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const uint32_t slot = a.pslot[i];
-        if (slot != kNoSlot) {
-            a.hkeys[slot] = kHashEmpty;
-            a.hvals[slot] = 0xFFFFFFFFu;
+            // every mask is compared first (kept in place of the loaded word),
+            // then the atomics go out in one burst: a register read by an
+            // atomic in flight is not overwritten before the point is done
+            uint32_t need = 0;
+#pragma unroll
+            for (int k = 0; k < kQuadIters; ++k) {
+                const bool on = qon && (int)(rsub + 16u * k) < K2;
+                if (!on) continue;
+                const uint32_t cyz = rows[rsub + 16u * k].y;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t m = in[j] ? lut[dq[j] + cyz] : 0xFFFFFFFFu;
+                    if ((old[k][j] & m) != old[k][j]) need |= 1u << (4 * k + j);
+                    old[k][j] = m;
+                }
+            }
+            if (need) {
+#pragma unroll
+                for (int k = 0; k < kQuadIters; ++k)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if ((need >> (4 * k + j)) & 1u) g_and((gu32 *)(mbase + roff[k] + 16u * qd + 4u * j), old[k][j]);
+            }
+            // shadow counters, offsets from the window's first cell
+            const size_t corner = row0 + (size_t)(r.x - (uint32_t)R);
+            const char __attribute__((address_space(1))) *pbase =
+                reinterpret_cast<const char __attribute__((address_space(1))) *>(glob(g.packed) + corner);
+            const uint32_t bin = r.w & 0xFFFFu;
+            const uint32_t s0 = t.sh_start[bin], s1 = t.sh_start[bin + 1];
+            uint32_t ov[kShadowIters];
+            bool on[kShadowIters];
+#pragma unroll
+            for (int k = 0; k < kShadowIters; ++k) {
+                const uint32_t j = s0 + l + 64u * k;
+                on[k] = j < s1;
+                if (on[k]) ov[k] = g_add((gu32 *)(pbase + sh_off[j]), 1u);
+            }
+#pragma unroll
+            for (int k = 0; k < kShadowIters; ++k) {
+                if (!on[k]) continue;
+                gu32 *p = (gu32 *)(pbase + sh_off[s0 + l + 64u * k]);
+                const uint32_t raw = ov[k] & 0x7FFFFFFFu;
+                if (raw >= g.hmax) g_sub(p, 1u);
+                else if (g.T >= 1u && raw == g.T - 1u) g_and(p, 0x7FFFFFFFu);
+            }
+        } else {  // a wave whose point is in another grid than the tables'
+            const size_t lin = (size_t)r.x + (size_t)g.nx * ((size_t)r.y + (size_t)g.ny * (size_t)r.z);
+            gu32 *mb = glob(g.mask) + lin;
+            gu32 *pb = glob(g.packed) + lin;
+            for (int c = (int)l; c < K2 * K; c += 64) {
+                const int ox = c % K - R, oy = (c / K) % K - R, oz = c / K2 - R;
+                const long long o = (long long)ox + (long long)g.nx * ((long long)oy + (long long)g.ny * oz);
+                const uint32_t q = l1 ? (uint32_t)(abs(ox) + abs(oy) + abs(oz)) : (uint32_t)(ox * ox + oy * oy + oz * oz);
+                const uint32_t m = t.mask_by_q[q];
+                const uint32_t old = mb[o];
+                if ((old & m) != old) g_and(mb + o, m);
+            }
+            const uint32_t bin = r.w & 0xFFFFu;
+            for (uint32_t j = t.sh_start[bin] + l; j < t.sh_start[bin + 1]; j += 64u) {
+                const uint32_t pk = t.sh_off[j];
+                const long long o = ((long long)(pk & 255u) - R) +
+                                    (long long)g.nx * (((long long)((pk >> 8) & 255u) - R) +
+                                                       (long long)g.ny * ((long long)((pk >> 16) & 255u) - R));
+                const uint32_t ov = g_add(pb + o, 1u);
+                const uint32_t raw = ov & 0x7FFFFFFFu;
+                if (raw >= g.hmax) g_sub(pb + o, 1u);
+                else if (g.T >= 1u && raw == g.T - 1u) g_and(pb + o, 0x7FFFFFFFu);
+            }
         }
     }
 }
@@ -1155,13 +1302,12 @@ hipError_t launch_pipeline(const PipeArgs &a, const Tuning &t, uint32_t points_c
     k_front<<<pb, kPtThreads, 0, st>>>(a, info);
     if (t.strategy == DBTSDF_STRATEGY_ATOMIC) {
         k_select_atomic<<<sb, kSelThreads, 0, st>>>(a, info);
-        k_stats<<<blocks_for(points_cap, stat_chunk, 512), kPtThreads, 0, st>>>(a, info, stat_chunk);
         if (ev_apply0) (void)hipEventRecord(ev_apply0, st);
         // the LDS cell table covers K <= 11 and cube shadows with r_s^2 <= 9;
         // other kernel sets and grids whose offsets overflow 32 bits take the
         // generic per-row kernel
-        const int K3 = a.tab.K * a.tab.K * a.tab.K;
-        if (a.small_offsets && K3 <= kCellTable && a.tab.n_bins == 26 && a.tab.shadow_r2 <= 9) {
+        if (a.small_offsets && a.quad_rows && a.tab.K <= kMaxPointK && a.tab.n_q <= (uint32_t)kRowPad &&
+            a.tab.n_bins == 26 && a.tab.shadow_r2 <= 9) {
             if (a.single_scan)
                 k_apply_points<true><<<t.apply_blocks, kPtThreads, 0, st>>>(a, info);
             else
@@ -1170,7 +1316,6 @@ hipError_t launch_pipeline(const PipeArgs &a, const Tuning &t, uint32_t points_c
         else
             k_apply_atomic<<<t.apply_blocks, kPtThreads, 0, st>>>(a, info);
         if (ev_apply1) (void)hipEventRecord(ev_apply1, st);
-        k_clear_hash<<<pb, kPtThreads, 0, st>>>(a, info);
         return hipGetLastError();
     }
     apply_fn f = find_apply(t, a.tab.R);
