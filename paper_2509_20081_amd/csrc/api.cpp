@@ -456,6 +456,7 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
     a.work = ws.work;
     a.entries = ws.entries;
     a.survivors = ws.survivors;
+    a.surv_rec = ws.entries;  // the brick lists' storage (at least one uint4 per point)
     a.scan_ctr = ws.ctr;
     a.traffic_ctr = ws.ctr + (size_t)ws.scans_cap * SC_N;
     a.items_cap = ws.items_cap;

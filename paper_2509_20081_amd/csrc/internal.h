@@ -117,7 +117,8 @@ struct PipeArgs {
     uint4 *entries;          // (voxel x, y, z, bin) of the listed points, grouped by brick
     uint32_t *rank;          // per (point, brick) pair: position in the brick's list
     uint4 *work;             // apply work units: (brick, grid, first entry, count | split << 31)
-    uint32_t *survivors;     // compacted survivor list (atomic strategy)
+    uint32_t *survivors;     // per-point strategy: grid index of each listed survivor
+    uint4 *surv_rec;         // per-point strategy: (voxel x, y, z, bin) of each listed survivor     // compacted survivor list (atomic strategy)
     unsigned long long *scan_ctr;     // n_scans * SC_N
     unsigned long long *traffic_ctr;  // n_grids * TC_N
     Ctrl *ctrl;              // followed in memory by the CallInfo

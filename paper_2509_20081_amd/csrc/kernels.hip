@@ -31,6 +31,10 @@
 // and LDS/atomic throughput.
 #include <hip/hip_runtime.h>
 
+#include <array>
+#include <map>
+#include <mutex>
+
 #include "internal.h"
 
 namespace dbtsdf {
@@ -42,6 +46,27 @@ __device__ __forceinline__ uint32_t lane() { return __lane_id(); }
 // pointers makes the compiler emit global_* rather than flat_* instructions;
 // flat loads also count against the LDS wait counter, so every LDS read
 // after them would wait for the outstanding voxel loads too.
+// A grid descriptor held in scalar registers (its fields are the same for
+// the whole wavefront).
+// (readfirstlane returns int: each half is taken as uint32_t before widening,
+// or a low half with bit 31 set would sign-extend over the high half)
+__device__ __forceinline__ uint64_t sgpr64(uint64_t v) {
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)v);
+    return ((uint64_t)hi << 32) | (uint64_t)lo;
+}
+__device__ __forceinline__ DevGrid uniform_grid(const DevGrid &in) {
+    DevGrid g = in;
+    g.mask = reinterpret_cast<uint32_t *>(sgpr64(reinterpret_cast<uint64_t>(in.mask)));
+    g.packed = reinterpret_cast<uint32_t *>(sgpr64(reinterpret_cast<uint64_t>(in.packed)));
+    g.nx = __builtin_amdgcn_readfirstlane(in.nx);
+    g.ny = __builtin_amdgcn_readfirstlane(in.ny);
+    g.nz = __builtin_amdgcn_readfirstlane(in.nz);
+    g.T = __builtin_amdgcn_readfirstlane(in.T);
+    g.hmax = __builtin_amdgcn_readfirstlane(in.hmax);
+    return g;
+}
+
 typedef __attribute__((address_space(1))) uint32_t gu32;
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) const u32x4 gu32x4;
@@ -880,7 +905,10 @@ __global__ __launch_bounds__(kSelThreads) void k_select_atomic(PipeArgs a, const
         if (tot) {
             if (threadIdx.x == 0) s_base = atomicAdd(&a.ctrl->n_survivors, tot);
             __syncthreads();
-            if (surv) a.survivors[s_base + pos] = i;
+            if (surv) {
+                a.survivors[s_base + pos] = a.scans[s].grid;
+                a.surv_rec[s_base + pos] = make_uint4(r.x, r.y, r.z, r.w & 0xFFFFu);
+            }
         }
         __syncthreads();  // s_red and s_base are reused by the next round
     }
@@ -916,10 +944,8 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_atomic(PipeArgs a, const C
     const uint32_t mag = ((1u << 20) + wx - 1u) / wx;
     const int ox = (int)xi - R;
     for (uint32_t e = lo + slot * (blockDim.x >> 6) + (threadIdx.x >> 6); e < n_surv; e += waves) {
-        const uint32_t i = a.survivors[e];
-        const uint4 r = a.rec[i];
-        const uint32_t s = find_scan(a.scans, info->n_scans, i);
-        const DevGrid g = a.grids[a.scans[s].grid];
+        const uint4 r = a.surv_rec[e];
+        const DevGrid g = a.grids[a.survivors[e]];
         for (uint32_t r0 = 0; r0 < rows; r0 += rpi * kAtomicBatch) {
             uint32_t old[kAtomicBatch], m[kAtomicBatch];
             size_t lin[kAtomicBatch];
@@ -967,12 +993,14 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_atomic(PipeArgs a, const C
 // eight vector loads per point, each lane's 16 bytes contiguous, instead of
 // K^3 / 64 dword loads whose lanes scatter over six rows. (The L1 tag lookups
 // of the scattered dword form bound the earlier version of this kernel.)
-// Each workgroup keeps, per window row (dy, dz), the row's byte offset from
-// the window's first row and dy^2 + dz^2 (|dy| + |dz| for the L1 metric) in
-// LDS, and the eq. 3 masks by distance index; a cell's mask is then one LDS
-// read. Eq. 4 is the read-first atomicAnd where the mask loses bits. The
-// cube bins' shadows are offset lists in LDS; their counters take the
-// guard-bit atomics of eqs. 5-6. Needs Nx % 4 == 0 (16-byte aligned rows).
+// Each workgroup keeps in LDS the byte offset of every window row (dy, dz)
+// and, per alignment phase of the window and row, the eq. 3 masks of the four
+// cells a lane covers (16 bits each, -1 outside the window): one 8-byte LDS
+// read per row. Eq. 4 is the read-first atomicAnd where the mask loses bits.
+// The cube bins' shadows are offset lists in LDS; their counters take the
+// guard-bit atomics of eqs. 5-6, issued together with the window loads so
+// that one memory round trip serves both. Needs Nx % 4 == 0 (16-byte aligned
+// rows).
 constexpr int kRowPad = 128;            // >= K^2 for K <= 11
 constexpr int kQuadIters = kRowPad * 4 / 64;
 constexpr int kShadowTable = 2048;      // r_s^2 <= 9: at most 76 cells per cube bin, 26 bins
@@ -983,9 +1011,10 @@ constexpr int kMaxPointK = 11;
 // tables are built once
 template <bool ONE>
 __global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const CallInfo *info) {
-    __shared__ uint2 rows[kRowPad];             // (byte offset of the row from the window's first row, dy^2 + dz^2)
-    __shared__ uint32_t lut[kRowPad];           // eq. 3 mask by distance index
+    __shared__ uint32_t roffs[kRowPad];         // byte offset of window row (dy, dz) from the window's first row
+    __shared__ uint2 mtab[16][kRowPad];         // eq. 3 masks of a lane's 4 cells (int16 each, -1 = outside)
     __shared__ uint32_t sh_off[kShadowTable];   // byte offsets of the shadow cells from the window's first cell
+    __shared__ uint32_t sh_rng[32];             // shadow list start of every bin, and the end
     const DevTables &t = a.tab;
     const int K = t.K, R = t.R, K2 = K * K;
     const bool l1 = t.metric == DBTSDF_DIST_L1;
@@ -1005,16 +1034,29 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const C
     const uint32_t wpb = blockDim.x >> 6;
     const uint32_t waves = (gridDim.x / n_xcd) * wpb;
     const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (uint32_t q = threadIdx.x; q < kRowPad; q += blockDim.x) lut[q] = q < t.n_q ? t.mask_by_q[q] : 0u;
+    // mtab[4 qd - a + 3][row]: the masks of cells dx = 4 qd - a - R + j (j = 0..3)
+    // of window row `row`, for a lane at quad qd of a window whose first
+    // column sits a cells into its quad. Masks of K <= 11 fit 15 bits.
+    for (int e = threadIdx.x; e < 16 * kRowPad; e += blockDim.x) {
+        const int sel = e / kRowPad, row = e % kRowPad;
+        const int dy = row % K - R, dz = row / K - R;
+        uint32_t m16[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int dx = sel - 3 - R + j;
+            m16[j] = 0xFFFFu;
+            if (row < K2 && dx >= -R && dx <= R) {
+                const uint32_t q = l1 ? (uint32_t)(abs(dx) + abs(dy) + abs(dz)) : (uint32_t)(dx * dx + dy * dy + dz * dz);
+                m16[j] = t.mask_by_q[q] & 0xFFFFu;
+            }
+        }
+        mtab[sel][row] = make_uint2(m16[0] | (m16[1] << 16), m16[2] | (m16[3] << 16));
+    }
+    for (uint32_t b = threadIdx.x; b <= t.n_bins; b += blockDim.x) sh_rng[b] = t.sh_start[b];
     uint32_t cur_grid = 0xFFFFFFFFu;
     auto build_tables = [&](const DevGrid &gg) {
-        for (int c = threadIdx.x; c < kRowPad; c += blockDim.x) {
-            const int oy = c % K, oz = c / K;
-            const int dy = oy - R, dz = oz - R;
-            rows[c] = c < K2 ? make_uint2(4u * gg.nx * ((uint32_t)oy + gg.ny * (uint32_t)oz),
-                                          l1 ? (uint32_t)(abs(dy) + abs(dz)) : (uint32_t)(dy * dy + dz * dz))
-                             : make_uint2(0u, 0u);
-        }
+        for (int c = threadIdx.x; c < kRowPad; c += blockDim.x)
+            roffs[c] = c < K2 ? 4u * gg.nx * ((uint32_t)(c % K) + gg.ny * (uint32_t)(c / K)) : 0u;
         for (uint32_t j = threadIdx.x; j < n_sh; j += blockDim.x) {
             const uint32_t pk = t.sh_off[j];
             sh_off[j] = 4u * ((pk & 255u) + gg.nx * (((pk >> 8) & 255u) + gg.ny * ((pk >> 16) & 255u)));
@@ -1024,13 +1066,24 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const C
         build_tables(a.grids[0]);
         __syncthreads();
     } else {
-        __syncthreads();  // lut
+        __syncthreads();  // mtab
     }
     const uint32_t qd = l & 3u;      // the lane's quad within a row
     const uint32_t rsub = l >> 2;    // the lane's row within a pass of 16 rows
     // every wave of the block walks its points in lock step with the others,
     // so the tables can be rebuilt (rarely: when the grid changes) under a barrier
     const uint32_t first = lo + slot * wpb;
+    // the next point's record is loaded one iteration ahead, as a vector load
+    // that completes together with the current point's window loads, so a
+    // point costs one memory round trip
+    auto fetch = [&](uint32_t e) {
+        uint32_t v = e;
+        asm volatile("" : "+v"(v));  // per-lane address: a vector load, counted with the window loads
+        return a.surv_rec[v];
+    };
+    uint4 r_next = first + wid < n_surv ? fetch(first + wid) : make_uint4(0u, 0u, 0u, 0u);
+    DevGrid g_one{};
+    if constexpr (ONE) g_one = uniform_grid(a.grids[0]);  // loaded once: stores to the planes might alias it
     for (uint32_t e0 = first; e0 < n_surv; e0 += waves) {
         const uint32_t e = e0 + wid;
         const bool live = e < n_surv;
@@ -1039,9 +1092,9 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const C
         if constexpr (ONE) {
             if (!live) break;
         } else {
-            if (live) gi = a.scans[find_scan(a.scans, info->n_scans, a.survivors[e])].grid;
+            if (live) gi = a.survivors[e];
             // the grid of the block's first live wave decides whether to rebuild
-            const uint32_t gblk = a.scans[find_scan(a.scans, info->n_scans, a.survivors[e0])].grid;
+            const uint32_t gblk = a.survivors[e0];
             if (gblk != cur_grid) {
                 __syncthreads();
                 cur_grid = gblk;
@@ -1051,8 +1104,10 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const C
             if (!live) continue;
             same = gi == cur_grid;
         }
-        const DevGrid g = a.grids[gi];
-        const uint4 r = a.rec[a.survivors[e]];
+        const DevGrid g = ONE ? g_one : uniform_grid(a.grids[gi]);
+        const uint4 r = make_uint4(__builtin_amdgcn_readfirstlane(r_next.x), __builtin_amdgcn_readfirstlane(r_next.y),
+                                   __builtin_amdgcn_readfirstlane(r_next.z), __builtin_amdgcn_readfirstlane(r_next.w));
+        if (e + waves < n_surv) r_next = fetch(e + waves);
         if (same) {
             // x0: first quad of the window rows; the front end admitted only
             // points whose whole window lies in the grid, and Nx % 4 == 0 keeps
@@ -1061,69 +1116,76 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const C
             const size_t row0 = (size_t)g.nx * ((size_t)(r.y - R) + (size_t)g.ny * (size_t)(r.z - R));
             const char __attribute__((address_space(1))) *mbase =
                 reinterpret_cast<const char __attribute__((address_space(1))) *>(glob(g.mask) + row0 + x0);
-            const int xl = (int)(x0 + 4u * qd) - (int)r.x;  // dx of the lane's first cell
+            const uint32_t sel = 4u * qd + 3u - ((r.x - (uint32_t)R) & 3u);
             const bool qon = x0 + 4u * qd <= r.x + (uint32_t)R;
-            uint32_t dq[4];
-            bool in[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int dx = xl + j;
-                in[j] = dx >= -R && dx <= R;
-                dq[j] = l1 ? (uint32_t)abs(dx) : (uint32_t)(dx * dx);
-            }
             uint32_t roff[kQuadIters];
             u32x4 old[kQuadIters];
 #pragma unroll
-            for (int k = 0; k < kQuadIters; ++k) roff[k] = rows[rsub + 16u * k].x;
+            for (int k = 0; k < kQuadIters; ++k) roff[k] = roffs[rsub + 16u * k];
 #pragma unroll
             for (int k = 0; k < kQuadIters; ++k) {
                 const bool on = qon && (int)(rsub + 16u * k) < K2;
-                old[k] = on ? *reinterpret_cast<gu32x4 *>(mbase + roff[k] + 16u * qd) : u32x4{0u, 0u, 0u, 0u};
+                const uint32_t boff = roff[k] + 16u * qd;  // 32-bit offset from a scalar base
+                old[k] = on ? *reinterpret_cast<gu32x4 *>(mbase + boff) : u32x4{0u, 0u, 0u, 0u};
             }
-            // every mask is compared first (kept in place of the loaded word),
-            // then the atomics go out in one burst: a register read by an
-            // atomic in flight is not overwritten before the point is done
-            uint32_t need = 0;
-#pragma unroll
-            for (int k = 0; k < kQuadIters; ++k) {
-                const bool on = qon && (int)(rsub + 16u * k) < K2;
-                if (!on) continue;
-                const uint32_t cyz = rows[rsub + 16u * k].y;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const uint32_t m = in[j] ? lut[dq[j] + cyz] : 0xFFFFFFFFu;
-                    if ((old[k][j] & m) != old[k][j]) need |= 1u << (4 * k + j);
-                    old[k][j] = m;
-                }
-            }
-            if (need) {
-#pragma unroll
-                for (int k = 0; k < kQuadIters; ++k)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        if ((need >> (4 * k + j)) & 1u) g_and((gu32 *)(mbase + roff[k] + 16u * qd + 4u * j), old[k][j]);
-            }
-            // shadow counters, offsets from the window's first cell
+            // shadow counters (eq. 5): the adds go out with the window loads, so
+            // their returns arrive in the same round trip
             const size_t corner = row0 + (size_t)(r.x - (uint32_t)R);
             const char __attribute__((address_space(1))) *pbase =
                 reinterpret_cast<const char __attribute__((address_space(1))) *>(glob(g.packed) + corner);
             const uint32_t bin = r.w & 0xFFFFu;
-            const uint32_t s0 = t.sh_start[bin], s1 = t.sh_start[bin + 1];
-            uint32_t ov[kShadowIters];
-            bool on[kShadowIters];
+            const uint32_t s0 = sh_rng[bin], s1 = sh_rng[bin + 1];
+            uint32_t ov[kShadowIters], soff[kShadowIters];
+            bool son[kShadowIters];
 #pragma unroll
             for (int k = 0; k < kShadowIters; ++k) {
                 const uint32_t j = s0 + l + 64u * k;
-                on[k] = j < s1;
-                if (on[k]) ov[k] = g_add((gu32 *)(pbase + sh_off[j]), 1u);
+                son[k] = j < s1;
+                soff[k] = son[k] ? sh_off[j] : 0u;
+                ov[k] = 0u;
+                if (son[k]) ov[k] = g_add((gu32 *)(pbase + soff[k]), 1u);
             }
+            // stored and stamped masks both have the form 2^n - 1, so the AND of
+            // eq. 4 loses bits exactly when old > m; every compare comes first,
+            // then the atomics go out in one burst (a register read by an
+            // atomic in flight is not overwritten before the point is done)
+            auto masks = [&](int k, uint32_t m[4]) {
+                const uint2 v = mtab[sel][rsub + 16u * k];
+                m[0] = (uint32_t)((int32_t)(v.x << 16) >> 16);
+                m[1] = (uint32_t)((int32_t)v.x >> 16);
+                m[2] = (uint32_t)((int32_t)(v.y << 16) >> 16);
+                m[3] = (uint32_t)((int32_t)v.y >> 16);
+            };
+            bool need = false;
+#pragma unroll
+            for (int k = 0; k < kQuadIters; ++k) {
+                uint32_t m[4];
+                masks(k, m);
+                need |= (old[k][0] > m[0]) | (old[k][1] > m[1]) | (old[k][2] > m[2]) | (old[k][3] > m[3]);
+            }
+            if (need) {  // rare once the map has formed: the compares are redone here
+#pragma unroll
+                for (int k = 0; k < kQuadIters; ++k) {
+                    uint32_t m[4];
+                    masks(k, m);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (old[k][j] > m[j]) g_and((gu32 *)(mbase + (roff[k] + 16u * qd + 4u * j)), m[j]);
+                }
+            }
+            // eqs. 5-6 for the shadow counters, with the returns that the add
+            // issued next to the window loads brought back: every add that saw
+            // a raw count >= H_max is cancelled, the add that saw T - 1 clears
+            // the sign (bits 16-30 absorb the transient overshoot)
 #pragma unroll
             for (int k = 0; k < kShadowIters; ++k) {
-                if (!on[k]) continue;
-                gu32 *p = (gu32 *)(pbase + sh_off[s0 + l + 64u * k]);
+                // an opaque use: the returned value is not touched (and waited
+                // for) before the window compares above have been issued
+                asm volatile("" : "+v"(ov[k]));
+                if (!son[k]) continue;
                 const uint32_t raw = ov[k] & 0x7FFFFFFFu;
-                if (raw >= g.hmax) g_sub(p, 1u);
-                else if (g.T >= 1u && raw == g.T - 1u) g_and(p, 0x7FFFFFFFu);
+                if (raw >= g.hmax) g_sub((gu32 *)(pbase + soff[k]), 1u);
+                else if (g.T >= 1u && raw == g.T - 1u) g_and((gu32 *)(pbase + soff[k]), 0x7FFFFFFFu);
             }
         } else {  // a wave whose point is in another grid than the tables'
             const size_t lin = (size_t)r.x + (size_t)g.nx * ((size_t)r.y + (size_t)g.ny * (size_t)r.z);
@@ -1277,13 +1339,39 @@ bool tuning_supported(const Tuning &t, int K) {
     return find_apply(t, (K - 1) / 2) != nullptr;
 }
 
+static int apply_blocks_query(const Tuning &t, int K, int device);
+
+// The occupancy query costs far more than a launch, so its answer is kept per
+// (device, strategy, shape, threads, K).
 int apply_blocks_default(const Tuning &t, int K, int device) {
+    static std::mutex mu;
+    static std::map<std::array<uint32_t, 7>, int> cache;
+    const std::array<uint32_t, 7> key = {(uint32_t)device, t.strategy, t.bx, t.by, t.bz, t.threads, (uint32_t)K};
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    const int v = apply_blocks_query(t, K, device);
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = v;
+    return v;
+}
+
+static int apply_blocks_query(const Tuning &t, int K, int device) {
     int cus = 256;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) cus = 256;
-    if (t.strategy == DBTSDF_STRATEGY_ATOMIC) return cus * 8;
-    // a persistent grid must be fully resident: blocks per CU from the
-    // kernel's real register and LDS use
+    // a persistent grid is sized to be fully resident: blocks per CU from the
+    // kernel's real register and LDS use (a second round of workgroups would
+    // start only when the first has finished its share)
     int per_cu = 0;
+    if (t.strategy == DBTSDF_STRATEGY_ATOMIC) {
+        const void *pk = K <= kMaxPointK ? reinterpret_cast<const void *>(k_apply_points<true>)
+                                         : reinterpret_cast<const void *>(k_apply_atomic);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pk, kPtThreads, 0) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        return cus * per_cu;
+    }
     apply_fn f = find_apply(t, (K - 1) / 2);
     if (!f || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(f),
                                                            (int)t.threads, 0) != hipSuccess || per_cu < 1)
@@ -1303,18 +1391,19 @@ hipError_t launch_pipeline(const PipeArgs &a, const Tuning &t, uint32_t points_c
     if (t.strategy == DBTSDF_STRATEGY_ATOMIC) {
         k_select_atomic<<<sb, kSelThreads, 0, st>>>(a, info);
         if (ev_apply0) (void)hipEventRecord(ev_apply0, st);
-        // the LDS cell table covers K <= 11 and cube shadows with r_s^2 <= 9;
-        // other kernel sets and grids whose offsets overflow 32 bits take the
-        // generic per-row kernel
+        // the row kernel covers K <= 11, cube shadows with r_s^2 <= 9 and grids
+        // with Nx % 4 == 0 whose window offsets fit 32 bits; everything else
+        // takes the generic per-row kernel
         if (a.small_offsets && a.quad_rows && a.tab.K <= kMaxPointK && a.tab.n_q <= (uint32_t)kRowPad &&
             a.tab.n_bins == 26 && a.tab.shadow_r2 <= 9) {
             if (a.single_scan)
                 k_apply_points<true><<<t.apply_blocks, kPtThreads, 0, st>>>(a, info);
             else
                 k_apply_points<false><<<t.apply_blocks, kPtThreads, 0, st>>>(a, info);
+            if (ev_apply1) (void)hipEventRecord(ev_apply1, st);
+            return hipGetLastError();
         }
-        else
-            k_apply_atomic<<<t.apply_blocks, kPtThreads, 0, st>>>(a, info);
+        k_apply_atomic<<<t.apply_blocks, kPtThreads, 0, st>>>(a, info);
         if (ev_apply1) (void)hipEventRecord(ev_apply1, st);
         return hipGetLastError();
     }
