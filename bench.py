@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "voxel-updates/s & scans/s (batched vs plain, bit-exact); p50/p99 scan latency"
 HBM_PEAK_GBS = 8000.0
+LDS_ATOMIC_OPS = 256 * 32 * 2.4e9
 
 
 def log(msg):
@@ -61,8 +62,24 @@ def load_scans(cfg, n, torch):
     return scans, dev
 
 
+def grid_hash(torch, g):
+    """Two position-weighted sums over both planes (torch-owned planes), for bit-exact comparisons."""
+    out = []
+    for t in (g.mask_tensor, g.packed_tensor):
+        x = t.view(-1)
+        s1 = s2 = 0
+        step = 1 << 26
+        for i in range(0, x.numel(), step):
+            c = x[i: i + step].to(torch.int64) & 0xFFFFFFFF
+            w = torch.arange(i, i + c.numel(), device=c.device, dtype=torch.int64) % 65521 + 1
+            s1 += int(c.sum().item())
+            s2 += int((c * w).sum().item())
+        out += [s1, s2]
+    return tuple(out)
+
+
 def run_plain(db, torch, gdef, ks, dev, warmup, steps, tuning, profile=True):
-    g = db.Grid(gdef["dims"], gdef["voxel_size"], gdef["origin"], ks)
+    g = db.Grid(gdef["dims"], gdef["voxel_size"], gdef["origin"], ks, planes="torch")
     if tuning:
         g.set_tuning(**{k: v for k, v in tuning.items() if k != "apply_blocks"})
     n_seq = len(dev)
@@ -86,7 +103,7 @@ def run_plain(db, torch, gdef, ks, dev, warmup, steps, tuning, profile=True):
 
 
 def run_batched(db, torch, gdef, ks, dev, warmup, steps, tuning, per_launch):
-    g = db.Grid(gdef["dims"], gdef["voxel_size"], gdef["origin"], ks)
+    g = db.Grid(gdef["dims"], gdef["voxel_size"], gdef["origin"], ks, planes="torch")
     if tuning:
         g.set_tuning(**{k: v for k, v in tuning.items() if k != "apply_blocks"})
     b = db.Batch(use_graph=True)
@@ -225,6 +242,103 @@ def copy_calibration(torch, nbytes=1 << 30):
     log(f"copy calibration: 3 copies of {nbytes} bytes")
 
 
+def copy_bandwidth(torch, nbytes=2 << 30, reps=5):
+    """Achieved device-copy bandwidth (read + write bytes per second), the practical HBM ceiling."""
+    a = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
+def run_c4(db, torch, ks, n_maps, n_scans, tuning):
+    """64 independent maps (sides 128..1024 @ 0.05 m) x 20 scans: plain (one scan per call) against
+    batched (one launch per round holding every map's scan of that round, graph-replayed), on the
+    same scans in the same order; grids of the smaller maps are compared bit for bit."""
+    from synth import scene as synth
+    t = time.time()
+    maps = []
+    for m in range(n_maps):
+        gdef = synth.config_grid(4, m)
+        sc = [(p, torch.from_numpy(x).cuda()) for p, x in synth.config_scans(4, m, range(n_scans))]
+        maps.append((gdef, sc))
+    n_pts = sum(int(x.shape[0]) for _, sc in maps for _, x in sc)
+    log(f"c4: generated {n_maps} maps x {n_scans} scans ({n_pts} points) in {time.time() - t:.1f}s")
+    small = [m for m, (gd, _) in enumerate(maps) if max(gd["dims"]) <= 384]
+
+    def make_grids():
+        gs = []
+        for gd, _ in maps:
+            g = db.Grid(gd["dims"], gd["voxel_size"], gd["origin"], ks, planes="torch")
+            if tuning:
+                g.set_tuning(**{k: v for k, v in tuning.items() if k != "apply_blocks"})
+            gs.append(g)
+        return gs
+
+    # plain; scan 0 of every map is the untimed warm-up (workspaces, first launches) in both forms
+    gs = make_grids()
+    for m, (_, sc) in enumerate(maps):
+        gs[m].integrate(sc[0][0], sc[0][1])
+    for g in gs:
+        g.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st_plain = []
+    for r in range(1, n_scans):
+        for m, (_, sc) in enumerate(maps):
+            st_plain.append(gs[m].integrate(sc[r][0], sc[r][1]))
+    for g in gs:
+        g.sync()
+    torch.cuda.synchronize()
+    dt_plain = time.perf_counter() - t0
+    upd = sum(s.as_dict()["voxel_updates"] for s in st_plain)
+    h_plain = {m: grid_hash(torch, gs[m]) for m in small}
+    for g in gs:
+        g.close()
+    del gs
+    torch.cuda.empty_cache()
+    # batched: one launch per round
+    gs = make_grids()
+    b = db.Batch(use_graph=True)
+    b.integrate([(gs[m], sc[0][0], sc[0][1]) for m, (_, sc) in enumerate(maps)])
+    b.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st_b = []
+    for r in range(1, n_scans):
+        st_b.extend(b.integrate([(gs[m], sc[r][0], sc[r][1]) for m, (_, sc) in enumerate(maps)]))
+    b.sync()
+    torch.cuda.synchronize()
+    dt_b = time.perf_counter() - t0
+    caps, reps = b.graph_stats()
+    updb = sum(s.as_dict()["voxel_updates"] for s in st_b)
+    same = all(grid_hash(torch, gs[m]) == h_plain[m] for m in small)
+    b.close()
+    for g in gs:
+        g.close()
+    del gs
+    torch.cuda.empty_cache()
+    grid_gb = sum(2 * 4 * gd["dims"][0] * gd["dims"][1] * gd["dims"][2] for gd, _ in maps) / 1e9
+    return dict(workload="c4_64maps_x20scans", maps=n_maps, scans_per_map=n_scans, points=n_pts,
+                resident_grid_gb=grid_gb,
+                timed_rounds=n_scans - 1,
+                plain=dict(value=upd / dt_plain, unit="voxel-updates/s", scans_per_s=n_maps * (n_scans - 1) / dt_plain),
+                batched=dict(value=updb / dt_b, unit="voxel-updates/s", scans_per_s=n_maps * (n_scans - 1) / dt_b,
+                             scans_per_launch=n_maps, graph_captures=caps, graph_replays=reps),
+                speedup=(updb / dt_b) / (upd / dt_plain), updates_equal=upd == updb,
+                bit_exact_maps_checked=len(small), bit_exact=same)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -243,6 +357,7 @@ def main():
     ap.add_argument("--serve-robots", type=int, default=32)
     ap.add_argument("--serve-scans-per-robot", type=int, default=6)
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--c4", action="store_true", help="also run the 64-map batching workload (about 160 GB of grids)")
     ap.add_argument("--tuning", type=str, default="", help="JSON tuning to use instead of autotuning")
     args = ap.parse_args()
 
@@ -293,6 +408,7 @@ def main():
     upd = sum(s["voxel_updates"] for s in sd)
     value = upd / dt
     log(f"plain: {args.steps} scans in {dt * 1e3:.1f} ms -> {value / 1e9:.1f} G voxel-updates/s; profile {prof}")
+    plain_hash = grid_hash(torch, g) if not args.no_batched else None
     g.close()
     torch.cuda.empty_cache()
 
@@ -315,8 +431,15 @@ def main():
         tj = json.load(open(tfile))
         if tj.get("kernel_source_hash") == kernel_source_hash() and tj.get("kernel") == kname:
             traffic = tj.get("bytes_per_launch")
+    copy_gbs = copy_bandwidth(torch)
+    visits = float(np.mean([t["voxel_updates"] for t in sd]))
     roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
                     traffic=traffic, kernel=kname, avg_launch_us=apply_ms * 1e3,
+                    measured_copy_gbs=copy_gbs, frac_vs_copy=achieved / copy_gbs,
+                    secondary=dict(ceiling="LDS/atomic dword ops: 256 CUs x 32 per clock x 2.4 GHz",
+                                   peak_ops_per_s=LDS_ATOMIC_OPS, achieved_ops_per_s=visits / (apply_ms * 1e-3),
+                                   frac=visits / (apply_ms * 1e-3) / LDS_ATOMIC_OPS,
+                                   per_launch="voxel-updates of one scan (K^3 per integrated point)"),
                     algorithmic_bytes_per_launch=apply_bytes,
                     per_launch="4*U_m + 4*C_m + 8*U_s of one scan (unique mask words read, changed words "
                                "written, unique shadow words read+written)",
@@ -333,7 +456,8 @@ def main():
         bupd = sum(s.as_dict()["voxel_updates"] for s in bst)
         batched = dict(value=bupd / bdt, unit="voxel-updates/s", scans_per_s=args.steps / bdt,
                        scans_per_launch=args.batch_scans, ms_per_scan=bdt * 1e3 / args.steps,
-                       graph_captures=caps, graph_replays=reps, speedup_vs_plain=(bupd / bdt) / value)
+                       graph_captures=caps, graph_replays=reps, speedup_vs_plain=(bupd / bdt) / value,
+                       bit_exact_vs_plain=grid_hash(torch, bg) == plain_hash)
         bg.close()
         log(f"batched: {batched}")
         torch.cuda.empty_cache()
@@ -351,9 +475,16 @@ def main():
                        served_definition="scheduled arrival to observed completion, Poisson arrivals")
         log(f"served: {served}")
 
+    c4 = None
+    if args.c4:
+        del dev
+        torch.cuda.empty_cache()
+        c4 = run_c4(db, torch, ks, synth.CONFIGS[4]["maps"], synth.CONFIGS[4]["scans"], tuning)
+        log(f"c4: {c4}")
+
     cpu = None if args.no_cpu else cpu_baseline(gdef, scans[: min(len(scans), 80)])
 
-    mean_pts = float(np.mean([int(p.shape[0]) for _, p in dev]))
+    mean_pts = float(np.mean([int(p.shape[0]) for _, p in scans]))
     out = {
         "metric": METRIC,
         "value": value,
@@ -377,6 +508,7 @@ def main():
         "batched": batched,
         "latency_ms": latency,
         "served": served,
+        "c4_batching": c4,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernel_source_hash": kernel_source_hash(),

@@ -240,6 +240,9 @@ dbtsdf_status dbtsdf_set_tuning(dbtsdf_grid *g, const dbtsdf_tuning *t);
  *            dbtsdf_sync() (it must stay valid until then).
  * Non-finite and zero-range points are not errors: they are counted.
  * Front end arithmetic is fp32, one IEEE operation per step, no contraction.
+ * The passes of a call are replayed from a HIP graph captured (on a private
+ * stream of the grid) the first time a call of that shape is made, and
+ * launched on the grid's stream.
  * Errors: INVALID_ARG, OUT_OF_RANGE (n too large), OUT_OF_MEMORY, DEVICE, POISONED.
  */
 dbtsdf_status dbtsdf_integrate_scan(dbtsdf_grid *g, const float pose[16], const float *points, uint64_t n,
@@ -300,7 +303,9 @@ dbtsdf_status dbtsdf_read_profile(dbtsdf_grid *g, double *call_ms, uint64_t *cal
  * A batch context owns a HIP stream-ordered workspace and a graph cache. All
  * grids of one call must live on the device the context was created on; the
  * context's stream is hip_stream (NULL = default stream), which must not be
- * used concurrently by another context.
+ * used concurrently by another context. use_graph = 0 launches the passes one
+ * by one instead of replaying graphs (graphs are captured on a private stream
+ * and launched on the context's stream, the default stream included).
  */
 dbtsdf_status dbtsdf_batch_create(void *hip_stream, int use_graph, dbtsdf_batch **out);
 

@@ -79,7 +79,46 @@ static dbtsdf_status make_device_tables(const KernelSet &ks, std::unique_ptr<Dev
 }
 
 // ---------------------------------------------------------- workspace ---
-Workspace::~Workspace() { release(); }
+Workspace::~Workspace() {
+    release();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+}
+
+// The graph of (call layout, tuning, capacity, part), captured on the
+// workspace's private stream the first time and replayed after that. Kernel
+// arguments are baked into the graph; everything that changes from call to
+// call (poses, point counts, scans) is read by the kernels from the
+// descriptor buffer, uploaded before each launch.
+static hipError_t pipeline_graph(Workspace &ws, const PipeArgs &a, const Tuning &tun, int part,
+                                 hipGraphExec_t *out) {
+    std::string key;
+    key.append((const char *)&a, sizeof(a));
+    key.append((const char *)&tun, sizeof(tun));
+    key.append((const char *)&ws.points_cap, sizeof(ws.points_cap));
+    key.append((const char *)&part, sizeof(part));
+    auto it = ws.graphs.find(key);
+    if (it != ws.graphs.end()) {
+        *out = it->second.exec;
+        return hipSuccess;
+    }
+    hipError_t e = hipSuccess;
+    if (!ws.cap_stream) e = hipStreamCreateWithFlags(&ws.cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    hipGraph_t graph = nullptr;
+    e = hipStreamBeginCapture(ws.cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    const hipError_t le = launch_pipeline(a, tun, ws.points_cap, ws.cap_stream, part);
+    e = hipStreamEndCapture(ws.cap_stream, &graph);
+    if (e == hipSuccess) e = le;
+    GraphEntry ge;
+    if (e == hipSuccess) e = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return e;
+    ws.graphs.emplace(key, ge);
+    ++ws.captures;
+    *out = ge.exec;
+    return hipSuccess;
+}
 
 void Workspace::drop_graphs() {
     for (auto &kv : graphs)
@@ -191,6 +230,27 @@ hipError_t Workspace::ensure_staging(size_t floats, hipStream_t st) {
     return e;
 }
 
+static_assert(sizeof(CallInfo) % 8 == 0 && sizeof(DevGrid) % 8 == 0 && sizeof(DevScan) % 8 == 0,
+              "descriptors are copied in 8-byte words");
+
+// A ring slot's buffer: pinned, coherent host memory that the first and last
+// passes of a call read and write directly.
+static bool alloc_slot(RingSlot &r, size_t bytes) {
+    if (hipHostMalloc(&r.host, bytes, hipHostMallocCoherent) != hipSuccess) {
+        (void)hipGetLastError();
+        r.host = nullptr;
+        return false;
+    }
+    if (hipHostGetDevicePointer(&r.host_dev, r.host, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipHostFree(r.host);
+        r.host = r.host_dev = nullptr;
+        return false;
+    }
+    r.bytes = bytes;
+    return true;
+}
+
 RingSlot &Workspace::next_slot(size_t bytes, std::string *err) {
     constexpr uint32_t kRing = 16;
     if (ring.size() < kRing) {
@@ -202,7 +262,7 @@ RingSlot &Workspace::next_slot(size_t bytes, std::string *err) {
             for (hipEvent_t &e : r.pe)
                 if (!e) (void)hipEventCreate(&e);
             const size_t want = std::max<size_t>(bytes, 64 * 1024);
-            if (!r.host && hipHostMalloc(&r.host, want, hipHostMallocDefault) == hipSuccess) r.bytes = want;
+            if (!r.host) alloc_slot(r, want);
         }
     }
     RingSlot &s = ring[ring_next];
@@ -213,14 +273,10 @@ RingSlot &Workspace::next_slot(size_t bytes, std::string *err) {
     }
     if (s.bytes < bytes) {
         if (s.host) (void)hipHostFree(s.host);
-        s.host = nullptr;
+        s.host = s.host_dev = nullptr;
         s.bytes = 0;
-        if (hipHostMalloc(&s.host, bytes, hipHostMallocDefault) != hipSuccess) {
-            if (err) *err = "pinned descriptor allocation failed";
-            s.host = nullptr;
-        } else {
-            s.bytes = bytes;
-        }
+        drop_graphs();  // graphs bake the slot's address in
+        if (!alloc_slot(s, bytes) && err) *err = "pinned descriptor allocation failed";
     }
     return s;
 }
@@ -306,13 +362,6 @@ static uint32_t entry_factor(const Tuning &t, int R) {
 }
 
 // ------------------------------------------------------------ enqueue ---
-static std::string graph_key(const PipeArgs &a, const Tuning &t, uint32_t cap) {
-    std::string k;
-    k.append((const char *)&a, sizeof(a));
-    k.append((const char *)&t, sizeof(t));
-    k.append((const char *)&cap, sizeof(cap));
-    return k;
-}
 
 dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &scans, bool use_graph, bool plain) {
     // drop empty scans (their statistics are all zero)
@@ -372,9 +421,9 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
     // descriptors, laid out as on the device: CallInfo | DevGrid[grids_cap] | DevScan[n_scans]
     const size_t n_sc = live.size(), n_gr = grids.size();
     const size_t scans_off = sizeof(CallInfo) + (size_t)ws.grids_cap * sizeof(DevGrid);
-    const size_t desc_bytes = scans_off + n_sc * sizeof(DevScan);
     const size_t ctr_bytes = ((size_t)ws.scans_cap * SC_N + (size_t)ws.grids_cap * TC_N) * 8;
-    const size_t ctr_off = (desc_bytes + 255) & ~(size_t)255;
+    // counters at a fixed place in the slot (a captured graph bakes the address in)
+    const size_t ctr_off = (scans_off + (size_t)ws.scans_cap * sizeof(DevScan) + 255) & ~(size_t)255;
     std::string err;
     RingSlot &slot = ws.next_slot(ctr_off + ctr_bytes, &err);
     if (!slot.host) {
@@ -433,8 +482,6 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
         if (s.stats) slot.pend.push_back(p);
     }
     char *dd = (char *)ws.d_desc;
-    e = hipMemcpyAsync(dd + sizeof(Ctrl), h, desc_bytes, hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return check_hip(e, "uploading descriptors", g0);
 
     PipeArgs a{};
     a.ctrl = (Ctrl *)dd;
@@ -457,6 +504,10 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
     a.entries = ws.entries;
     a.survivors = ws.survivors;
     a.surv_rec = ws.entries;  // the brick lists' storage (at least one uint4 per point)
+    a.host_desc = (const uint2 *)slot.host_dev;
+    a.host_ctr = (unsigned long long *)((char *)slot.host_dev + ctr_off);
+    a.desc_scans_off = (uint32_t)scans_off;
+    a.scans_cap = ws.scans_cap;
     a.scan_ctr = ws.ctr;
     a.traffic_ctr = ws.ctr + (size_t)ws.scans_cap * SC_N;
     a.items_cap = ws.items_cap;
@@ -478,43 +529,33 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
         if (8 * span >= (1ull << 32)) a.small_offsets = 0u;  // window byte offsets fit 32 bits
     }
 
+    // plain calls, and batches that ask for it, replay captured graphs (one
+    // host call instead of one per pass); with profiling on, the apply runs
+    // as a part of its own between two events
+    const bool graphs = plain || use_graph;
     slot.prof = 0;
+    auto run_part = [&](int part) -> hipError_t {
+        if (!graphs) return launch_pipeline(a, tun, ws.points_cap, st, part);
+        hipGraphExec_t ex = nullptr;
+        hipError_t ge = pipeline_graph(ws, a, tun, part, &ex);
+        if (ge != hipSuccess) return ge;
+        ++ws.replays;
+        return hipGraphLaunch(ex, st);
+    };
     if (ws.profile) {
         e = hipEventRecord(slot.pe[0], st);
-        if (e != hipSuccess) return check_hip(e, "profiling event", g0);
-        slot.prof = use_graph ? 1 : 2;
-    }
-    if (use_graph) {
-        const std::string key = graph_key(a, tun, ws.points_cap);
-        auto it = ws.graphs.find(key);
-        if (it == ws.graphs.end()) {
-            hipGraph_t graph = nullptr;
-            e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
-            if (e == hipSuccess) {
-                hipError_t le = launch_pipeline(a, tun, ws.points_cap, st);
-                e = hipStreamEndCapture(st, &graph);
-                if (e == hipSuccess) e = le;
-            }
-            GraphEntry ge;
-            if (e == hipSuccess) e = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
-            if (graph) (void)hipGraphDestroy(graph);
-            if (e != hipSuccess) return check_hip(e, "capturing the integration graph", g0);
-            it = ws.graphs.emplace(key, ge).first;
-            ++ws.captures;
-        }
-        e = hipGraphLaunch(it->second.exec, st);
-        ++ws.replays;
-        if (e == hipSuccess && slot.prof) e = hipEventRecord(slot.pe[2], st);
-    } else if (slot.prof) {
-        e = launch_pipeline(a, tun, ws.points_cap, st, slot.pe[1], slot.pe[2]);
+        if (e == hipSuccess) e = run_part(kPartPre);
+        if (e == hipSuccess) e = hipEventRecord(slot.pe[1], st);
+        if (e == hipSuccess) e = run_part(kPartApply);
+        if (e == hipSuccess) e = hipEventRecord(slot.pe[2], st);
+        slot.prof = 2;
     } else {
-        e = launch_pipeline(a, tun, ws.points_cap, st);
+        e = run_part(kPartAll);
     }
     if (e != hipSuccess) return check_hip(e, "launching the integration kernels", g0);
 
     slot.ctr_off = ctr_off;
-    e = hipMemcpyAsync(h + ctr_off, ws.ctr, ctr_bytes, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipEventRecord(slot.ev, st);
+    e = hipEventRecord(slot.ev, st);
     if (e != hipSuccess) return check_hip(e, "queueing statistics readback", g0);
     slot.busy = true;
     return DBTSDF_OK;
@@ -934,7 +975,7 @@ dbtsdf_status dbtsdf_batch_integrate(dbtsdf_batch *b, uint32_t n_scans, dbtsdf_g
         v[i] = ScanIn{grids[i], poses + 16 * (size_t)i, dev, n[i], stats ? &stats[i] : nullptr};
         off += n[i];
     }
-    dbtsdf_status s = enqueue_scans(*b->ws, b->stream, v, b->use_graph && b->stream != nullptr, false);
+    dbtsdf_status s = enqueue_scans(*b->ws, b->stream, v, b->use_graph, false);
     if (s != DBTSDF_OK) return s;
     hipError_t e = hipEventRecord(b->ev, b->stream);
     for (dbtsdf_grid *g : distinct)

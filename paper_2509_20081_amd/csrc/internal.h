@@ -130,6 +130,12 @@ struct PipeArgs {
     uint32_t small_offsets;  // every grid: 8 R (1 + Nx + Nx Ny) < 2^32 (window byte offsets fit 32 bits)
     uint32_t single_scan;    // the call holds exactly one scan (one grid)
     uint32_t quad_rows;      // every grid: Nx % 4 == 0 (16-byte aligned grid rows)
+    // the call's descriptors are read from, and its counters written to, the
+    // pinned host buffer of its ring slot by the first and last passes
+    const uint2 *host_desc;  // CallInfo | DevGrid[grids_cap] | DevScan[n_scans]
+    unsigned long long *host_ctr;  // scan counters then traffic counters, as ctrl's copy
+    uint32_t desc_scans_off; // byte offset of the DevScan array in the descriptors
+    uint32_t scans_cap;      // counters layout: scans_cap * SC_N scan counters first
 };
 
 // ---------------------------------------------------------- launch config ---
@@ -147,9 +153,10 @@ bool tuning_supported(const Tuning &t, int K);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, uint64_t n, hipStream_t st);
 hipError_t launch_grid_init(uint32_t *mask, uint32_t *packed, uint64_t n, hipStream_t st);
-// ev_apply (optional, pair of events) brackets the apply kernel.
-hipError_t launch_pipeline(const PipeArgs &a, const Tuning &t, uint32_t points_cap, hipStream_t st,
-                           hipEvent_t ev_apply0 = nullptr, hipEvent_t ev_apply1 = nullptr);
+// The pass sequence of one call: all of it, the passes before the apply, or
+// the apply alone (the split lets profiling bracket the apply with events).
+enum { kPartAll = 0, kPartPre = 1, kPartApply = 2 };
+hipError_t launch_pipeline(const PipeArgs &a, const Tuning &t, uint32_t points_cap, hipStream_t st, int part);
 hipError_t launch_read_distance(const uint32_t *mask, const uint32_t *packed, int8_t *out, uint64_t n,
                                 hipStream_t st);
 // Copy box [lo, hi) of one plane (x fastest) into out; with packed != null,

@@ -232,6 +232,28 @@ __global__ void k_reset(PipeArgs a, const CallInfo *info) {
     }
 }
 
+// First pass of a call: the descriptors, from the ring slot's pinned host
+// buffer into device memory (ctrl + 1).
+constexpr int kCopyBlocks = 16;
+__global__ __launch_bounds__(256) void k_upload(PipeArgs a) {
+    const uint32_t n_sc = reinterpret_cast<const CallInfo *>(a.host_desc)->n_scans;
+    const uint32_t words = (a.desc_scans_off + n_sc * (uint32_t)sizeof(DevScan)) / 8u;
+    uint2 *dst = reinterpret_cast<uint2 *>(a.ctrl + 1);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < words; i += gridDim.x * blockDim.x)
+        dst[i] = a.host_desc[i];
+}
+
+// Last pass of a call: the statistics counters into the ring slot's pinned
+// host buffer.
+__global__ __launch_bounds__(256) void k_download(PipeArgs a, const CallInfo *info) {
+    const uint32_t n_s = info->n_scans * SC_N, n_t = info->n_grids * TC_N;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_s + n_t; i += gridDim.x * blockDim.x) {
+        if (i < n_s) a.host_ctr[i] = a.scan_ctr[i];
+        else a.host_ctr[(size_t)a.scans_cap * SC_N + (i - n_s)] = a.traffic_ctr[i - n_s];
+    }
+    __threadfence_system();
+}
+
 __global__ __launch_bounds__(kPtThreads) void k_front(PipeArgs a, const CallInfo *info) {
     const uint32_t n = info->n_points, n_scans = info->n_scans;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -1379,18 +1401,21 @@ static int apply_blocks_query(const Tuning &t, int K, int device) {
     return cus * per_cu;
 }
 
-hipError_t launch_pipeline(const PipeArgs &a, const Tuning &t, uint32_t points_cap, hipStream_t st,
-                           hipEvent_t ev_apply0, hipEvent_t ev_apply1) {
+hipError_t launch_pipeline(const PipeArgs &a, const Tuning &t, uint32_t points_cap, hipStream_t st, int part) {
     const CallInfo *info = reinterpret_cast<const CallInfo *>(a.ctrl + 1);
     const uint32_t pb = blocks_for(points_cap, kPtThreads, 4096);
     const uint32_t sb = blocks_for(points_cap, kSelThreads, 1024);
     uint32_t stat_chunk = 1024;
     while ((uint64_t)stat_chunk * 512 < points_cap) stat_chunk *= 2;
-    k_reset<<<8, 256, 0, st>>>(a, info);
-    k_front<<<pb, kPtThreads, 0, st>>>(a, info);
+    const bool pre = part != kPartApply, apply = part != kPartPre;
+    if (pre) k_upload<<<kCopyBlocks, 256, 0, st>>>(a);
     if (t.strategy == DBTSDF_STRATEGY_ATOMIC) {
-        k_select_atomic<<<sb, kSelThreads, 0, st>>>(a, info);
-        if (ev_apply0) (void)hipEventRecord(ev_apply0, st);
+        if (pre) {
+            k_reset<<<8, 256, 0, st>>>(a, info);
+            k_front<<<pb, kPtThreads, 0, st>>>(a, info);
+            k_select_atomic<<<sb, kSelThreads, 0, st>>>(a, info);
+        }
+        if (!apply) return hipGetLastError();
         // the row kernel covers K <= 11, cube shadows with r_s^2 <= 9 and grids
         // with Nx % 4 == 0 whose window offsets fit 32 bits; everything else
         // takes the generic per-row kernel
@@ -1400,22 +1425,26 @@ hipError_t launch_pipeline(const PipeArgs &a, const Tuning &t, uint32_t points_c
                 k_apply_points<true><<<t.apply_blocks, kPtThreads, 0, st>>>(a, info);
             else
                 k_apply_points<false><<<t.apply_blocks, kPtThreads, 0, st>>>(a, info);
-            if (ev_apply1) (void)hipEventRecord(ev_apply1, st);
-            return hipGetLastError();
+        } else {
+            k_apply_atomic<<<t.apply_blocks, kPtThreads, 0, st>>>(a, info);
         }
-        k_apply_atomic<<<t.apply_blocks, kPtThreads, 0, st>>>(a, info);
-        if (ev_apply1) (void)hipEventRecord(ev_apply1, st);
+        k_download<<<kCopyBlocks, 256, 0, st>>>(a, info);
         return hipGetLastError();
     }
     apply_fn f = find_apply(t, a.tab.R);
     if (!f) return hipErrorInvalidValue;
-    k_select_pairs<<<sb, kSelThreads, 0, st>>>(a, info);
-    k_stats<<<blocks_for(points_cap, stat_chunk, 512), kPtThreads, 0, st>>>(a, info, stat_chunk);
-    k_offsets<<<blocks_for(points_cap, kPtThreads, 256), kPtThreads, 0, st>>>(a);
-    k_fill_pairs<<<pb, kPtThreads, 0, st>>>(a, info);
-    if (ev_apply0) (void)hipEventRecord(ev_apply0, st);
-    hipLaunchKernelGGL(f, dim3(t.apply_blocks), dim3(t.threads), 0, st, a);
-    if (ev_apply1) (void)hipEventRecord(ev_apply1, st);
+    if (pre) {
+        k_reset<<<8, 256, 0, st>>>(a, info);
+        k_front<<<pb, kPtThreads, 0, st>>>(a, info);
+        k_select_pairs<<<sb, kSelThreads, 0, st>>>(a, info);
+        k_stats<<<blocks_for(points_cap, stat_chunk, 512), kPtThreads, 0, st>>>(a, info, stat_chunk);
+        k_offsets<<<blocks_for(points_cap, kPtThreads, 256), kPtThreads, 0, st>>>(a);
+        k_fill_pairs<<<pb, kPtThreads, 0, st>>>(a, info);
+    }
+    if (apply) {
+        hipLaunchKernelGGL(f, dim3(t.apply_blocks), dim3(t.threads), 0, st, a);
+        k_download<<<kCopyBlocks, 256, 0, st>>>(a, info);
+    }
     return hipGetLastError();
 }
 

@@ -37,7 +37,8 @@ struct PendingStat {
 };
 
 struct RingSlot {
-    void *host = nullptr;    // pinned: descriptors, then counters copied back
+    void *host = nullptr;    // pinned, coherent: descriptors, then the counters written back
+    void *host_dev = nullptr;  // the same buffer's device address
     size_t bytes = 0;
     hipEvent_t ev = nullptr;
     bool busy = false;
@@ -74,6 +75,7 @@ struct Workspace {
     std::vector<RingSlot> ring;
     uint32_t ring_next = 0;
     std::map<std::string, GraphEntry> graphs;
+    hipStream_t cap_stream = nullptr;    // private stream the graphs are captured on
     uint64_t captures = 0, replays = 0;
     bool profile = false;
     double prof_call_ms = 0.0, prof_apply_ms = 0.0;

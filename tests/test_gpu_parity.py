@@ -283,21 +283,28 @@ def test_batch_and_graph_replays_equal_plain(db):
             g.integrate(pose, P.to_device(pts))
         g.sync()
         plain.append(P.gpu_planes(g))
-    for use_graph, out in ((True, batched_g), (False, batched_n)):
-        b = db.Batch(use_graph=use_graph)
-        grids = [P.make_pair(d, vs, org, **synth.KERNEL_DEFAULTS)[1] for d, vs, org, _ in maps]
-        for rnd in range(4):              # 4 batches: one scan of every map each, plus a repeat
+    # graph-replayed and directly launched batches in lockstep: every replay is
+    # compared with the direct launches, with eager work in between
+    bg_, bn_ = db.Batch(use_graph=True), db.Batch(use_graph=False)
+    grids_g = [P.make_pair(d, vs, org, **synth.KERNEL_DEFAULTS)[1] for d, vs, org, _ in maps]
+    grids_n = [P.make_pair(d, vs, org, **synth.KERNEL_DEFAULTS)[1] for d, vs, org, _ in maps]
+    for rnd in range(4):              # 4 batches: one scan of every map each, plus a repeat
+        for b, grids in ((bg_, grids_g), (bn_, grids_n)):
             items = [(grids[i], maps[i][3][rnd][0], P.to_device(maps[i][3][rnd][1])) for i in range(3)]
-            if rnd == 3:                  # host points path
+            if rnd == 3:              # host points path
                 items = [(g_, pose, pts.cpu().numpy()) for g_, pose, pts in items]
             b.integrate(items)
             b.sync()
             torch.cuda.synchronize()
             _ = torch.ones(1024, device="cuda").sum().item()   # unrelated eager work between replays
-        out.extend(P.gpu_planes(g_) for g_ in grids)
-        if use_graph:
-            caps, reps = b.graph_stats()
-            assert reps == 4 and caps <= 2
+        for i in range(3):
+            P.assert_grids_equal(*P.gpu_planes(grids_g[i]), *P.gpu_planes(grids_n[i]), what=f"replay {rnd} map {i}")
+    batched_g.extend(P.gpu_planes(g_) for g_ in grids_g)
+    batched_n.extend(P.gpu_planes(g_) for g_ in grids_n)
+    caps, reps = bg_.graph_stats()
+    assert reps == 4 and caps <= 4   # at most one graph per ring slot used
+    caps_n, reps_n = bn_.graph_stats()
+    assert reps_n == 0 and caps_n == 0
     for i in range(3):
         P.assert_grids_equal(*batched_g[i], *plain[i], what=f"graph batch map {i}")
         P.assert_grids_equal(*batched_n[i], *plain[i], what=f"batch map {i}")
