@@ -282,12 +282,13 @@ void dbtsdf_destroy_grid(dbtsdf_grid *g);
 
 /* ---------------------------------------------------------------- profiling
  * Device-side timing with HIP events on the work's own stream. When enabled,
- * each integrate call records events at its start, just before the apply
- * kernel (the per-brick eq. 4-6 merge, the dominant kernel) and at its end;
- * read_profile synchronises the stream and returns the accumulated
- * milliseconds and counts since profiling was (re)enabled. Graph-replayed
- * batch calls report the whole call only (applies stays 0). Any output may be
- * NULL. Enabling resets the totals.
+ * each integrate call (plain or batched) records events at its start, just
+ * before the apply kernel (eqs. 4-6, the dominant kernel) and just after it;
+ * the apply kernel is then launched directly between its two events, and the
+ * passes before and after it are replayed from graphs. call time = start to
+ * the end of the apply kernel. read_profile synchronises the stream and
+ * returns the accumulated milliseconds and counts since profiling was
+ * (re)enabled. Any output may be NULL. Enabling resets the totals.
  */
 dbtsdf_status dbtsdf_set_profiling(dbtsdf_grid *g, int enable);
 dbtsdf_status dbtsdf_read_profile(dbtsdf_grid *g, double *call_ms, uint64_t *calls, double *apply_ms,

@@ -53,8 +53,8 @@ static hipError_t upload(DeviceTables &d, const std::vector<T> &v, const T **out
     return e;
 }
 
-static dbtsdf_status make_device_tables(const KernelSet &ks, std::unique_ptr<DeviceTables> &out) {
-    auto d = std::make_unique<DeviceTables>();
+static dbtsdf_status make_device_tables(const KernelSet &ks, std::shared_ptr<DeviceTables> &out) {
+    auto d = std::make_shared<DeviceTables>();
     d->params = ks.p;
     DevTables &t = d->t;
     hipError_t e = upload(*d, ks.mask_by_q, &t.mask_by_q);
@@ -543,11 +543,14 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
         return hipGraphLaunch(ex, st);
     };
     if (ws.profile) {
+        // the apply kernel is launched directly between its two events, so
+        // they time the kernel rather than a graph launch around it
         e = hipEventRecord(slot.pe[0], st);
         if (e == hipSuccess) e = run_part(kPartPre);
         if (e == hipSuccess) e = hipEventRecord(slot.pe[1], st);
-        if (e == hipSuccess) e = run_part(kPartApply);
+        if (e == hipSuccess) e = launch_pipeline(a, tun, ws.points_cap, st, kPartApply);
         if (e == hipSuccess) e = hipEventRecord(slot.pe[2], st);
+        if (e == hipSuccess) e = run_part(kPartPost);
         slot.prof = 2;
     } else {
         e = run_part(kPartAll);
@@ -655,8 +658,20 @@ static dbtsdf_status create_grid_impl(const dbtsdf_grid_params *params, const db
     g->n_voxels = (uint64_t)params->dims[0] * params->dims[1] * params->dims[2];
     hipError_t e = hipGetDevice(&g->device);
     if (e != hipSuccess) return check_hip(e, "hipGetDevice");
-    s = make_device_tables(*ks->ks, g->tables);
-    if (s != DBTSDF_OK) return s;
+    {
+        // one device copy of the tables per kernel set and device: grids made
+        // from the same kernel set also share their captured graphs
+        std::lock_guard<std::mutex> lk(const_cast<dbtsdf_kernel_set *>(ks)->mu);
+        auto &slot = const_cast<dbtsdf_kernel_set *>(ks)->dev[g->device];
+        if (!slot) {
+            s = make_device_tables(*ks->ks, slot);
+            if (s != DBTSDF_OK) {
+                slot.reset();
+                return s;
+            }
+        }
+        g->tables = slot;
+    }
     if (mask_dev || packed_dev) {
         if (!mask_dev || !packed_dev) return invalid("both planes must be given");
         if (((uintptr_t)mask_dev | (uintptr_t)packed_dev) & 15u) return invalid("planes must be 16-byte aligned");

@@ -153,9 +153,10 @@ bool tuning_supported(const Tuning &t, int K);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, uint64_t n, hipStream_t st);
 hipError_t launch_grid_init(uint32_t *mask, uint32_t *packed, uint64_t n, hipStream_t st);
-// The pass sequence of one call: all of it, the passes before the apply, or
-// the apply alone (the split lets profiling bracket the apply with events).
-enum { kPartAll = 0, kPartPre = 1, kPartApply = 2 };
+// The pass sequence of one call: all of it, or the passes before the apply,
+// the apply alone, and the passes after it (the split lets profiling bracket
+// the apply kernel with events).
+enum { kPartAll = 0, kPartPre = 1, kPartApply = 2, kPartPost = 3 };
 hipError_t launch_pipeline(const PipeArgs &a, const Tuning &t, uint32_t points_cap, hipStream_t st, int part);
 hipError_t launch_read_distance(const uint32_t *mask, const uint32_t *packed, int8_t *out, uint64_t n,
                                 hipStream_t st);

@@ -1407,7 +1407,8 @@ hipError_t launch_pipeline(const PipeArgs &a, const Tuning &t, uint32_t points_c
     const uint32_t sb = blocks_for(points_cap, kSelThreads, 1024);
     uint32_t stat_chunk = 1024;
     while ((uint64_t)stat_chunk * 512 < points_cap) stat_chunk *= 2;
-    const bool pre = part != kPartApply, apply = part != kPartPre;
+    const bool all = part == kPartAll;
+    const bool pre = all || part == kPartPre, apply = all || part == kPartApply, post = all || part == kPartPost;
     if (pre) k_upload<<<kCopyBlocks, 256, 0, st>>>(a);
     if (t.strategy == DBTSDF_STRATEGY_ATOMIC) {
         if (pre) {
@@ -1415,20 +1416,21 @@ hipError_t launch_pipeline(const PipeArgs &a, const Tuning &t, uint32_t points_c
             k_front<<<pb, kPtThreads, 0, st>>>(a, info);
             k_select_atomic<<<sb, kSelThreads, 0, st>>>(a, info);
         }
-        if (!apply) return hipGetLastError();
         // the row kernel covers K <= 11, cube shadows with r_s^2 <= 9 and grids
         // with Nx % 4 == 0 whose window offsets fit 32 bits; everything else
         // takes the generic per-row kernel
-        if (a.small_offsets && a.quad_rows && a.tab.K <= kMaxPointK && a.tab.n_q <= (uint32_t)kRowPad &&
-            a.tab.n_bins == 26 && a.tab.shadow_r2 <= 9) {
-            if (a.single_scan)
-                k_apply_points<true><<<t.apply_blocks, kPtThreads, 0, st>>>(a, info);
-            else
-                k_apply_points<false><<<t.apply_blocks, kPtThreads, 0, st>>>(a, info);
-        } else {
-            k_apply_atomic<<<t.apply_blocks, kPtThreads, 0, st>>>(a, info);
+        if (apply) {
+            if (a.small_offsets && a.quad_rows && a.tab.K <= kMaxPointK && a.tab.n_q <= (uint32_t)kRowPad &&
+                a.tab.n_bins == 26 && a.tab.shadow_r2 <= 9) {
+                if (a.single_scan)
+                    k_apply_points<true><<<t.apply_blocks, kPtThreads, 0, st>>>(a, info);
+                else
+                    k_apply_points<false><<<t.apply_blocks, kPtThreads, 0, st>>>(a, info);
+            } else {
+                k_apply_atomic<<<t.apply_blocks, kPtThreads, 0, st>>>(a, info);
+            }
         }
-        k_download<<<kCopyBlocks, 256, 0, st>>>(a, info);
+        if (post) k_download<<<kCopyBlocks, 256, 0, st>>>(a, info);
         return hipGetLastError();
     }
     apply_fn f = find_apply(t, a.tab.R);
@@ -1441,10 +1443,8 @@ hipError_t launch_pipeline(const PipeArgs &a, const Tuning &t, uint32_t points_c
         k_offsets<<<blocks_for(points_cap, kPtThreads, 256), kPtThreads, 0, st>>>(a);
         k_fill_pairs<<<pb, kPtThreads, 0, st>>>(a, info);
     }
-    if (apply) {
-        hipLaunchKernelGGL(f, dim3(t.apply_blocks), dim3(t.threads), 0, st, a);
-        k_download<<<kCopyBlocks, 256, 0, st>>>(a, info);
-    }
+    if (apply) hipLaunchKernelGGL(f, dim3(t.apply_blocks), dim3(t.threads), 0, st, a);
+    if (post) k_download<<<kCopyBlocks, 256, 0, st>>>(a, info);
     return hipGetLastError();
 }
 

@@ -5,14 +5,23 @@
 
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <memory>
 #include <string>
 #include <vector>
 
 #include "internal.h"
 
+namespace dbtsdf {
+struct DeviceTables;
+}
+
 struct dbtsdf_kernel_set {
     std::unique_ptr<dbtsdf::KernelSet> ks;
+    // device copies of the tables, one per device, shared by the grids made
+    // from this kernel set (and kept alive by them)
+    std::mutex mu;
+    std::map<int, std::shared_ptr<dbtsdf::DeviceTables>> dev;
 };
 
 namespace dbtsdf {
@@ -104,7 +113,7 @@ struct dbtsdf_grid {
     uint32_t *mask = nullptr;
     uint32_t *packed = nullptr;
     uint64_t n_voxels = 0;
-    std::unique_ptr<dbtsdf::DeviceTables> tables;
+    std::shared_ptr<dbtsdf::DeviceTables> tables;
     dbtsdf::Tuning tuning;
     uint32_t *brick_cnt = nullptr;
     uint32_t *brick_slot = nullptr;
