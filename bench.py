@@ -248,11 +248,13 @@ def run_serve(db, torch, seconds, warm_s, rate_hz, n_robots, scans_per_robot, se
     return out
 
 
-def cpu_baseline(gdef, scans, budget_s=15.0):
+def cpu_baseline(gdef, scans, kparams, budget_s=15.0):
     """The CPU oracle, single-threaded, on the first scans of the same sequence."""
     from oracle.oracle import Oracle
     from synth import scene as synth
-    o = Oracle(dims=gdef["dims"], voxel_size=gdef["voxel_size"], origin=gdef["origin"], **synth.KERNEL_DEFAULTS)
+    kw = dict(synth.KERNEL_DEFAULTS)
+    kw.update(kparams)
+    o = Oracle(dims=gdef["dims"], voxel_size=gdef["voxel_size"], origin=gdef["origin"], **kw)
     m, p = o.new_grid()
     upd, t_tot, n = 0, 0.0, 0
     for pose, pts in scans:
@@ -398,6 +400,8 @@ def main():
     ap.add_argument("--serve-scans-per-robot", type=int, default=6)
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--c4", action="store_true", help="also run the 64-map batching workload (about 160 GB of grids)")
+    ap.add_argument("--kernel", choices=("workload", "paper"), default="workload",
+                    help="kernel set: the workload's (K = 11, 26 cube bins) or the paper's (K = 21, 40 x 40 bins)")
     ap.add_argument("--tuning", type=str, default="", help="JSON tuning to use instead of autotuning")
     args = ap.parse_args()
 
@@ -423,8 +427,9 @@ def main():
     gdef = synth.config_grid(cfg)
     n_seq = synth.CONFIGS[cfg]["scans"]
     scans, dev = load_scans(cfg, min(n_seq, args.warmup + args.steps), torch)
-    ks = db.KernelSet(kernel_size=11, binning="cube26", shadow_r2=9)
-    K3 = 11 ** 3
+    kparams = dict(kernel_size=11, binning="cube26", shadow_r2=9) if args.kernel == "workload" else \
+        dict(kernel_size=21, binning="azel", bins_az=40, bins_el=40, shadow_r2=9)
+    ks = db.KernelSet(**kparams)
 
     tuning = json.loads(args.tuning) if args.tuning else None
     if tuning is None and not args.no_autotune:
@@ -463,8 +468,12 @@ def main():
     apply_ms = prof["apply_ms"] / max(prof["applies"], 1)
     call_ms = prof["call_ms"] / max(prof["calls"], 1)
     achieved = apply_bytes / (apply_ms * 1e-3) / 1e9
-    kname = (f"k_apply_brick<{tuning['brick'][0]},{tuning['brick'][1]},{tuning['brick'][2]},"
-             f"{tuning['block_threads']}>" if tuning["strategy"] == "brick" else "k_apply_points<true>")
+    if tuning["strategy"] == "brick":
+        kname = f"k_apply_brick<{tuning['brick'][0]},{tuning['brick'][1]},{tuning['brick'][2]},{tuning['block_threads']}>"
+    elif kparams["kernel_size"] <= 11 and kparams["binning"] == "cube26" and gdef["dims"][0] % 4 == 0:
+        kname = "k_apply_points<true>"   # the row kernel of the plain one-scan call
+    else:
+        kname = "k_apply_atomic"
     traffic = None
     tfile = os.path.join(ROOT, "profiles", f"traffic_c{cfg}.json")
     if os.path.exists(tfile):
@@ -522,7 +531,7 @@ def main():
         c4 = run_c4(db, torch, ks, synth.CONFIGS[4]["maps"], synth.CONFIGS[4]["scans"], tuning)
         log(f"c4: {c4}")
 
-    cpu = None if args.no_cpu else cpu_baseline(gdef, scans[: min(len(scans), 80)])
+    cpu = None if args.no_cpu else cpu_baseline(gdef, scans[: min(len(scans), 80)], kparams)
 
     mean_pts = float(np.mean([int(p.shape[0]) for _, p in scans]))
     out = {
@@ -540,7 +549,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": synth.CONFIGS[cfg]["name"], "grid": list(gdef["dims"]),
                    "voxel_size_m": round(gdef["voxel_size"], 6), "mean_points_per_scan": mean_pts,
-                   "kernel": "K=11 (11^3), cube26 bins, r_s^2=9, T=5, H_max=65535, first-return dedup",
+                   "kernel": ("K=11 (11^3), cube26 bins" if args.kernel == "workload" else
+                              "K=21 (21^3), 40x40 azimuth/elevation bins (the paper's kernel set)")
+                             + ", r_s^2=9, T=5, H_max=65535, first-return dedup",
                    "form": "plain: one scan per launch sequence, points resident in HBM",
                    "tuning": tuning},
         "scans_per_s": args.steps / dt,

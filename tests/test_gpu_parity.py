@@ -184,6 +184,30 @@ def test_config1_full_grid(db):
     assert ref["n_integrated"] > 5000
 
 
+PAPER_KERNEL = dict(kernel_size=21, binning="azel", bins_az=40, bins_el=40, shadow_r2=9)
+
+
+@pytest.mark.parametrize("tuning", [dict(strategy="atomic"), dict(strategy="brick", brick=(32, 8, 8), block_threads=256)],
+                         ids=["atomic", "brick32x8x8"])
+def test_paper_kernel_set_config1(db, tuning):
+    """The paper's own kernel set (Sec. III-B: K = 21, 40 x 40 direction bins) on the 16x1024 scan
+    into 256^3 @ 0.1 m: whole grid and statistics against the oracle."""
+    gdef = synth.config_grid(1)
+    kw = dict(synth.KERNEL_DEFAULTS)
+    kw.update(PAPER_KERNEL)
+    o, g, _ = P.make_pair(gdef["dims"], gdef["voxel_size"], gdef["origin"], **kw)
+    g.set_tuning(**tuning)
+    m, p = o.new_grid()
+    for pose, pts in synth.config_scans(1, 0, [0]):
+        ref = o.integrate(m, p, pose, pts)
+        st = g.integrate(pose, P.to_device(pts))
+        g.sync()
+        P.assert_stats_equal(st.as_dict(), ref, traffic=False, what="c1 paper kernel")
+    gm, gp = P.gpu_planes(g)
+    P.assert_grids_equal(gm, gp, m, p, what="c1 paper kernel")
+    assert ref["n_integrated"] > 3000
+
+
 def test_config2_full_grid_three_scans(db):
     """1024x1024x256 @ 0.05 m, 64x1024 scans along the trajectory: whole grid after 3 scans."""
     (o, g, _), gdef = _config_grid_pair(db, 2, count_traffic=True)
