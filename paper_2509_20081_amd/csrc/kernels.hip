@@ -936,13 +936,15 @@ __global__ __launch_bounds__(kSelThreads) void k_select_atomic(PipeArgs a, const
     }
 }
 
-// One wavefront per surviving point, straight into HBM: read-first atomicAnd
-// (eq. 4) and the guard-bit counter (eqs. 5-6): every add that sees a raw
-// count >= H_max is cancelled, and the add that sees T - 1 clears the sign.
-// Bits 16-30 absorb the transient overshoot of concurrent adds. Each lane
-// issues the loads of kAtomicBatch cells before it compares any of them, so a
-// point costs a few memory round trips rather than one per cell row.
-constexpr int kAtomicBatch = 2;
+// One wavefront per surviving point, straight into HBM (any kernel size,
+// binning and grid): read-first atomicAnd (eq. 4) and the guard-bit counter
+// (eqs. 5-6): every add that sees a raw count >= H_max is cancelled, and the
+// add that sees T - 1 clears the sign. Bits 16-30 absorb the transient
+// overshoot of concurrent adds. The lanes cover floor(64 / K) rows of K cells
+// per pass; each lane issues the loads of kAtomicBatch passes before it
+// compares any of them, and the shadow adds of a point go out together.
+constexpr int kAtomicBatch = 8;
+constexpr int kShadowBatch = 4;
 constexpr uint32_t kXcds = 8;           // accelerator complex dies of the MI355X
 
 __global__ __launch_bounds__(kPtThreads) void k_apply_atomic(PipeArgs a, const CallInfo *info) {
@@ -967,43 +969,54 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_atomic(PipeArgs a, const C
     const int ox = (int)xi - R;
     for (uint32_t e = lo + slot * (blockDim.x >> 6) + (threadIdx.x >> 6); e < n_surv; e += waves) {
         const uint4 r = a.surv_rec[e];
-        const DevGrid g = a.grids[a.survivors[e]];
+        const DevGrid g = uniform_grid(a.grids[a.survivors[e]]);
+        // the window's first cell (x - R, y - R, z - R); the front end admitted
+        // only points whose whole window lies in the grid
+        const size_t corner = (size_t)(r.x - (uint32_t)R) +
+                              (size_t)g.nx * ((size_t)(r.y - (uint32_t)R) + (size_t)g.ny * (size_t)(r.z - (uint32_t)R));
+        gu32 *mb = glob(g.mask) + corner;
+        gu32 *pb = glob(g.packed) + corner;
         for (uint32_t r0 = 0; r0 < rows; r0 += rpi * kAtomicBatch) {
             uint32_t old[kAtomicBatch], m[kAtomicBatch];
-            size_t lin[kAtomicBatch];
+            size_t off[kAtomicBatch];
             bool on[kAtomicBatch];
 #pragma unroll
             for (int u = 0; u < kAtomicBatch; ++u) {
                 const uint32_t rr = r0 + (uint32_t)u * rpi + ri;
                 on[u] = lane_on && rr < rows;
-                old[u] = 0u;
-                m[u] = 0u;
-                lin[u] = 0;
-                if (on[u]) {
-                    const uint32_t rz = (rr * mag) >> 20;
-                    const uint32_t ry = rr - rz * wx;
-                    const int oy = (int)ry - R, oz = (int)rz - R;
-                    const uint32_t q = l1 ? (uint32_t)(abs(ox) + abs(oy) + abs(oz)) : (uint32_t)(ox * ox + oy * oy + oz * oz);
-                    m[u] = lut[q];
-                    lin[u] = (size_t)(r.x + ox) + (size_t)g.nx * ((size_t)(r.y + oy) + (size_t)g.ny * (size_t)(r.z + oz));
-                    old[u] = g.mask[lin[u]];
-                }
+                const uint32_t rz = (rr * mag) >> 20;
+                const uint32_t ry = rr - rz * wx;
+                const int oy = (int)ry - R, oz = (int)rz - R;
+                const uint32_t q = l1 ? (uint32_t)(abs(ox) + abs(oy) + abs(oz)) : (uint32_t)(ox * ox + oy * oy + oz * oz);
+                m[u] = on[u] ? lut[q] : 0xFFFFFFFFu;
+                off[u] = (size_t)xi + (size_t)g.nx * ((size_t)ry + (size_t)g.ny * (size_t)rz);
+                old[u] = on[u] ? mb[off[u]] : 0u;
             }
 #pragma unroll
             for (int u = 0; u < kAtomicBatch; ++u)
-                if (on[u] && (old[u] & m[u]) != old[u]) atomicAnd(&g.mask[lin[u]], m[u]);
+                if (on[u] && (old[u] & m[u]) != old[u]) g_and(mb + off[u], m[u]);
         }
         const uint32_t bin = r.w & 0xFFFFu;
-        for (uint32_t j = t.sh_start[bin] + l; j < t.sh_start[bin + 1]; j += 64u) {
-            const uint32_t off = t.sh_off[j];
-            const int sx = (int)r.x + (int)(off & 255u) - R;
-            const int sy = (int)r.y + (int)((off >> 8) & 255u) - R;
-            const int sz = (int)r.z + (int)((off >> 16) & 255u) - R;
-            const size_t lin = (size_t)sx + (size_t)g.nx * ((size_t)sy + (size_t)g.ny * (size_t)sz);
-            const uint32_t old = atomicAdd(&g.packed[lin], 1u);
-            const uint32_t raw = old & 0x7FFFFFFFu;
-            if (raw >= g.hmax) atomicSub(&g.packed[lin], 1u);
-            else if (g.T >= 1u && raw == g.T - 1u) atomicAnd(&g.packed[lin], 0x7FFFFFFFu);
+        const uint32_t s0 = t.sh_start[bin], s1 = t.sh_start[bin + 1];
+        for (uint32_t j0 = s0; j0 < s1; j0 += 64u * kShadowBatch) {
+            uint32_t ov[kShadowBatch];
+            size_t so[kShadowBatch];
+            bool son[kShadowBatch];
+#pragma unroll
+            for (int k = 0; k < kShadowBatch; ++k) {
+                const uint32_t j = j0 + l + 64u * (uint32_t)k;
+                son[k] = j < s1;
+                const uint32_t pk = son[k] ? t.sh_off[j] : 0u;
+                so[k] = (size_t)(pk & 255u) + (size_t)g.nx * ((size_t)((pk >> 8) & 255u) + (size_t)g.ny * (size_t)((pk >> 16) & 255u));
+                ov[k] = son[k] ? g_add(pb + so[k], 1u) : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < kShadowBatch; ++k) {
+                if (!son[k]) continue;
+                const uint32_t raw = ov[k] & 0x7FFFFFFFu;
+                if (raw >= g.hmax) g_sub(pb + so[k], 1u);
+                else if (g.T >= 1u && raw == g.T - 1u) g_and(pb + so[k], 0x7FFFFFFFu);
+            }
         }
     }
 }
