@@ -1,34 +1,43 @@
 // gfx950 kernels of DB-TSDF scan integration (Sec. III-C of the paper).
 //
 // One call integrates a set of scans (one for the plain entry point, many for
-// the batched one) through this pass sequence on one stream:
+// the batched one) through this pass sequence on one stream, replayed from a
+// captured graph:
 //
+//   k_upload   the call's descriptors from its pinned host ring slot
 //   k_reset    zero the per-call counters
 //   k_front    per point: fp32 transform into the map frame, validity,
 //              voxelisation, K^3 bounds test, direction bin (eq. 2); the
 //              first-return-per-voxel rule (Sec. IV-B) by an atomicMin of the
 //              point index into a hash table keyed by (scan, voxel)
-//   k_select   per (point, brick) pair: survivor test; bucketing of survivors
-//              by the grid bricks their K^3 cube touches (the counter's
-//              atomicAdd gives the pair's rank in the brick's list)
-//   k_offsets  exclusive scan of the per-brick counts -> list offsets; heavy
-//              bricks are split into several apply work units
-//   k_fill     per pair: write the point index at its rank; release the
-//              hash slots
-//   k_apply    persistent: one workgroup owns one brick at a time in LDS,
-//              stamps the eq. 3 masks of every listed point with LDS atomicAnd
-//              (eq. 4) and counts shadow hits with LDS atomicAdd, then merges
-//              the brick into HBM once: mask &= stamp (write skipped when
-//              unchanged) and h = min(h + c, H_max) with the eq. 6 sign rule.
+//   then one of two strategies, with identical results:
+//   per point (default)
+//     k_select_atomic  survivor test, compacted survivor records, per-scan
+//                      statistics, release of the hash slots
+//     k_apply_points   one wavefront per survivor: the K^3 window in aligned
+//                      16-byte rows, eq. 4 by read-first atomicAnd, eqs. 5-6
+//                      by guard-bit counter atomics (k_apply_atomic: any K)
+//   per brick
+//     k_select_pairs   survivor test; bucketing of survivors by the grid
+//                      bricks their K^3 cube touches (the counter's atomicAdd
+//                      gives the pair's rank in the brick's list)
+//     k_stats, k_offsets, k_fill_pairs   statistics, list offsets and work
+//                      units (heavy bricks split), list fill
+//     k_apply_brick    persistent: one workgroup owns one brick at a time in
+//                      LDS, stamps the eq. 3 masks of every listed point with
+//                      LDS atomicAnd (eq. 4) and counts shadow hits with LDS
+//                      atomicAdd, then merges the brick into HBM once:
+//                      mask &= stamp (write skipped when unchanged) and
+//                      h = min(h + c, H_max) with the eq. 6 sign rule
+//   k_download the statistics counters into the ring slot
 //
 // Merging per brick is exact because the eq. 4 AND commutes and is
 // idempotent, and c unit steps of eq. 5 saturate to min(h + c, H_max) while
 // eq. 6 clears the sign iff h_old < T <= h_new; so the grid does not depend on
-// the order of points or scans. The alternative "atomic" strategy applies one
-// point per wavefront straight into HBM with 32-bit atomics.
+// the order of points or scans.
 //
 // Nothing here is a dense contraction, so MFMA is not used; the bound is HBM
-// and LDS/atomic throughput.
+// and L2/LDS atomic throughput.
 #include <hip/hip_runtime.h>
 
 #include <array>
