@@ -208,6 +208,28 @@ def test_paper_kernel_set_config1(db, tuning):
     assert ref["n_integrated"] > 3000
 
 
+@pytest.mark.parametrize("strategy", ["atomic", "brick"])
+def test_plain_graph_replays_over_the_ring(db, strategy):
+    """20 plain calls into one grid (more than the 16 ring slots, so every slot's captured graph is
+    replayed again), eager work between calls: statistics and grid checked after every call."""
+    import torch
+    dims = (64, 64, 48)
+    o, g, _ = P.make_pair(dims, 0.1, (0.0, 0.0, 0.0), **synth.KERNEL_DEFAULTS)
+    g.set_tuning(strategy=strategy)
+    m, p = o.new_grid()
+    rng = np.random.default_rng(7)
+    for k in range(20):
+        pose = synth.random_pose(rng, np.array(dims) * 0.05 - 0.5, np.array(dims) * 0.05 + 0.5)
+        pts = synth.random_cloud(rng, int(rng.integers(200, 3000)), -np.array(dims) * 0.04, np.array(dims) * 0.04)
+        ref = o.integrate(m, p, pose, pts)
+        st = g.integrate(pose, P.to_device(pts))
+        _ = torch.ones(4096, device="cuda").cumsum(0)[-1].item()   # unrelated eager work
+        g.sync()
+        P.assert_stats_equal(st.as_dict(), ref, traffic=False, what=f"call {k}")
+        gm, gp = P.gpu_planes(g)
+        P.assert_grids_equal(gm, gp, m, p, what=f"call {k}")
+
+
 def test_config2_full_grid_three_scans(db):
     """1024x1024x256 @ 0.05 m, 64x1024 scans along the trajectory: whole grid after 3 scans."""
     (o, g, _), gdef = _config_grid_pair(db, 2, count_traffic=True)
