@@ -36,6 +36,11 @@ METRIC = "voxel-updates/s & scans/s (batched vs plain, bit-exact); p50/p99 scan 
 HBM_PEAK_GBS = 8000.0
 LDS_ATOMIC_OPS = 256 * 32 * 2.4e9
 RING_SLOTS = 16  # calls in flight per grid / batch context; each slot has its own graphs
+# the plain form's timed region times every 4th call with HIP events (a timed
+# call launches its apply kernel between events instead of inside the call's
+# graph, which costs it some microseconds); 4 divides the ring, so each ring
+# slot is always timed or never and the warm-up captures every graph used
+PROF_EVERY = 4
 
 
 def log(msg):
@@ -102,15 +107,17 @@ def run_plain(db, torch, gdef, ks, dev, warmup, steps, tuning, profile=True):
     n_seq = len(dev)
     # the warm-up runs as profiled as the timed region: every ring slot's
     # graphs (16 slots) are captured before the clock starts
+    if warmup < RING_SLOTS:
+        log(f"warm-up of {warmup} calls visits fewer than the {RING_SLOTS} ring slots: "
+            "some graph captures fall into the timed region")
     if profile:
-        g.set_profiling(True)
+        g.set_profiling(True, every=PROF_EVERY)
     for k in range(warmup):
         pose, pts = dev[k % n_seq]
         g.integrate(pose, pts)
     g.sync()
     if profile:
-        g.set_profiling(False)
-        g.set_profiling(True)  # restart the counters
+        g.set_profiling(True, every=PROF_EVERY)  # restart the totals (the call count runs on)
     torch.cuda.synchronize()
     with no_gc():
         t0 = time.perf_counter()
@@ -484,6 +491,8 @@ def main():
     visits = float(np.mean([t["voxel_updates"] for t in sd]))
     roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
                     traffic=traffic, kernel=kname, avg_launch_us=apply_ms * 1e3,
+                    timed_launches=prof["applies"],
+                    timing="HIP events around the apply kernel of every %dth call of the timed region" % PROF_EVERY,
                     measured_copy_gbs=copy_gbs, frac_vs_copy=achieved / copy_gbs,
                     secondary=dict(ceiling="LDS/atomic dword ops: 256 CUs x 32 per clock x 2.4 GHz",
                                    peak_ops_per_s=LDS_ATOMIC_OPS, achieved_ops_per_s=visits / (apply_ms * 1e-3),

@@ -281,14 +281,19 @@ dbtsdf_status dbtsdf_write_voxels(dbtsdf_grid *g, const uint32_t *mask_in, const
 void dbtsdf_destroy_grid(dbtsdf_grid *g);
 
 /* ---------------------------------------------------------------- profiling
- * Device-side timing with HIP events on the work's own stream. When enabled,
- * each integrate call (plain or batched) records events at its start, just
+ * Device-side timing with HIP events on the work's own stream. `enable` is a
+ * period: 0 turns profiling off, N >= 1 times every N-th integrate call
+ * (plain or batched; 1 = every call): those whose index, counted over all
+ * calls on the grid (batch context) since its creation, is a multiple of N.
+ * Negative is DBTSDF_ERR_INVALID_ARG. A timed call records events at its start, just
  * before the apply kernel (eqs. 4-6, the dominant kernel) and just after it;
  * the apply kernel is then launched directly between its two events, and the
- * passes before and after it are replayed from graphs. call time = start to
- * the end of the apply kernel. read_profile synchronises the stream and
- * returns the accumulated milliseconds and counts since profiling was
- * (re)enabled. Any output may be NULL. Enabling resets the totals.
+ * passes before and after it are replayed from graphs (the split costs the
+ * timed call some microseconds of launch gaps, which a period above 1
+ * spreads thin). call time = start to the end of the apply kernel.
+ * read_profile synchronises the stream and returns the accumulated
+ * milliseconds and counts of the timed calls since profiling was last set.
+ * Any output may be NULL. Setting resets the totals.
  */
 dbtsdf_status dbtsdf_set_profiling(dbtsdf_grid *g, int enable);
 dbtsdf_status dbtsdf_read_profile(dbtsdf_grid *g, double *call_ms, uint64_t *calls, double *apply_ms,

@@ -71,6 +71,14 @@ def _points_arg(points):
     return arr.ctypes.data_as(C.c_void_p), int(arr.shape[0]), 0, arr
 
 
+def _period(enable, every) -> int:
+    if not enable:
+        return 0
+    if int(every) < 1:
+        raise ValueError("every must be >= 1")
+    return int(every)
+
+
 def _read_profile(fn, h) -> dict:
     cm, am = C.c_double(), C.c_double()
     cn, an = C.c_uint64(), C.c_uint64()
@@ -207,8 +215,9 @@ class Grid:
         L.check(L.lib().dbtsdf_reset_grid(self._h), "reset_grid")
 
     # -- device timing ----------------------------------------------------------
-    def set_profiling(self, enable=True) -> None:
-        L.check(L.lib().dbtsdf_set_profiling(self._h, 1 if enable else 0), "set_profiling")
+    def set_profiling(self, enable=True, every: int = 1) -> None:
+        """Time every `every`-th integrate call with HIP events (off when `enable` is false)."""
+        L.check(L.lib().dbtsdf_set_profiling(self._h, _period(enable, every)), "set_profiling")
 
     def read_profile(self) -> dict:
         return _read_profile(L.lib().dbtsdf_read_profile, self._h)
@@ -323,8 +332,9 @@ class Batch:
         L.check(L.lib().dbtsdf_batch_sync(self._h), "batch_sync")
         self._keep = self._keep[-4:]
 
-    def set_profiling(self, enable=True) -> None:
-        L.check(L.lib().dbtsdf_batch_set_profiling(self._h, 1 if enable else 0), "batch_set_profiling")
+    def set_profiling(self, enable=True, every: int = 1) -> None:
+        """Time every `every`-th launch with HIP events (off when `enable` is false)."""
+        L.check(L.lib().dbtsdf_batch_set_profiling(self._h, _period(enable, every)), "batch_set_profiling")
 
     def read_profile(self) -> dict:
         return _read_profile(L.lib().dbtsdf_batch_read_profile, self._h)

@@ -181,7 +181,10 @@ hipError_t Workspace::ensure(uint32_t n_points, uint32_t n_scans, uint32_t n_gri
     const uint64_t ic = (uint64_t)entry_factor * points_cap;
     if (ic > 0xFFFFFFF0ull) return hipErrorInvalidValue;
     items_cap = entries_cap = (uint32_t)ic;
-    hash_cap = next_pow2(2ull * points_cap, 8192);
+    // a sparse table keeps linear probing short: a wavefront's insert costs as
+    // many atomic round trips as its longest probe sequence (load <= 1/8 up to
+    // 2^21 points, never above 1/2)
+    hash_cap = next_pow2(std::max<uint64_t>(2ull * points_cap, std::min<uint64_t>(8ull * points_cap, 1ull << 24)), 8192);
     desc_bytes = sizeof(Ctrl) + sizeof(CallInfo) + (size_t)grids_cap * sizeof(DevGrid) + (size_t)scans_cap * sizeof(DevScan);
     const size_t ctr_words = (size_t)scans_cap * SC_N + (size_t)grids_cap * TC_N;
     struct A {
@@ -230,7 +233,8 @@ hipError_t Workspace::ensure_staging(size_t floats, hipStream_t st) {
     return e;
 }
 
-static_assert(sizeof(CallInfo) % 8 == 0 && sizeof(DevGrid) % 8 == 0 && sizeof(DevScan) % 8 == 0,
+static_assert(sizeof(Ctrl) % 8 == 0 && sizeof(CallInfo) % 8 == 0 && sizeof(DevGrid) % 8 == 0 &&
+                  sizeof(DevScan) % 8 == 0,
               "descriptors are copied in 8-byte words");
 
 // A ring slot's buffer: pinned, coherent host memory that the first and last
@@ -520,7 +524,8 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
     // exact unique-word counts need every brick merged by one work unit
     a.chunk = traffic ? 0u : tun.chunk;
     // the plain one-scan call has a kernel of its own (no per-point scan lookup)
-    a.single_scan = plain && live.size() == 1 ? 1u : 0u;
+    // (its front pass reads the scan descriptor from the host in 16-byte pieces)
+    a.single_scan = plain && live.size() == 1 && scans_off % 16 == 0 ? 1u : 0u;
     a.small_offsets = 1u;
     a.quad_rows = 1u;
     for (dbtsdf_grid *g : grids) {
@@ -530,8 +535,8 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
     }
 
     // plain calls, and batches that ask for it, replay captured graphs (one
-    // host call instead of one per pass); with profiling on, the apply runs
-    // as a part of its own between two events
+    // host call instead of one per pass); with profiling on, events bracket
+    // the call and its apply kernel
     const bool graphs = plain || use_graph;
     slot.prof = 0;
     auto run_part = [&](int part) -> hipError_t {
@@ -542,7 +547,12 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
         ++ws.replays;
         return hipGraphLaunch(ex, st);
     };
-    if (ws.profile) {
+    // with profiling on, the calls whose index is a multiple of prof_every
+    // are timed (the index runs over all calls, so with a period that
+    // divides the ring size a ring slot is always timed or never)
+    const uint64_t call_index = ws.n_calls++;
+    const bool timed = ws.prof_every && call_index % ws.prof_every == 0;
+    if (timed) {
         // the apply kernel is launched directly between its two events, so
         // they time the kernel rather than a graph launch around it
         e = hipEventRecord(slot.pe[0], st);
@@ -550,7 +560,7 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
         if (e == hipSuccess) e = hipEventRecord(slot.pe[1], st);
         if (e == hipSuccess) e = launch_pipeline(a, tun, ws.points_cap, st, kPartApply);
         if (e == hipSuccess) e = hipEventRecord(slot.pe[2], st);
-        if (e == hipSuccess) e = run_part(kPartPost);
+        if (e == hipSuccess && pipeline_has_post(tun)) e = run_part(kPartPost);
         slot.prof = 2;
     } else {
         e = run_part(kPartAll);
@@ -895,7 +905,8 @@ static dbtsdf_status read_prof(Workspace &ws, hipStream_t st, double *call_ms, u
 
 dbtsdf_status dbtsdf_set_profiling(dbtsdf_grid *g, int enable) {
     if (!g) return invalid("NULL grid");
-    g->ws->profile = enable != 0;
+    if (enable < 0) return invalid("negative profiling period");
+    g->ws->prof_every = (uint32_t)enable;
     g->ws->prof_call_ms = g->ws->prof_apply_ms = 0.0;
     g->ws->prof_calls = g->ws->prof_apply = 0;
     return DBTSDF_OK;
@@ -909,7 +920,8 @@ dbtsdf_status dbtsdf_read_profile(dbtsdf_grid *g, double *call_ms, uint64_t *cal
 
 dbtsdf_status dbtsdf_batch_set_profiling(dbtsdf_batch *b, int enable) {
     if (!b) return invalid("NULL batch");
-    b->ws->profile = enable != 0;
+    if (enable < 0) return invalid("negative profiling period");
+    b->ws->prof_every = (uint32_t)enable;
     b->ws->prof_call_ms = b->ws->prof_apply_ms = 0.0;
     b->ws->prof_calls = b->ws->prof_apply = 0;
     return DBTSDF_OK;

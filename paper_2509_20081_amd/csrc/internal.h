@@ -92,6 +92,8 @@ struct Ctrl {
     uint32_t total_entries;  // (point, brick) pairs listed
     uint32_t n_survivors;    // integrated points (atomic strategy)
     uint32_t n_work;         // apply work units (bricks, heavy ones split)
+    uint32_t select_done;    // workgroups of the select pass that have finished (atomic strategy)
+    uint32_t pad[3];
 };
 
 // Sizes of the current call, read by the kernels from device memory so that a
@@ -157,6 +159,9 @@ hipError_t launch_grid_init(uint32_t *mask, uint32_t *packed, uint64_t n, hipStr
 // the apply alone, and the passes after it (the split lets profiling bracket
 // the apply kernel with events).
 enum { kPartAll = 0, kPartPre = 1, kPartApply = 2, kPartPost = 3 };
+// The per-point strategy writes the statistics from its select pass: it has
+// no passes after the apply.
+inline bool pipeline_has_post(const Tuning &t) { return t.strategy != DBTSDF_STRATEGY_ATOMIC; }
 hipError_t launch_pipeline(const PipeArgs &a, const Tuning &t, uint32_t points_cap, hipStream_t st, int part);
 hipError_t launch_read_distance(const uint32_t *mask, const uint32_t *packed, int8_t *out, uint64_t n,
                                 hipStream_t st);

@@ -11,9 +11,11 @@
 //              first-return-per-voxel rule (Sec. IV-B) by an atomicMin of the
 //              point index into a hash table keyed by (scan, voxel)
 //   then one of two strategies, with identical results:
-//   per point (default)
+//   per point (default; a one-scan call folds k_upload and k_reset into
+//   k_front, and k_download into k_select_atomic: three passes in all)
 //     k_select_atomic  survivor test, compacted survivor records, per-scan
-//                      statistics, release of the hash slots
+//                      statistics, release of the hash slots; its last
+//                      workgroup writes the statistics into the ring slot
 //     k_apply_points   one wavefront per survivor: the K^3 window in aligned
 //                      16-byte rows, eq. 4 by read-first atomicAnd, eqs. 5-6
 //                      by guard-bit counter atomics (k_apply_atomic: any K)
@@ -29,7 +31,7 @@
 //                      atomicAdd, then merges the brick into HBM once:
 //                      mask &= stamp (write skipped when unchanged) and
 //                      h = min(h + c, H_max) with the eq. 6 sign rule
-//   k_download the statistics counters into the ring slot
+//   k_download the statistics counters into the ring slot (per brick)
 //
 // Merging per brick is exact because the eq. 4 AND commutes and is
 // idempotent, and c unit steps of eq. 5 saturate to min(h + c, H_max) while
@@ -232,13 +234,21 @@ __device__ __forceinline__ uint32_t front_end(const DevScan &s, const DevGrid &g
 constexpr int kPtThreads = 256;
 constexpr int kSelThreads = 256;    // one claim atomic per block of points
 
-__global__ void k_reset(PipeArgs a, const CallInfo *info) {
-    const uint32_t n_sc = info->n_scans * SC_N, n_tc = info->n_grids * TC_N;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_sc + n_tc + 4; i += gridDim.x * blockDim.x) {
+constexpr uint32_t kCtrlWords = sizeof(Ctrl) / 4;
+
+// Clears the call's counters: threads [first, first + stride) of the launch.
+__device__ __forceinline__ void reset_counters(const PipeArgs &a, uint32_t n_scans, uint32_t n_grids, uint32_t first,
+                                               uint32_t stride) {
+    const uint32_t n_sc = n_scans * SC_N, n_tc = n_grids * TC_N;
+    for (uint32_t i = first; i < n_sc + n_tc + kCtrlWords; i += stride) {
         if (i < n_sc) a.scan_ctr[i] = 0ull;
         else if (i < n_sc + n_tc) a.traffic_ctr[i - n_sc] = 0ull;
         else ((uint32_t *)a.ctrl)[i - n_sc - n_tc] = 0u;
     }
+}
+
+__global__ void k_reset(PipeArgs a, const CallInfo *info) {
+    reset_counters(a, info->n_scans, info->n_grids, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
 // First pass of a call: the descriptors, from the ring slot's pinned host
@@ -263,12 +273,56 @@ __global__ __launch_bounds__(256) void k_download(PipeArgs a, const CallInfo *in
     __threadfence_system();
 }
 
-__global__ __launch_bounds__(kPtThreads) void k_front(PipeArgs a, const CallInfo *info) {
+// Transform, voxelise, bin and dedup-insert every point of the call. In a
+// one-scan call (ONE) the passes that copy the descriptors in and clear the
+// counters are folded in: every workgroup reads what it needs of the call's
+// descriptors (the sizes, the grid's dimensions, the scan) straight from the
+// ring slot's pinned host buffer into LDS, in eight 16-byte reads, and
+// workgroup 0 also writes the whole device copy that the later passes read
+// and clears the counters (no pass before this one touches either).
+constexpr uint32_t kInfoWords = sizeof(CallInfo) / 8, kGridWords = sizeof(DevGrid) / 8,
+                   kScanWords = sizeof(DevScan) / 8;
+constexpr uint32_t kOneDescWords = kInfoWords + kGridWords + kScanWords;
+static_assert(kOneDescWords <= 64 && kCtrlWords + SC_N + TC_N <= (uint32_t)kPtThreads - 128, "one pass of workgroup 0");
+static_assert(sizeof(CallInfo) == 16 && offsetof(DevGrid, nx) == 32 && sizeof(DevScan) <= 96,
+              "the one-scan front pass reads the descriptors in these 16-byte pieces");
+
+template <bool ONE>
+__global__ __launch_bounds__(kPtThreads) void k_front(PipeArgs a, const CallInfo *info_dev) {
+    __shared__ uint4 s_desc[ONE ? 8 : 1];
+    const CallInfo *info = info_dev;
+    const DevScan *scans = a.scans;
+    const DevGrid *grids = a.grids;
+    DevGrid g_one{};
+    if constexpr (ONE) {
+        const uint32_t t = threadIdx.x;
+        // host layout: CallInfo, DevGrid[grids_cap] and, at desc_scans_off
+        // (a multiple of 16), DevScan[n_scans]; piece 1 is the grid's
+        // nx, ny, nz (and nbx), pieces 2-7 the scan (the last runs 8 bytes
+        // into the next scan slot, which the buffer always holds)
+        const uint4 *h16 = reinterpret_cast<const uint4 *>(a.host_desc);
+        if (t < 8u) s_desc[t] = h16[t == 0u ? 0u : t == 1u ? 3u : a.desc_scans_off / 16u + (t - 2u)];
+        if (blockIdx.x == 0) {
+            if (t >= 64u && t < 64u + kOneDescWords) {
+                const uint32_t w = t - 64u;
+                const uint32_t src = w < kInfoWords + kGridWords ? w : a.desc_scans_off / 8u + (w - kInfoWords - kGridWords);
+                reinterpret_cast<uint2 *>(a.ctrl + 1)[src] = a.host_desc[src];
+            } else if (t >= 128u) {
+                reset_counters(a, 1u, 1u, t - 128u, kPtThreads - 128u);
+            }
+        }
+        __syncthreads();
+        info = reinterpret_cast<const CallInfo *>(s_desc);
+        g_one.nx = s_desc[1].x;
+        g_one.ny = s_desc[1].y;
+        g_one.nz = s_desc[1].z;
+        scans = reinterpret_cast<const DevScan *>(s_desc + 2);
+    }
     const uint32_t n = info->n_points, n_scans = info->n_scans;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const uint32_t s = find_scan(a.scans, n_scans, i);
-        const DevScan &sc = a.scans[s];
-        const DevGrid &g = a.grids[sc.grid];
+        const uint32_t s = ONE ? 0u : find_scan(scans, n_scans, i);
+        const DevScan &sc = scans[s];
+        const DevGrid &g = ONE ? g_one : grids[sc.grid];
         const uint32_t j = i - sc.begin;
         const float px = sc.pts[3 * (size_t)j + 0];
         const float py = sc.pts[3 * (size_t)j + 1];
@@ -943,6 +997,33 @@ __global__ __launch_bounds__(kSelThreads) void k_select_atomic(PipeArgs a, const
         }
         __syncthreads();  // s_red and s_base are reused by the next round
     }
+    // The pass that copies the statistics out is folded in here: they are
+    // final once every workgroup's counter atomics are done (the apply does
+    // not touch them), so the last workgroup to finish writes them into the
+    // ring slot's pinned host buffer.
+    // Counters are touched only by device-scope atomics, performed at one
+    // coherence point; a wave's atomics are acknowledged once its vector
+    // memory count drains, so after the drain and the barrier the workgroup's
+    // updates are all in place before it counts itself done. (A device-scope
+    // fence here would write back and invalidate the XCD's L2 in every wave.)
+    __shared__ uint32_t s_last;
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0)
+        s_last = __hip_atomic_fetch_add(&a.ctrl->select_done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                         gridDim.x - 1u
+                     ? 1u
+                     : 0u;
+    __syncthreads();
+    if (s_last) {
+        const uint32_t n_s = info->n_scans * SC_N, n_t = info->n_grids * TC_N;
+        for (uint32_t i = threadIdx.x; i < n_s + n_t; i += blockDim.x) {
+            unsigned long long *src = i < n_s ? &a.scan_ctr[i] : &a.traffic_ctr[i - n_s];
+            a.host_ctr[i < n_s ? (size_t)i : (size_t)a.scans_cap * SC_N + (i - n_s)] =
+                __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");  // system scope: the host reads them
+    }
 }
 
 // One wavefront per surviving point, straight into HBM (any kernel size,
@@ -1431,11 +1512,17 @@ hipError_t launch_pipeline(const PipeArgs &a, const Tuning &t, uint32_t points_c
     while ((uint64_t)stat_chunk * 512 < points_cap) stat_chunk *= 2;
     const bool all = part == kPartAll;
     const bool pre = all || part == kPartPre, apply = all || part == kPartApply, post = all || part == kPartPost;
-    if (pre) k_upload<<<kCopyBlocks, 256, 0, st>>>(a);
     if (t.strategy == DBTSDF_STRATEGY_ATOMIC) {
+        // three passes: front (one-scan calls copy their descriptors in and
+        // clear the counters there), select (writes the statistics out), apply
         if (pre) {
-            k_reset<<<8, 256, 0, st>>>(a, info);
-            k_front<<<pb, kPtThreads, 0, st>>>(a, info);
+            if (a.single_scan) {
+                k_front<true><<<pb, kPtThreads, 0, st>>>(a, info);
+            } else {
+                k_upload<<<kCopyBlocks, 256, 0, st>>>(a);
+                k_reset<<<8, 256, 0, st>>>(a, info);
+                k_front<false><<<pb, kPtThreads, 0, st>>>(a, info);
+            }
             k_select_atomic<<<sb, kSelThreads, 0, st>>>(a, info);
         }
         // the row kernel covers K <= 11, cube shadows with r_s^2 <= 9 and grids
@@ -1452,14 +1539,15 @@ hipError_t launch_pipeline(const PipeArgs &a, const Tuning &t, uint32_t points_c
                 k_apply_atomic<<<t.apply_blocks, kPtThreads, 0, st>>>(a, info);
             }
         }
-        if (post) k_download<<<kCopyBlocks, 256, 0, st>>>(a, info);
+        (void)post;
         return hipGetLastError();
     }
     apply_fn f = find_apply(t, a.tab.R);
     if (!f) return hipErrorInvalidValue;
     if (pre) {
+        k_upload<<<kCopyBlocks, 256, 0, st>>>(a);
         k_reset<<<8, 256, 0, st>>>(a, info);
-        k_front<<<pb, kPtThreads, 0, st>>>(a, info);
+        k_front<false><<<pb, kPtThreads, 0, st>>>(a, info);
         k_select_pairs<<<sb, kSelThreads, 0, st>>>(a, info);
         k_stats<<<blocks_for(points_cap, stat_chunk, 512), kPtThreads, 0, st>>>(a, info, stat_chunk);
         k_offsets<<<blocks_for(points_cap, kPtThreads, 256), kPtThreads, 0, st>>>(a);

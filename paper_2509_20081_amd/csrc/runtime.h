@@ -86,7 +86,8 @@ struct Workspace {
     std::map<std::string, GraphEntry> graphs;
     hipStream_t cap_stream = nullptr;    // private stream the graphs are captured on
     uint64_t captures = 0, replays = 0;
-    bool profile = false;
+    uint32_t prof_every = 0;             // time every prof_every-th call (0: profiling off)
+    uint64_t n_calls = 0;                // integrate calls enqueued on this workspace
     double prof_call_ms = 0.0, prof_apply_ms = 0.0;
     uint64_t prof_calls = 0, prof_apply = 0;
 

@@ -230,6 +230,35 @@ def test_plain_graph_replays_over_the_ring(db, strategy):
         P.assert_grids_equal(gm, gp, m, p, what=f"call {k}")
 
 
+@pytest.mark.parametrize("strategy", ["atomic", "brick"])
+def test_profiling_period_mixes_call_forms(db, strategy):
+    """Profiling every 3rd call: timed calls (split launch) and untimed calls (one graph) interleave
+    over the ring; the totals count the timed calls only and every call matches the oracle."""
+    dims = (64, 64, 48)
+    o, g, _ = P.make_pair(dims, 0.1, (0.0, 0.0, 0.0), **synth.KERNEL_DEFAULTS)
+    g.set_tuning(strategy=strategy)
+    with pytest.raises(ValueError):
+        g.set_profiling(True, every=0)
+    g.set_profiling(True, every=3)
+    m, p = o.new_grid()
+    rng = np.random.default_rng(11)
+    n_calls = 19
+    for k in range(n_calls):
+        pose = synth.random_pose(rng, np.array(dims) * 0.05 - 0.5, np.array(dims) * 0.05 + 0.5)
+        pts = synth.random_cloud(rng, int(rng.integers(200, 3000)), -np.array(dims) * 0.04, np.array(dims) * 0.04)
+        ref = o.integrate(m, p, pose, pts)
+        st = g.integrate(pose, P.to_device(pts))
+        g.sync()
+        P.assert_stats_equal(st.as_dict(), ref, traffic=False, what=f"call {k}")
+    gm, gp = P.gpu_planes(g)
+    P.assert_grids_equal(gm, gp, m, p, what="after the profiled run")
+    pr = g.read_profile()
+    assert pr["calls"] == pr["applies"] == (n_calls + 2) // 3   # call indices 0, 3, ..., 18
+    assert 0.0 < pr["apply_ms"] <= pr["call_ms"]
+    g.set_profiling(False)
+    assert g.read_profile()["calls"] == 0
+
+
 def test_config2_full_grid_three_scans(db):
     """1024x1024x256 @ 0.05 m, 64x1024 scans along the trajectory: whole grid after 3 scans."""
     (o, g, _), gdef = _config_grid_pair(db, 2, count_traffic=True)
