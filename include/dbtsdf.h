@@ -146,6 +146,8 @@ typedef enum {
  * (0 = default 64, 0xFFFFFFFF = never split). With DBTSDF_STRATEGY_ATOMIC the
  * brick is ignored. Any valid tuning gives bit-identical grids. A new grid
  * starts with DBTSDF_STRATEGY_ATOMIC, brick 32x8x8, 256 threads, chunk 64.
+ * A call that counts traffic (DBTSDF_COUNT_TRAFFIC) or spans more than 65536
+ * grids runs with DBTSDF_STRATEGY_BRICK whatever the tuning says.
  */
 typedef struct {
     uint32_t strategy;

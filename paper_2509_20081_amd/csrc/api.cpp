@@ -128,7 +128,7 @@ void Workspace::drop_graphs() {
 
 void Workspace::release() {
     drop_graphs();
-    void *ptrs[] = {d_desc, rec, pslot, hkeys, hvals, items, item_off, item_cnt, entries, survivors, ctr, staging, rank, work};
+    void *ptrs[] = {d_desc, rec, pslot, hkeys, hvals, items, item_off, item_cnt, entries, ctr, staging, rank, work};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     d_desc = nullptr;
@@ -137,7 +137,7 @@ void Workspace::release() {
     hkeys = nullptr;
     hvals = nullptr;
     items = nullptr;
-    item_off = item_cnt = survivors = rank = nullptr;
+    item_off = item_cnt = rank = nullptr;
     entries = nullptr;
     work = nullptr;
     ctr = nullptr;
@@ -202,7 +202,6 @@ hipError_t Workspace::ensure(uint32_t n_points, uint32_t n_scans, uint32_t n_gri
         {(void **)&entries, (size_t)entries_cap * sizeof(uint4)},
         {(void **)&rank, (size_t)entries_cap * 4},
         {(void **)&work, ((size_t)items_cap + entries_cap) * sizeof(uint4)},
-        {(void **)&survivors, (size_t)points_cap * 4},
         {(void **)&ctr, ctr_words * 8},
     };
     for (auto &a : al) {
@@ -412,6 +411,8 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
     }
     Tuning tun = g0->tuning;
     if (traffic) tun.strategy = DBTSDF_STRATEGY_BRICK;  // unique-word counts come from the brick merge
+    // the per-point strategy carries a survivor's grid in 16 bits
+    if (grids.size() > kMaxAtomicGrids) tun.strategy = DBTSDF_STRATEGY_BRICK;
     if (tun.apply_blocks == 0) tun.apply_blocks = (uint32_t)apply_blocks_default(tun, g0->K, g0->device);
     for (dbtsdf_grid *g : grids) {
         dbtsdf_status s = ensure_bricks(g);
@@ -506,7 +507,6 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
     a.rank = ws.rank;
     a.work = ws.work;
     a.entries = ws.entries;
-    a.survivors = ws.survivors;
     a.surv_rec = ws.entries;  // the brick lists' storage (at least one uint4 per point)
     a.host_desc = (const uint2 *)slot.host_dev;
     a.host_ctr = (unsigned long long *)((char *)slot.host_dev + ctr_off);

@@ -19,6 +19,7 @@ constexpr uint64_t kMaxScansPerCall = 1ull << 20;
 constexpr int kVoxelKeyBits = 40;               // dedup key = scan << 40 | linear voxel
 constexpr uint64_t kHashEmpty = ~0ull;
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
+constexpr uint32_t kMaxAtomicGrids = 1u << 16;  // per-point strategy: grid index in 16 bits of a survivor record
 
 // point record word w: bits 0-15 direction bin, bits 16-17 status,
 // bit 30 set by the select pass on returns that are integrated
@@ -119,8 +120,7 @@ struct PipeArgs {
     uint4 *entries;          // (voxel x, y, z, bin) of the listed points, grouped by brick
     uint32_t *rank;          // per (point, brick) pair: position in the brick's list
     uint4 *work;             // apply work units: (brick, grid, first entry, count | split << 31)
-    uint32_t *survivors;     // per-point strategy: grid index of each listed survivor
-    uint4 *surv_rec;         // per-point strategy: (voxel x, y, z, bin) of each listed survivor     // compacted survivor list (atomic strategy)
+    uint4 *surv_rec;         // per-point strategy: compacted survivors (voxel x, y, z, bin | grid << 16)
     unsigned long long *scan_ctr;     // n_scans * SC_N
     unsigned long long *traffic_ctr;  // n_grids * TC_N
     Ctrl *ctrl;              // followed in memory by the CallInfo

@@ -990,10 +990,9 @@ __global__ __launch_bounds__(kSelThreads) void k_select_atomic(PipeArgs a, const
         if (tot) {
             if (threadIdx.x == 0) s_base = atomicAdd(&a.ctrl->n_survivors, tot);
             __syncthreads();
-            if (surv) {
-                a.survivors[s_base + pos] = a.scans[s].grid;
-                a.surv_rec[s_base + pos] = make_uint4(r.x, r.y, r.z, r.w & 0xFFFFu);
-            }
+            // the record word carries the bin (bits 0-15) and the grid (bits
+            // 16-31; calls of more grids take the brick strategy)
+            if (surv) a.surv_rec[s_base + pos] = make_uint4(r.x, r.y, r.z, (r.w & 0xFFFFu) | (a.scans[s].grid << 16));
         }
         __syncthreads();  // s_red and s_base are reused by the next round
     }
@@ -1059,7 +1058,7 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_atomic(PipeArgs a, const C
     const int ox = (int)xi - R;
     for (uint32_t e = lo + slot * (blockDim.x >> 6) + (threadIdx.x >> 6); e < n_surv; e += waves) {
         const uint4 r = a.surv_rec[e];
-        const DevGrid g = uniform_grid(a.grids[a.survivors[e]]);
+        const DevGrid g = uniform_grid(a.grids[r.w >> 16]);
         // the window's first cell (x - R, y - R, z - R); the front end admitted
         // only points whose whole window lies in the grid
         const size_t corner = (size_t)(r.x - (uint32_t)R) +
@@ -1118,28 +1117,33 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_atomic(PipeArgs a, const C
 // eight vector loads per point, each lane's 16 bytes contiguous, instead of
 // K^3 / 64 dword loads whose lanes scatter over six rows. (The L1 tag lookups
 // of the scattered dword form bound the earlier version of this kernel.)
-// Each workgroup keeps in LDS the byte offset of every window row (dy, dz)
-// and, per alignment phase of the window and row, the eq. 3 masks of the four
-// cells a lane covers (16 bits each, -1 outside the window): one 8-byte LDS
-// read per row. Eq. 4 is the read-first atomicAnd where the mask loses bits.
-// The cube bins' shadows are offset lists in LDS; their counters take the
-// guard-bit atomics of eqs. 5-6, issued together with the window loads so
-// that one memory round trip serves both. Needs Nx % 4 == 0 (16-byte aligned
-// rows).
+// Each workgroup keeps in LDS, per alignment phase of the window and row, the
+// eq. 3 masks of the four cells a lane covers (16 bits each, -1 outside the
+// window): one 8-byte LDS read per row. Eq. 4 is the read-first atomicAnd
+// where the mask loses bits. The cube bins' shadows are offset lists in LDS;
+// their counters take the guard-bit atomics of eqs. 5-6, issued together with
+// the window loads so that one memory round trip serves both. The tables do
+// not depend on the grid: a point's row and shadow offsets are formed from
+// its grid's dimensions, and its grid index rides in its survivor record, so
+// a batch of scans into many grids runs the same loop as a single scan.
+// kPointsPerWave consecutive survivors (neighbours in scan order, whose
+// windows overlap) go to one wave and their loads are in flight together:
+// fewer waves keep the memory system as busy, over a smaller L2 working set
+// of windows. Needs Nx % 4 == 0 (16-byte aligned rows).
 constexpr int kRowPad = 128;            // >= K^2 for K <= 11
 constexpr int kQuadIters = kRowPad * 4 / 64;
 constexpr int kShadowTable = 2048;      // r_s^2 <= 9: at most 76 cells per cube bin, 26 bins
 constexpr int kShadowIters = 2;         // 76 <= 2 x 64
 constexpr int kMaxPointK = 11;
+constexpr int kPointsPerWave = 2;
 
-// ONE: the call holds a single scan, so every point is in grid 0 and the
-// tables are built once
+// ONE: the call holds a single scan (every point in grid 0)
 template <bool ONE>
 __global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const CallInfo *info) {
-    __shared__ uint32_t roffs[kRowPad];         // byte offset of window row (dy, dz) from the window's first row
     __shared__ uint2 mtab[16][kRowPad];         // eq. 3 masks of a lane's 4 cells (int16 each, -1 = outside)
-    __shared__ uint32_t sh_off[kShadowTable];   // byte offsets of the shadow cells from the window's first cell
+    __shared__ uint32_t sh_pk[kShadowTable];    // shadow cells of every bin: (dx+R) | (dy+R) << 8 | (dz+R) << 16
     __shared__ uint32_t sh_rng[32];             // shadow list start of every bin, and the end
+    constexpr int NP = kPointsPerWave;
     const DevTables &t = a.tab;
     const int K = t.K, R = t.R, K2 = K * K;
     const bool l1 = t.metric == DBTSDF_DIST_L1;
@@ -1155,7 +1159,7 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const C
     const uint32_t n_xcd = (gridDim.x % kXcds) == 0 ? kXcds : 1u;
     const uint32_t xcd = blockIdx.x % n_xcd, slot = blockIdx.x / n_xcd;
     const uint32_t lo = (uint32_t)((uint64_t)n_all * xcd / n_xcd);
-    const uint32_t n_surv = (uint32_t)((uint64_t)n_all * (xcd + 1) / n_xcd);
+    const uint32_t hi = (uint32_t)((uint64_t)n_all * (xcd + 1) / n_xcd);
     const uint32_t wpb = blockDim.x >> 6;
     const uint32_t waves = (gridDim.x / n_xcd) * wpb;
     const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1178,104 +1182,110 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const C
         mtab[sel][row] = make_uint2(m16[0] | (m16[1] << 16), m16[2] | (m16[3] << 16));
     }
     for (uint32_t b = threadIdx.x; b <= t.n_bins; b += blockDim.x) sh_rng[b] = t.sh_start[b];
-    uint32_t cur_grid = 0xFFFFFFFFu;
-    auto build_tables = [&](const DevGrid &gg) {
-        for (int c = threadIdx.x; c < kRowPad; c += blockDim.x)
-            roffs[c] = c < K2 ? 4u * gg.nx * ((uint32_t)(c % K) + gg.ny * (uint32_t)(c / K)) : 0u;
-        for (uint32_t j = threadIdx.x; j < n_sh; j += blockDim.x) {
-            const uint32_t pk = t.sh_off[j];
-            sh_off[j] = 4u * ((pk & 255u) + gg.nx * (((pk >> 8) & 255u) + gg.ny * ((pk >> 16) & 255u)));
-        }
-    };
-    if constexpr (ONE) {
-        build_tables(a.grids[0]);
-        __syncthreads();
-    } else {
-        __syncthreads();  // mtab
-    }
+    for (uint32_t j = threadIdx.x; j < n_sh; j += blockDim.x) sh_pk[j] = t.sh_off[j];
+    __syncthreads();
+
     const uint32_t qd = l & 3u;      // the lane's quad within a row
     const uint32_t rsub = l >> 2;    // the lane's row within a pass of 16 rows
-    // every wave of the block walks its points in lock step with the others,
-    // so the tables can be rebuilt (rarely: when the grid changes) under a barrier
-    const uint32_t first = lo + slot * wpb;
-    // the next point's record is loaded one iteration ahead, as a vector load
-    // that completes together with the current point's window loads, so a
-    // point costs one memory round trip
+    // the lane's window rows: (dy, dz) of row rsub + 16 k, relative to the
+    // window's first row
+    uint32_t rdy[kQuadIters], rdz[kQuadIters];
+#pragma unroll
+    for (int k = 0; k < kQuadIters; ++k) {
+        const uint32_t row = rsub + 16u * k;
+        rdy[k] = row < (uint32_t)K2 ? row % (uint32_t)K : 0u;
+        rdz[k] = row < (uint32_t)K2 ? row / (uint32_t)K : 0u;
+    }
+    const uint32_t stride = waves * (uint32_t)NP;
+    const uint32_t first = lo + (slot * wpb + wid) * (uint32_t)NP;
+    // the next round's records are loaded one round ahead, as vector loads
+    // that complete together with this round's window loads, so a round
+    // costs one memory round trip
     auto fetch = [&](uint32_t e) {
         uint32_t v = e;
         asm volatile("" : "+v"(v));  // per-lane address: a vector load, counted with the window loads
         return a.surv_rec[v];
     };
-    uint4 r_next = first + wid < n_surv ? fetch(first + wid) : make_uint4(0u, 0u, 0u, 0u);
-    DevGrid g_one{};
-    if constexpr (ONE) g_one = uniform_grid(a.grids[0]);  // loaded once: stores to the planes might alias it
-    for (uint32_t e0 = first; e0 < n_surv; e0 += waves) {
-        const uint32_t e = e0 + wid;
-        const bool live = e < n_surv;
-        uint32_t gi = 0;
-        bool same = true;
-        if constexpr (ONE) {
-            if (!live) break;
-        } else {
-            if (live) gi = a.survivors[e];
-            // the grid of the block's first live wave decides whether to rebuild
-            const uint32_t gblk = a.survivors[e0];
-            if (gblk != cur_grid) {
-                __syncthreads();
-                cur_grid = gblk;
-                build_tables(a.grids[gblk]);
-                __syncthreads();
-            }
-            if (!live) continue;
-            same = gi == cur_grid;
+    uint4 rn[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) rn[p] = first + p < hi ? fetch(first + p) : make_uint4(0u, 0u, 0u, 0u);
+    // the grid of the last point seen (loaded again only when it changes)
+    uint32_t cur_gi = 0u;
+    DevGrid cur_g = uniform_grid(a.grids[0]);
+    for (uint32_t e = first; e < hi; e += stride) {
+        uint4 r[NP];
+        bool live[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            r[p] = make_uint4(__builtin_amdgcn_readfirstlane(rn[p].x), __builtin_amdgcn_readfirstlane(rn[p].y),
+                              __builtin_amdgcn_readfirstlane(rn[p].z), __builtin_amdgcn_readfirstlane(rn[p].w));
+            live[p] = e + p < hi;
         }
-        const DevGrid g = ONE ? g_one : uniform_grid(a.grids[gi]);
-        const uint4 r = make_uint4(__builtin_amdgcn_readfirstlane(r_next.x), __builtin_amdgcn_readfirstlane(r_next.y),
-                                   __builtin_amdgcn_readfirstlane(r_next.z), __builtin_amdgcn_readfirstlane(r_next.w));
-        if (e + waves < n_surv) r_next = fetch(e + waves);
-        if (same) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+            if (e + stride + p < hi) rn[p] = fetch(e + stride + p);
+        DevGrid g[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            if constexpr (!ONE) {
+                const uint32_t gi = r[p].w >> 16;
+                if (live[p] && gi != cur_gi) {
+                    cur_gi = gi;
+                    cur_g = uniform_grid(a.grids[gi]);
+                }
+            }
+            g[p] = cur_g;
+        }
+        // every point's window loads, then every point's shadow adds
+        const char __attribute__((address_space(1))) *mbase[NP];
+        const char __attribute__((address_space(1))) *pbase[NP];
+        uint32_t sel[NP], roff[NP][kQuadIters];
+        u32x4 old[NP][kQuadIters];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
             // x0: first quad of the window rows; the front end admitted only
             // points whose whole window lies in the grid, and Nx % 4 == 0 keeps
             // every quad that meets the window inside its grid row
-            const uint32_t x0 = (r.x - (uint32_t)R) & ~3u;
-            const size_t row0 = (size_t)g.nx * ((size_t)(r.y - R) + (size_t)g.ny * (size_t)(r.z - R));
-            const char __attribute__((address_space(1))) *mbase =
-                reinterpret_cast<const char __attribute__((address_space(1))) *>(glob(g.mask) + row0 + x0);
-            const uint32_t sel = 4u * qd + 3u - ((r.x - (uint32_t)R) & 3u);
-            const bool qon = x0 + 4u * qd <= r.x + (uint32_t)R;
-            uint32_t roff[kQuadIters];
-            u32x4 old[kQuadIters];
-#pragma unroll
-            for (int k = 0; k < kQuadIters; ++k) roff[k] = roffs[rsub + 16u * k];
+            const uint32_t x0 = (r[p].x - (uint32_t)R) & ~3u;
+            const size_t row0 = (size_t)g[p].nx * ((size_t)(r[p].y - R) + (size_t)g[p].ny * (size_t)(r[p].z - R));
+            mbase[p] = reinterpret_cast<const char __attribute__((address_space(1))) *>(glob(g[p].mask) + row0 + x0);
+            pbase[p] = reinterpret_cast<const char __attribute__((address_space(1))) *>(
+                glob(g[p].packed) + row0 + (size_t)(r[p].x - (uint32_t)R));
+            sel[p] = 4u * qd + 3u - ((r[p].x - (uint32_t)R) & 3u);
+            const bool qon = live[p] && x0 + 4u * qd <= r[p].x + (uint32_t)R;
+            const uint32_t sy = 4u * g[p].nx, sz = 4u * g[p].nx * g[p].ny;  // row strides in bytes
 #pragma unroll
             for (int k = 0; k < kQuadIters; ++k) {
+                roff[p][k] = rdy[k] * sy + rdz[k] * sz;   // 32 bits: the call checked 8 R (1 + Nx + Nx Ny) < 2^32
                 const bool on = qon && (int)(rsub + 16u * k) < K2;
-                const uint32_t boff = roff[k] + 16u * qd;  // 32-bit offset from a scalar base
-                old[k] = on ? *reinterpret_cast<gu32x4 *>(mbase + boff) : u32x4{0u, 0u, 0u, 0u};
+                old[p][k] = on ? *reinterpret_cast<gu32x4 *>(mbase[p] + roff[p][k] + 16u * qd)
+                               : u32x4{0u, 0u, 0u, 0u};
             }
-            // shadow counters (eq. 5): the adds go out with the window loads, so
-            // their returns arrive in the same round trip
-            const size_t corner = row0 + (size_t)(r.x - (uint32_t)R);
-            const char __attribute__((address_space(1))) *pbase =
-                reinterpret_cast<const char __attribute__((address_space(1))) *>(glob(g.packed) + corner);
-            const uint32_t bin = r.w & 0xFFFFu;
-            const uint32_t s0 = sh_rng[bin], s1 = sh_rng[bin + 1];
-            uint32_t ov[kShadowIters], soff[kShadowIters];
-            bool son[kShadowIters];
+        }
+        uint32_t ov[NP][kShadowIters], soff[NP][kShadowIters];
+        bool son[NP][kShadowIters];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const uint32_t bin = r[p].w & 0xFFFFu;
+            const uint32_t s0 = sh_rng[bin], s1 = live[p] ? sh_rng[bin + 1] : s0;
 #pragma unroll
             for (int k = 0; k < kShadowIters; ++k) {
                 const uint32_t j = s0 + l + 64u * k;
-                son[k] = j < s1;
-                soff[k] = son[k] ? sh_off[j] : 0u;
-                ov[k] = 0u;
-                if (son[k]) ov[k] = g_add((gu32 *)(pbase + soff[k]), 1u);
+                son[p][k] = j < s1;
+                const uint32_t pk = son[p][k] ? sh_pk[j] : 0u;
+                soff[p][k] = 4u * ((pk & 255u) + g[p].nx * (((pk >> 8) & 255u) + g[p].ny * ((pk >> 16) & 255u)));
+                ov[p][k] = 0u;
+                if (son[p][k]) ov[p][k] = g_add((gu32 *)(pbase[p] + soff[p][k]), 1u);
             }
-            // stored and stamped masks both have the form 2^n - 1, so the AND of
-            // eq. 4 loses bits exactly when old > m; every compare comes first,
-            // then the atomics go out in one burst (a register read by an
-            // atomic in flight is not overwritten before the point is done)
+        }
+        // eq. 4: stored and stamped masks are both 2^n - 1, so the AND loses
+        // bits exactly when old > m; every compare comes first, then the
+        // atomics of a point that needs them go out in one burst (a register
+        // read by an atomic in flight is not overwritten before the round ends)
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
             auto masks = [&](int k, uint32_t m[4]) {
-                const uint2 v = mtab[sel][rsub + 16u * k];
+                const uint2 v = mtab[sel[p]][rsub + 16u * k];
                 m[0] = (uint32_t)((int32_t)(v.x << 16) >> 16);
                 m[1] = (uint32_t)((int32_t)v.x >> 16);
                 m[2] = (uint32_t)((int32_t)(v.y << 16) >> 16);
@@ -1286,7 +1296,7 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const C
             for (int k = 0; k < kQuadIters; ++k) {
                 uint32_t m[4];
                 masks(k, m);
-                need |= (old[k][0] > m[0]) | (old[k][1] > m[1]) | (old[k][2] > m[2]) | (old[k][3] > m[3]);
+                need |= (old[p][k][0] > m[0]) | (old[p][k][1] > m[1]) | (old[p][k][2] > m[2]) | (old[p][k][3] > m[3]);
             }
             if (need) {  // rare once the map has formed: the compares are redone here
 #pragma unroll
@@ -1295,45 +1305,24 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const C
                     masks(k, m);
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
-                        if (old[k][j] > m[j]) g_and((gu32 *)(mbase + (roff[k] + 16u * qd + 4u * j)), m[j]);
+                        if (old[p][k][j] > m[j]) g_and((gu32 *)(mbase[p] + (roff[p][k] + 16u * qd + 4u * j)), m[j]);
                 }
             }
-            // eqs. 5-6 for the shadow counters, with the returns that the add
-            // issued next to the window loads brought back: every add that saw
-            // a raw count >= H_max is cancelled, the add that saw T - 1 clears
-            // the sign (bits 16-30 absorb the transient overshoot)
+        }
+        // eqs. 5-6 with the returns of the adds: every add that saw a raw
+        // count >= H_max is cancelled, the add that saw T - 1 clears the sign
+        // (bits 16-30 absorb the transient overshoot)
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
 #pragma unroll
             for (int k = 0; k < kShadowIters; ++k) {
                 // an opaque use: the returned value is not touched (and waited
                 // for) before the window compares above have been issued
-                asm volatile("" : "+v"(ov[k]));
-                if (!son[k]) continue;
-                const uint32_t raw = ov[k] & 0x7FFFFFFFu;
-                if (raw >= g.hmax) g_sub((gu32 *)(pbase + soff[k]), 1u);
-                else if (g.T >= 1u && raw == g.T - 1u) g_and((gu32 *)(pbase + soff[k]), 0x7FFFFFFFu);
-            }
-        } else {  // a wave whose point is in another grid than the tables'
-            const size_t lin = (size_t)r.x + (size_t)g.nx * ((size_t)r.y + (size_t)g.ny * (size_t)r.z);
-            gu32 *mb = glob(g.mask) + lin;
-            gu32 *pb = glob(g.packed) + lin;
-            for (int c = (int)l; c < K2 * K; c += 64) {
-                const int ox = c % K - R, oy = (c / K) % K - R, oz = c / K2 - R;
-                const long long o = (long long)ox + (long long)g.nx * ((long long)oy + (long long)g.ny * oz);
-                const uint32_t q = l1 ? (uint32_t)(abs(ox) + abs(oy) + abs(oz)) : (uint32_t)(ox * ox + oy * oy + oz * oz);
-                const uint32_t m = t.mask_by_q[q];
-                const uint32_t old = mb[o];
-                if ((old & m) != old) g_and(mb + o, m);
-            }
-            const uint32_t bin = r.w & 0xFFFFu;
-            for (uint32_t j = t.sh_start[bin] + l; j < t.sh_start[bin + 1]; j += 64u) {
-                const uint32_t pk = t.sh_off[j];
-                const long long o = ((long long)(pk & 255u) - R) +
-                                    (long long)g.nx * (((long long)((pk >> 8) & 255u) - R) +
-                                                       (long long)g.ny * ((long long)((pk >> 16) & 255u) - R));
-                const uint32_t ov = g_add(pb + o, 1u);
-                const uint32_t raw = ov & 0x7FFFFFFFu;
-                if (raw >= g.hmax) g_sub(pb + o, 1u);
-                else if (g.T >= 1u && raw == g.T - 1u) g_and(pb + o, 0x7FFFFFFFu);
+                asm volatile("" : "+v"(ov[p][k]));
+                if (!son[p][k]) continue;
+                const uint32_t raw = ov[p][k] & 0x7FFFFFFFu;
+                if (raw >= g[p].hmax) g_sub((gu32 *)(pbase[p] + soff[p][k]), 1u);
+                else if (g[p].T >= 1u && raw == g[p].T - 1u) g_and((gu32 *)(pbase[p] + soff[p][k]), 0x7FFFFFFFu);
             }
         }
     }

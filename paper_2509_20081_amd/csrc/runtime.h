@@ -74,7 +74,7 @@ struct Workspace {
     unsigned long long *hkeys = nullptr;
     uint32_t *hvals = nullptr;
     unsigned long long *items = nullptr;
-    uint32_t *item_off = nullptr, *item_cnt = nullptr, *survivors = nullptr;
+    uint32_t *item_off = nullptr, *item_cnt = nullptr;
     uint4 *entries = nullptr;
     uint32_t *rank = nullptr;
     uint4 *work = nullptr;
