@@ -64,6 +64,12 @@ static dbtsdf_status make_device_tables(const KernelSet &ks, std::shared_ptr<Dev
     if (e == hipSuccess) e = upload(*d, ks.az_s, &t.az_s);
     if (e == hipSuccess) e = upload(*d, ks.el_s2, &t.el_s2);
     if (e == hipSuccess) e = upload(*d, ks.el_neg, &t.el_neg);
+    t.row_image = nullptr;
+    if (e == hipSuccess && !ks.row_image.empty()) {
+        const uint32_t *img = nullptr;
+        e = upload(*d, ks.row_image, &img);
+        t.row_image = reinterpret_cast<const uint4 *>(img);
+    }
     if (e != hipSuccess) return check_hip(e, "uploading kernel tables");
     t.n_q = (uint32_t)ks.mask_by_q.size();
     t.n_bins = ks.n_bins;
@@ -413,7 +419,7 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
     if (traffic) tun.strategy = DBTSDF_STRATEGY_BRICK;  // unique-word counts come from the brick merge
     // the per-point strategy carries a survivor's grid in 16 bits
     if (grids.size() > kMaxAtomicGrids) tun.strategy = DBTSDF_STRATEGY_BRICK;
-    if (tun.apply_blocks == 0) tun.apply_blocks = (uint32_t)apply_blocks_default(tun, g0->K, g0->device);
+    if (tun.apply_blocks == 0) tun.apply_blocks = (uint32_t)apply_blocks_default(tun, g0->K, g0->tables->t.row_image != nullptr, g0->device);
     for (dbtsdf_grid *g : grids) {
         dbtsdf_status s = ensure_bricks(g);
         if (s != DBTSDF_OK) return s;

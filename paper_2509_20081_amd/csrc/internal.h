@@ -40,9 +40,33 @@ struct KernelSet {
     // AZEL boundary tables (fp32, index k = 1..B_az/2-1 and 1..B_el-1, slot 0 unused)
     std::vector<float> az_c, az_s, el_s2;
     std::vector<uint32_t> el_neg;
+    std::vector<uint32_t> row_image;     // kImgWords, or empty when the row kernel does not cover the set
 };
 
 KernelSet *build_kernel_set(const dbtsdf_kernel_params &p, std::string *err);
+
+// The LDS tables of the per-point row kernel, laid out as the kernel holds
+// them and copied in whole by every workgroup (16-byte words):
+//   mtab[sel][row]   sel = 4 qd - a + 3 (lane quad qd, window phase a), row =
+//                    (dy + R) + K (dz + R): the eq. 3 masks of cells dx = sel -
+//                    3 - R + j, j = 0..3, as int16 pairs (-1 outside the window)
+//   sh_pk[j]         the shadow cells of every bin, (dx+R) | (dy+R) << 8 | (dz+R) << 16
+//   sh_bits[b][w]    bin b's shadow set as bits (dx+3) + 7 (dy+3) + 49 (dz+3)
+//   sh_rng[b]        start of bin b's cells in sh_pk, and the end after the last bin
+// Built only for kernel sets the row kernel covers: K <= 11, at most 31 bins,
+// r_s^2 <= 9 (cells in [-3, 3]^3, at most 128 per bin, 2048 in all) and masks
+// below 2^15.
+constexpr uint32_t kRowPad = 128;          // >= K^2 for K <= 11
+constexpr uint32_t kRowSel = 16;
+constexpr uint32_t kShadowTable = 2048;
+constexpr uint32_t kShadowSetWords = 11;   // 7^3 = 343 bits
+constexpr uint32_t kRowBins = 32;          // sh_rng entries: at most 31 bins and the end
+constexpr uint32_t kImgMtab = 0, kImgShPk = kRowSel * kRowPad * 2, kImgShBits = kImgShPk + kShadowTable,
+                   kImgShRng = kImgShBits + kRowBins * kShadowSetWords,
+                   kImgWords = (kImgShRng + kRowBins + 1023) / 1024 * 1024;  // whole rounds of 256 16-byte copies
+static_assert(kImgWords % 4 == 0 && kImgShPk % 4 == 0 && kImgShBits % 4 == 0 && kImgShRng % 4 == 0,
+              "16-byte sections");
+bool build_row_image(const KernelSet &ks, std::vector<uint32_t> &img);
 int host_bin(const KernelSet &ks, float dx, float dy, float dz);
 
 // ---------------------------------------------------- device descriptors ---
@@ -53,6 +77,7 @@ struct DevTables {
     const uint32_t *sh_off;      // total shadow cells
     const float *az_c, *az_s, *el_s2;
     const uint32_t *el_neg;
+    const uint4 *row_image;  // the row kernel's LDS tables, or null
     uint32_t n_q;
     uint32_t n_bins;
     int32_t K, R;
@@ -172,6 +197,8 @@ hipError_t launch_gather_box(const uint32_t *plane, const uint32_t *packed, cons
 // Number of positions where a != b (n words), added into *count.
 hipError_t launch_count_diff(const uint32_t *a, const uint32_t *b, uint64_t n, unsigned long long *count,
                              hipStream_t st);
-int apply_blocks_default(const Tuning &t, int K, int device);
+// Workgroups of a fully resident persistent apply grid (row_kernel: the
+// kernel set has the row kernel's tables).
+int apply_blocks_default(const Tuning &t, int K, bool row_kernel, int device);
 
 }  // namespace dbtsdf

@@ -182,8 +182,47 @@ KernelSet *build_kernel_set(const dbtsdf_kernel_params &p, std::string *err) {
                 }
     }
     ks->sh_start[ks->n_bins] = (uint32_t)ks->sh_off.size();
+    if (!build_row_image(*ks, ks->row_image)) ks->row_image.clear();
     if (ks->sh_off.empty()) ks->sh_off.push_back(0);  // non-empty device allocation
     return ks;
+}
+
+bool build_row_image(const KernelSet &ks, std::vector<uint32_t> &img) {
+    const int K = ks.K, R = ks.R;
+    if (K * K > (int)kRowPad || ks.n_bins + 1 > kRowBins || ks.p.shadow_r2 > 9 || ks.sh_off.size() > kShadowTable)
+        return false;
+    for (uint32_t b = 0; b < ks.n_bins; ++b)
+        if (ks.sh_start[b + 1] - ks.sh_start[b] > 128) return false;
+    for (uint32_t m : ks.mask_by_q)
+        if (m >= 0x8000u) return false;
+    img.assign(kImgWords, 0u);
+    const bool l1 = ks.p.metric == DBTSDF_DIST_L1;
+    for (uint32_t sel = 0; sel < kRowSel; ++sel)
+        for (uint32_t row = 0; row < kRowPad; ++row) {
+            const int dy = (int)(row % K) - R, dz = (int)(row / K) - R;
+            uint32_t m16[4];
+            for (int j = 0; j < 4; ++j) {
+                const int dx = (int)sel - 3 - R + j;
+                m16[j] = 0xFFFFu;
+                if (row < (uint32_t)(K * K) && dx >= -R && dx <= R) {
+                    const uint32_t q = l1 ? (uint32_t)(abs(dx) + abs(dy) + abs(dz)) : (uint32_t)(dx * dx + dy * dy + dz * dz);
+                    m16[j] = ks.mask_by_q[q] & 0xFFFFu;
+                }
+            }
+            img[kImgMtab + 2 * (sel * kRowPad + row) + 0] = m16[0] | (m16[1] << 16);
+            img[kImgMtab + 2 * (sel * kRowPad + row) + 1] = m16[2] | (m16[3] << 16);
+        }
+    const uint32_t n_sh = ks.sh_start[ks.n_bins];
+    for (uint32_t j = 0; j < n_sh; ++j) img[kImgShPk + j] = ks.sh_off[j];
+    for (uint32_t b = 0; b < ks.n_bins; ++b)
+        for (uint32_t j = ks.sh_start[b]; j < ks.sh_start[b + 1]; ++j) {
+            const uint32_t pk = ks.sh_off[j];
+            const int dx = (int)(pk & 255u) - R, dy = (int)((pk >> 8) & 255u) - R, dz = (int)((pk >> 16) & 255u) - R;
+            const uint32_t idx = (uint32_t)((dx + 3) + 7 * (dy + 3) + 49 * (dz + 3));
+            img[kImgShBits + b * kShadowSetWords + idx / 32] |= 1u << (idx % 32);
+        }
+    for (uint32_t b = 0; b <= ks.n_bins; ++b) img[kImgShRng + b] = ks.sh_start[b];
+    return true;
 }
 
 }  // namespace dbtsdf

@@ -1130,25 +1130,29 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_atomic(PipeArgs a, const C
 // windows overlap) go to one wave and their loads are in flight together:
 // fewer waves keep the memory system as busy, over a smaller L2 working set
 // of windows. Needs Nx % 4 == 0 (16-byte aligned rows).
-constexpr int kRowPad = 128;            // >= K^2 for K <= 11
-constexpr int kQuadIters = kRowPad * 4 / 64;
-constexpr int kShadowTable = 2048;      // r_s^2 <= 9: at most 76 cells per cube bin, 26 bins
-constexpr int kShadowIters = 2;         // 76 <= 2 x 64
-constexpr int kMaxPointK = 11;
+constexpr int kQuadIters = (int)kRowPad * 4 / 64;
+constexpr int kShadowIters = 2;         // at most 128 shadow cells per bin
 constexpr int kPointsPerWave = 2;
+constexpr uint32_t kImgQuads = kImgWords / 4;
+constexpr uint32_t kImgCopies = (kImgQuads + kPtThreads - 1) / kPtThreads;
 
 // ONE: the call holds a single scan (every point in grid 0)
 template <bool ONE>
 __global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const CallInfo *info) {
-    __shared__ uint2 mtab[16][kRowPad];         // eq. 3 masks of a lane's 4 cells (int16 each, -1 = outside)
-    __shared__ uint32_t sh_pk[kShadowTable];    // shadow cells of every bin: (dx+R) | (dy+R) << 8 | (dz+R) << 16
-    __shared__ uint32_t sh_rng[32];             // shadow list start of every bin, and the end
+    // the kernel set's tables (layout in internal.h), copied in whole: every
+    // thread's 16-byte loads are in flight together
+    __shared__ uint4 s_img[kImgQuads];
+    const uint2(*mtab)[kRowPad] = reinterpret_cast<const uint2(*)[kRowPad]>(reinterpret_cast<uint32_t *>(s_img) + kImgMtab);
+    const uint32_t *sh_pk = reinterpret_cast<const uint32_t *>(s_img) + kImgShPk;
+    const uint32_t *sh_bits = reinterpret_cast<const uint32_t *>(s_img) + kImgShBits;
+    const uint32_t *sh_rng = reinterpret_cast<const uint32_t *>(s_img) + kImgShRng;
     constexpr int NP = kPointsPerWave;
     const DevTables &t = a.tab;
     const int K = t.K, R = t.R, K2 = K * K;
-    const bool l1 = t.metric == DBTSDF_DIST_L1;
     const uint32_t l = lane();
-    const uint32_t n_sh = t.sh_start[t.n_bins];
+    static_assert(kImgQuads % kPtThreads == 0, "whole copy rounds");
+#pragma unroll
+    for (uint32_t c = 0; c < kImgCopies; ++c) s_img[threadIdx.x + c * kPtThreads] = t.row_image[threadIdx.x + c * kPtThreads];
 
     // XCD-aware split: workgroups are dealt to the eight XCDs round-robin, so
     // workgroup b runs on XCD b % 8. Each XCD takes one contiguous eighth of
@@ -1163,26 +1167,6 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const C
     const uint32_t wpb = blockDim.x >> 6;
     const uint32_t waves = (gridDim.x / n_xcd) * wpb;
     const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // mtab[4 qd - a + 3][row]: the masks of cells dx = 4 qd - a - R + j (j = 0..3)
-    // of window row `row`, for a lane at quad qd of a window whose first
-    // column sits a cells into its quad. Masks of K <= 11 fit 15 bits.
-    for (int e = threadIdx.x; e < 16 * kRowPad; e += blockDim.x) {
-        const int sel = e / kRowPad, row = e % kRowPad;
-        const int dy = row % K - R, dz = row / K - R;
-        uint32_t m16[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int dx = sel - 3 - R + j;
-            m16[j] = 0xFFFFu;
-            if (row < K2 && dx >= -R && dx <= R) {
-                const uint32_t q = l1 ? (uint32_t)(abs(dx) + abs(dy) + abs(dz)) : (uint32_t)(dx * dx + dy * dy + dz * dz);
-                m16[j] = t.mask_by_q[q] & 0xFFFFu;
-            }
-        }
-        mtab[sel][row] = make_uint2(m16[0] | (m16[1] << 16), m16[2] | (m16[3] << 16));
-    }
-    for (uint32_t b = threadIdx.x; b <= t.n_bins; b += blockDim.x) sh_rng[b] = t.sh_start[b];
-    for (uint32_t j = threadIdx.x; j < n_sh; j += blockDim.x) sh_pk[j] = t.sh_off[j];
     __syncthreads();
 
     const uint32_t qd = l & 3u;      // the lane's quad within a row
@@ -1262,7 +1246,10 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const C
                                : u32x4{0u, 0u, 0u, 0u};
             }
         }
-        uint32_t ov[NP][kShadowIters], soff[NP][kShadowIters];
+        // shadow counters (eq. 5). A cell in the shadows of several points of
+        // the round (same grid) takes one add of their number, issued by the
+        // first of them; the others skip it
+        uint32_t ov[NP][kShadowIters], soff[NP][kShadowIters], cnt[NP][kShadowIters];
         bool son[NP][kShadowIters];
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
@@ -1273,9 +1260,26 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const C
                 const uint32_t j = s0 + l + 64u * k;
                 son[p][k] = j < s1;
                 const uint32_t pk = son[p][k] ? sh_pk[j] : 0u;
+                uint32_t c = 1u;
+#pragma unroll
+                for (int q = 0; q < NP; ++q) {
+                    if (q == p || !live[q] || (!ONE && (r[q].w >> 16) != (r[p].w >> 16))) continue;
+                    // the cell relative to point q, in [-3, 3]^3 when it can be in q's shadow
+                    const int rx = (int)(pk & 255u) - R + (int)r[p].x - (int)r[q].x;
+                    const int ry = (int)((pk >> 8) & 255u) - R + (int)r[p].y - (int)r[q].y;
+                    const int rz = (int)((pk >> 16) & 255u) - R + (int)r[p].z - (int)r[q].z;
+                    bool in = rx >= -3 && rx <= 3 && ry >= -3 && ry <= 3 && rz >= -3 && rz <= 3;
+                    if (in) {
+                        const uint32_t idx = (uint32_t)((rx + 3) + 7 * (ry + 3) + 49 * (rz + 3));
+                        in = ((sh_bits[(r[q].w & 0xFFFFu) * kShadowSetWords + idx / 32u] >> (idx % 32u)) & 1u) != 0u;
+                    }
+                    if (q < p) son[p][k] = son[p][k] && !in;
+                    else c += in ? 1u : 0u;
+                }
+                cnt[p][k] = c;
                 soff[p][k] = 4u * ((pk & 255u) + g[p].nx * (((pk >> 8) & 255u) + g[p].ny * ((pk >> 16) & 255u)));
                 ov[p][k] = 0u;
-                if (son[p][k]) ov[p][k] = g_add((gu32 *)(pbase[p] + soff[p][k]), 1u);
+                if (son[p][k]) ov[p][k] = g_add((gu32 *)(pbase[p] + soff[p][k]), c);
             }
         }
         // eq. 4: stored and stamped masks are both 2^n - 1, so the AND loses
@@ -1309,9 +1313,11 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const C
                 }
             }
         }
-        // eqs. 5-6 with the returns of the adds: every add that saw a raw
-        // count >= H_max is cancelled, the add that saw T - 1 clears the sign
-        // (bits 16-30 absorb the transient overshoot)
+        // eqs. 5-6 with the returns of the adds of c: an add that saw a raw
+        // count >= H_max is cancelled, one that crossed H_max gives back its
+        // excess, the add whose range [raw, min(raw + c, H_max)] steps over
+        // T - 1 -> T clears the sign (bits 16-30 absorb the transient
+        // overshoot; c = 1 is the unit scheme)
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
 #pragma unroll
@@ -1320,9 +1326,14 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const C
                 // for) before the window compares above have been issued
                 asm volatile("" : "+v"(ov[p][k]));
                 if (!son[p][k]) continue;
-                const uint32_t raw = ov[p][k] & 0x7FFFFFFFu;
-                if (raw >= g[p].hmax) g_sub((gu32 *)(pbase[p] + soff[p][k]), 1u);
-                else if (g[p].T >= 1u && raw == g[p].T - 1u) g_and((gu32 *)(pbase[p] + soff[p][k]), 0x7FFFFFFFu);
+                gu32 *w = (gu32 *)(pbase[p] + soff[p][k]);
+                const uint32_t raw = ov[p][k] & 0x7FFFFFFFu, c = cnt[p][k], H = g[p].hmax, T = g[p].T;
+                if (raw >= H) {
+                    g_sub(w, c);
+                } else {
+                    if (raw + c > H) g_sub(w, raw + c - H);
+                    if (T >= 1u && raw < T && T <= min(raw + c, H)) g_and(w, 0x7FFFFFFFu);
+                }
             }
         }
     }
@@ -1453,26 +1464,27 @@ bool tuning_supported(const Tuning &t, int K) {
     return find_apply(t, (K - 1) / 2) != nullptr;
 }
 
-static int apply_blocks_query(const Tuning &t, int K, int device);
+static int apply_blocks_query(const Tuning &t, int K, bool row_kernel, int device);
 
 // The occupancy query costs far more than a launch, so its answer is kept per
-// (device, strategy, shape, threads, K).
-int apply_blocks_default(const Tuning &t, int K, int device) {
+// (device, strategy, shape, threads, K, kernel).
+int apply_blocks_default(const Tuning &t, int K, bool row_kernel, int device) {
     static std::mutex mu;
-    static std::map<std::array<uint32_t, 7>, int> cache;
-    const std::array<uint32_t, 7> key = {(uint32_t)device, t.strategy, t.bx, t.by, t.bz, t.threads, (uint32_t)K};
+    static std::map<std::array<uint32_t, 8>, int> cache;
+    const std::array<uint32_t, 8> key = {(uint32_t)device, t.strategy, t.bx, t.by, t.bz, t.threads, (uint32_t)K,
+                                         row_kernel ? 1u : 0u};
     {
         std::lock_guard<std::mutex> lk(mu);
         auto it = cache.find(key);
         if (it != cache.end()) return it->second;
     }
-    const int v = apply_blocks_query(t, K, device);
+    const int v = apply_blocks_query(t, K, row_kernel, device);
     std::lock_guard<std::mutex> lk(mu);
     cache[key] = v;
     return v;
 }
 
-static int apply_blocks_query(const Tuning &t, int K, int device) {
+static int apply_blocks_query(const Tuning &t, int K, bool row_kernel, int device) {
     int cus = 256;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) cus = 256;
     // a persistent grid is sized to be fully resident: blocks per CU from the
@@ -1480,7 +1492,7 @@ static int apply_blocks_query(const Tuning &t, int K, int device) {
     // start only when the first has finished its share)
     int per_cu = 0;
     if (t.strategy == DBTSDF_STRATEGY_ATOMIC) {
-        const void *pk = K <= kMaxPointK ? reinterpret_cast<const void *>(k_apply_points<true>)
+        const void *pk = row_kernel ? reinterpret_cast<const void *>(k_apply_points<true>)
                                          : reinterpret_cast<const void *>(k_apply_atomic);
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pk, kPtThreads, 0) != hipSuccess || per_cu < 1)
             per_cu = 1;
@@ -1514,12 +1526,11 @@ hipError_t launch_pipeline(const PipeArgs &a, const Tuning &t, uint32_t points_c
             }
             k_select_atomic<<<sb, kSelThreads, 0, st>>>(a, info);
         }
-        // the row kernel covers K <= 11, cube shadows with r_s^2 <= 9 and grids
-        // with Nx % 4 == 0 whose window offsets fit 32 bits; everything else
-        // takes the generic per-row kernel
+        // the row kernel covers the kernel sets it has tables for (K <= 11,
+        // r_s^2 <= 9, at most 31 bins) and grids with Nx % 4 == 0 whose window
+        // offsets fit 32 bits; everything else takes the generic per-row kernel
         if (apply) {
-            if (a.small_offsets && a.quad_rows && a.tab.K <= kMaxPointK && a.tab.n_q <= (uint32_t)kRowPad &&
-                a.tab.n_bins == 26 && a.tab.shadow_r2 <= 9) {
+            if (a.small_offsets && a.quad_rows && a.tab.row_image != nullptr) {
                 if (a.single_scan)
                     k_apply_points<true><<<t.apply_blocks, kPtThreads, 0, st>>>(a, info);
                 else

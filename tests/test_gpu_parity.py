@@ -230,6 +230,38 @@ def test_plain_graph_replays_over_the_ring(db, strategy):
         P.assert_grids_equal(gm, gp, m, p, what=f"call {k}")
 
 
+@pytest.mark.parametrize("hit", [(2, 3), (1, 1), (5, 65535)])
+@pytest.mark.parametrize("dedup", [True, False])
+def test_dense_neighbouring_returns_saturate_exactly(db, hit, dedup):
+    """Returns one voxel apart in input order (neighbours share most of their shadows, so the per-point
+    kernel adds shared shadow cells once with their count) on a small hit cap: counters, signs and masks
+    match the oracle scan after scan, through saturation."""
+    T, H = hit
+    dims = (32, 32, 32)
+    o, g, _ = P.make_pair(dims, 1.0, (0.0, 0.0, 0.0), kernel_size=7, binning="cube26", shadow_r2=9,
+                          hit_threshold=T, hit_max=H, dedup=dedup)
+    g.set_tuning(strategy="atomic")
+    m, p = o.new_grid()
+    rng = np.random.default_rng(23)
+    sensor = np.array([16.5, 16.5, 16.5])
+    for i in range(6):
+        pose = np.eye(4, dtype=np.float32)
+        pose[:3, 3] = sensor + rng.uniform(-0.4, 0.4, 3)
+        # a patch of a wall and a patch of a floor, walked row by row, plus repeats
+        u, v = np.meshgrid(np.arange(-6, 7), np.arange(-6, 7), indexing="ij")
+        wall = np.stack([np.full(u.size, 9.3), u.ravel() + 0.2, v.ravel() - 0.1], 1)
+        floor = np.stack([u.ravel() - 0.3, v.ravel() + 0.4, np.full(u.size, -8.6)], 1)
+        pts = np.concatenate([wall, floor, wall[::7]]) + rng.normal(0, 0.05, (2 * u.size + len(wall[::7]), 3))
+        pts = pts.astype(np.float32)
+        ref = o.integrate(m, p, pose, pts)
+        st = g.integrate(pose, P.to_device(pts))
+        g.sync()
+        P.assert_stats_equal(st.as_dict(), ref, traffic=False, what=f"scan {i}")
+        gm, gp = P.gpu_planes(g)
+        P.assert_grids_equal(gm, gp, m, p, what=f"scan {i}")
+    assert ref["n_integrated"] > 200
+
+
 @pytest.mark.parametrize("strategy", ["atomic", "brick"])
 def test_profiling_period_mixes_call_forms(db, strategy):
     """Profiling every 3rd call: timed calls (split launch) and untimed calls (one graph) interleave
