@@ -419,7 +419,15 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
     if (traffic) tun.strategy = DBTSDF_STRATEGY_BRICK;  // unique-word counts come from the brick merge
     // the per-point strategy carries a survivor's grid in 16 bits
     if (grids.size() > kMaxAtomicGrids) tun.strategy = DBTSDF_STRATEGY_BRICK;
-    if (tun.apply_blocks == 0) tun.apply_blocks = (uint32_t)apply_blocks_default(tun, g0->K, g0->tables->t.row_image != nullptr, g0->device);
+    // the per-point strategy's row kernel: tables for the kernel set, 16-byte
+    // aligned grid rows and window byte offsets within 32 bits in every grid
+    bool row_kernel = g0->tables->t.row_image != nullptr;
+    for (dbtsdf_grid *g : grids) {
+        const uint64_t span = (uint64_t)g->tables->t.R *
+                              (1ull + g->params.dims[0] + (uint64_t)g->params.dims[0] * g->params.dims[1]);
+        if (g->params.dims[0] % 4u || 8 * span >= (1ull << 32)) row_kernel = false;
+    }
+    if (tun.apply_blocks == 0) tun.apply_blocks = (uint32_t)apply_blocks_default(tun, g0->K, row_kernel, g0->device);
     for (dbtsdf_grid *g : grids) {
         dbtsdf_status s = ensure_bricks(g);
         if (s != DBTSDF_OK) return s;
@@ -532,13 +540,7 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
     // the plain one-scan call has a kernel of its own (no per-point scan lookup)
     // (its front pass reads the scan descriptor from the host in 16-byte pieces)
     a.single_scan = plain && live.size() == 1 && scans_off % 16 == 0 ? 1u : 0u;
-    a.small_offsets = 1u;
-    a.quad_rows = 1u;
-    for (dbtsdf_grid *g : grids) {
-        if (g->params.dims[0] % 4u) a.quad_rows = 0u;
-        const uint64_t span = (uint64_t)R * (1ull + g->params.dims[0] + (uint64_t)g->params.dims[0] * g->params.dims[1]);
-        if (8 * span >= (1ull << 32)) a.small_offsets = 0u;  // window byte offsets fit 32 bits
-    }
+    a.row_kernel = row_kernel ? 1u : 0u;
 
     // plain calls, and batches that ask for it, replay captured graphs (one
     // host call instead of one per pass); with profiling on, events bracket

@@ -154,9 +154,10 @@ struct PipeArgs {
     uint32_t count_traffic;
     uint32_t span[3];        // most bricks a K^3 cube can touch per axis
     uint32_t chunk;          // listed points per apply work unit (0 = never split a brick)
-    uint32_t small_offsets;  // every grid: 8 R (1 + Nx + Nx Ny) < 2^32 (window byte offsets fit 32 bits)
+    uint32_t row_kernel;     // the per-point strategy's apply is the row kernel: the kernel set has its
+                             // tables and every grid has Nx % 4 == 0 (16-byte aligned rows) and window
+                             // byte offsets that fit 32 bits (8 R (1 + Nx + Nx Ny) < 2^32)
     uint32_t single_scan;    // the call holds exactly one scan (one grid)
-    uint32_t quad_rows;      // every grid: Nx % 4 == 0 (16-byte aligned grid rows)
     // the call's descriptors are read from, and its counters written to, the
     // pinned host buffer of its ring slot by the first and last passes
     const uint2 *host_desc;  // CallInfo | DevGrid[grids_cap] | DevScan[n_scans]

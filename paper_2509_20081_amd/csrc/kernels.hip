@@ -1530,7 +1530,7 @@ hipError_t launch_pipeline(const PipeArgs &a, const Tuning &t, uint32_t points_c
         // r_s^2 <= 9, at most 31 bins) and grids with Nx % 4 == 0 whose window
         // offsets fit 32 bits; everything else takes the generic per-row kernel
         if (apply) {
-            if (a.small_offsets && a.quad_rows && a.tab.row_image != nullptr) {
+            if (a.row_kernel) {
                 if (a.single_scan)
                     k_apply_points<true><<<t.apply_blocks, kPtThreads, 0, st>>>(a, info);
                 else
