@@ -272,6 +272,31 @@ dbtsdf_status dbtsdf_read_voxels(dbtsdf_grid *g, const uint32_t lo[3], const uin
 dbtsdf_status dbtsdf_read_distance(dbtsdf_grid *g, const uint32_t lo[3], const uint32_t hi[3], int8_t *dist_out);
 
 /*
+ * Mesh export (the pipeline's last block, Sec. III: Marching Cubes of the
+ * fused map at iso = 0.0) of the signed distance that read_distance gives.
+ * Takes every cube of the dual grid whose eight corner voxels lie in the box
+ * [lo, hi) (lo, hi NULL: the whole grid). A corner is inside when its distance
+ * is negative; a crossed edge from voxel u to u + e_a has its vertex at
+ * t = d(u) / (d(u) - d(u + e_a)), coordinate o + (u + 0.5) s on the other
+ * axes and o_a + (u_a + 0.5) s + t s along a (fp32, one operation at a time,
+ * in that order). Saddle faces keep inside corners apart; face segments run
+ * counter-clockwise seen from outside the cube and chain into loops fanned
+ * from their smallest edge number (edges 4 a + rank of the lower corner among
+ * those with bit a clear; corners x + 2y + 4z), or from their centre (the
+ * mean of the loop's vertices) when a loop holds all four crossed edges of a
+ * saddle face. Normals (right-hand rule) point to positive distance.
+ * tris_dev: device memory for max_tris triangles of 9 floats (v0 xyz, v1 xyz,
+ * v2 xyz), or NULL with max_tris 0 to count only. *n_tris receives the number
+ * of triangles of the mesh; when it exceeds max_tris only max_tris of them are
+ * written (which ones is unspecified). The order of the triangles is
+ * unspecified. Runs on the grid's stream and synchronises it.
+ * Errors: INVALID_ARG (NULL n_tris, NULL tris_dev with max_tris > 0),
+ * OUT_OF_RANGE (box), OUT_OF_MEMORY, DEVICE, POISONED.
+ */
+dbtsdf_status dbtsdf_extract_mesh(dbtsdf_grid *g, const uint32_t lo[3], const uint32_t hi[3], float *tris_dev,
+                                  uint64_t max_tris, uint64_t *n_tris);
+
+/*
  * Overwrite the whole grid from host planes (Nx*Ny*Nz uint32 each, x fastest),
  * e.g. a checkpoint written from dbtsdf_read_voxels. Rejects (INVALID_ARG)
  * planes that break the representation: a mask not of the form 2^n - 1, bits

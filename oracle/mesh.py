@@ -232,12 +232,17 @@ def canonical(tris: np.ndarray) -> np.ndarray:
     t = np.asarray(tris, np.float32).reshape(-1, 3, 3)
     if len(t) == 0:
         return t.reshape(0, 9)
-    keys = t.view(np.uint32).reshape(-1, 3, 3)
-    rows = []
-    for tri, key in zip(t, keys):
-        ks = [tuple(key[i]) for i in range(3)]
-        r = ks.index(min(ks))
-        rows.append(np.roll(tri, -r, axis=0).reshape(9))
-    rows = np.asarray(rows, np.float32)
+    keys = t.view(np.uint32).reshape(-1, 3, 3).astype(np.uint64)
+    # least vertex by (x, y, z) bit patterns, compared lexicographically
+    code = (keys[:, :, 0] << np.uint64(32)) | keys[:, :, 1]
+    best = np.zeros(len(t), np.int64)
+    for i in (1, 2):
+        b = best
+        cb, ci = code[np.arange(len(t)), b], code[:, i]
+        zb, zi = keys[np.arange(len(t)), b, 2], keys[:, i, 2]
+        better = (ci < cb) | ((ci == cb) & (zi < zb))
+        best = np.where(better, i, b)
+    idx = (np.arange(3)[None, :] + best[:, None]) % 3
+    rows = np.take_along_axis(t, idx[:, :, None], axis=1).reshape(-1, 9)
     order = np.lexsort(rows.view(np.uint32).T[::-1])
     return rows[order]

@@ -271,6 +271,34 @@ class Grid:
                 "read_distance")
         return out
 
+    def count_mesh(self, lo=None, hi=None) -> int:
+        """Number of triangles extract_mesh would return for the box [lo, hi)."""
+        lo_a, hi_a, _ = self._box(lo, hi)
+        n = C.c_uint64()
+        L.check(L.lib().dbtsdf_extract_mesh(self._h, lo_a, hi_a, None, 0, C.byref(n)), "extract_mesh")
+        return int(n.value)
+
+    def extract_mesh(self, lo=None, hi=None, out=None):
+        """Marching-cubes mesh of the zero level over the box [lo, hi): a (n, 3, 3) float32 CUDA tensor of
+        triangles (vertices counter-clockwise about the normal, which points to positive distance), in no
+        particular order. `out`, a float32 CUDA tensor of shape (m, 3, 3), is filled instead when given
+        and m is enough (a counting pass sizes the result otherwise)."""
+        import torch
+        lo_a, hi_a, _ = self._box(lo, hi)
+        n = C.c_uint64()
+        if out is None:
+            count = self.count_mesh(lo, hi)
+            dev = self.mask_tensor.device if self.mask_tensor is not None else torch.device("cuda")
+            out = torch.empty((count, 3, 3), dtype=torch.float32, device=dev)
+        if out.dtype != torch.float32 or not out.is_cuda or not out.is_contiguous() or tuple(out.shape[1:]) != (3, 3):
+            raise ValueError("out must be a contiguous float32 CUDA tensor of shape (m, 3, 3)")
+        ptr = C.c_void_p(out.data_ptr()) if out.shape[0] else None
+        L.check(L.lib().dbtsdf_extract_mesh(self._h, lo_a, hi_a, ptr, int(out.shape[0]), C.byref(n)),
+                "extract_mesh")
+        if int(n.value) > out.shape[0]:
+            raise ValueError(f"mesh has {int(n.value)} triangles, out holds {out.shape[0]}")
+        return out[: int(n.value)]
+
     def write_voxels(self, mask, packed) -> None:
         m = np.ascontiguousarray(mask, dtype=np.uint32)
         p = np.ascontiguousarray(packed, dtype=np.uint32)

@@ -79,6 +79,7 @@ SIGNATURES = {
     "dbtsdf_read_voxels": (C.c_int, [P, P, P, P, P]),
     "dbtsdf_read_distance": (C.c_int, [P, P, P, P]),
     "dbtsdf_write_voxels": (C.c_int, [P, P, P]),
+    "dbtsdf_extract_mesh": (C.c_int, [P, P, P, P, U64, C.POINTER(U64)]),
     "dbtsdf_destroy_grid": (None, [P]),
     "dbtsdf_set_profiling": (C.c_int, [P, C.c_int]),
     "dbtsdf_read_profile": (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(U64), C.POINTER(C.c_double),

@@ -864,6 +864,61 @@ dbtsdf_status dbtsdf_read_distance(dbtsdf_grid *g, const uint32_t lo[3], const u
     return gather(g, lo, hi, g->mask, g->packed, dist_out, 1);
 }
 
+dbtsdf_status dbtsdf_extract_mesh(dbtsdf_grid *g, const uint32_t lo[3], const uint32_t hi[3], float *tris_dev,
+                                  uint64_t max_tris, uint64_t *n_tris) {
+    if (!g || !n_tris) return invalid("NULL argument");
+    if (!tris_dev && max_tris) return invalid("NULL triangle buffer with max_tris > 0");
+    *n_tris = 0;
+    const uint32_t zero[3] = {0, 0, 0};
+    if (!lo != !hi) return invalid("give both box corners or neither");
+    if (!lo) {
+        lo = zero;
+        hi = g->params.dims;
+    }
+    dbtsdf_status s = check_box(g, lo, hi);
+    if (s != DBTSDF_OK) return s;
+    if (g->poisoned) return DBTSDF_ERR_POISONED;
+    if (hi[0] - lo[0] < 2 || hi[1] - lo[1] < 2 || hi[2] - lo[2] < 2) return DBTSDF_OK;  // no whole cube
+    hipError_t e = hipSetDevice(g->device);
+    if (e == hipSuccess && !g->mesh_table) {
+        e = hipMalloc((void **)&g->mesh_table, sizeof(MeshTable));
+        if (e == hipSuccess) e = hipMemcpy(g->mesh_table, &mesh_table(), sizeof(MeshTable), hipMemcpyHostToDevice);
+        if (e != hipSuccess && g->mesh_table) {
+            (void)hipFree(g->mesh_table);
+            g->mesh_table = nullptr;
+        }
+    }
+    if (e == hipSuccess && !g->mesh_count) e = hipMalloc((void **)&g->mesh_count, sizeof(unsigned long long));
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        set_error("mesh export buffers do not fit in device memory");
+        return DBTSDF_ERR_OUT_OF_MEMORY;
+    }
+    MeshArgs m{};
+    m.mask = g->mask;
+    m.packed = g->packed;
+    m.table = g->mesh_table;
+    m.out = max_tris ? tris_dev : nullptr;
+    m.count = g->mesh_count;
+    m.cap = max_tris;
+    m.nx = g->params.dims[0];
+    m.ny = g->params.dims[1];
+    for (int k = 0; k < 3; ++k) {
+        m.lo[k] = lo[k];
+        m.nc[k] = hi[k] - lo[k] - 1;
+        m.origin[k] = g->params.origin[k];
+    }
+    m.s = g->params.voxel_size;
+    unsigned long long count = 0;
+    if (e == hipSuccess) e = launch_fill_u64(g->mesh_count, 0ull, 1, g->stream);
+    if (e == hipSuccess) e = launch_mesh(m, g->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&count, g->mesh_count, sizeof(count), hipMemcpyDeviceToHost, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return check_hip(e, "extracting the mesh", g);
+    *n_tris = count;
+    return DBTSDF_OK;
+}
+
 dbtsdf_status dbtsdf_write_voxels(dbtsdf_grid *g, const uint32_t *mask_in, const uint32_t *packed_in) {
     if (!g || !mask_in || !packed_in) return invalid("NULL argument");
     if (g->poisoned) return DBTSDF_ERR_POISONED;
@@ -895,6 +950,8 @@ void dbtsdf_destroy_grid(dbtsdf_grid *g) {
         if (g->packed) (void)hipFree(g->packed);
     }
     if (g->ev) (void)hipEventDestroy(g->ev);
+    if (g->mesh_table) (void)hipFree(g->mesh_table);
+    if (g->mesh_count) (void)hipFree(g->mesh_count);
     delete g;
 }
 

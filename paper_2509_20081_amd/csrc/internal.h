@@ -198,6 +198,32 @@ hipError_t launch_gather_box(const uint32_t *plane, const uint32_t *packed, cons
 // Number of positions where a != b (n words), added into *count.
 hipError_t launch_count_diff(const uint32_t *a, const uint32_t *b, uint64_t n, unsigned long long *count,
                              hipStream_t st);
+// ------------------------------------------------------------ mesh export ---
+// Marching Cubes case table (mesh.cpp): per corner case (bit c set = corner c
+// inside), byte 0 the triangle count, byte 1 the loop count, then per loop a
+// header (vertex count m | 16 when fanned from its centre) and its m edge
+// numbers, from the smallest.
+constexpr uint32_t kMeshCaseBytes = 24;
+struct MeshTable {
+    uint8_t b[256][kMeshCaseBytes];
+};
+const MeshTable &mesh_table();
+
+struct MeshArgs {
+    const uint32_t *mask;
+    const uint32_t *packed;
+    const uint32_t *table;       // the MeshTable on the device
+    float *out;                  // 9 floats per triangle, or null (count only)
+    unsigned long long *count;   // triangles found (reset by the caller)
+    unsigned long long cap;      // triangles out can hold
+    uint32_t nx, ny;             // grid dimensions (plane strides)
+    uint32_t lo[3];              // first cube (its lower corner voxel)
+    uint32_t nc[3];              // cubes per axis
+    float origin[3];
+    float s;
+};
+hipError_t launch_mesh(const MeshArgs &m, hipStream_t st);
+
 // Workgroups of a fully resident persistent apply grid (row_kernel: the
 // kernel set has the row kernel's tables).
 int apply_blocks_default(const Tuning &t, int K, bool row_kernel, int device);

@@ -42,6 +42,7 @@
 // and L2/LDS atomic throughput.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <array>
 #include <map>
 #include <mutex>
@@ -1339,6 +1340,134 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const C
     }
 }
 
+// ========================================================== mesh export ===
+// Marching Cubes of the zero level of the signed distance d = (s ? +1 : -1) *
+// popcount(mask) (the mesh export at iso = 0.0 of the paper's pipeline, Sec.
+// III): one thread per cube of the box; a corner is inside when d < 0, i.e.
+// its sign bit is clear and its mask is not empty, so the case needs no
+// popcount. Crossed edges take their vertex at t = d_lo / (d_lo - d_hi) along
+// the edge, every coordinate one fp32 operation at a time. A wavefront
+// reserves room for its cubes' triangles with one atomic; the triangles of a
+// launch therefore come out in no fixed order.
+constexpr int kMeshThreads = 256;
+
+__device__ __forceinline__ uint32_t mesh_low_corner(uint32_t e) {
+    const uint32_t a = e >> 2, r = e & 3u;
+    return a == 0u ? 2u * r : a == 1u ? ((r & 1u) | ((r & 2u) << 1)) : r;
+}
+
+__global__ __launch_bounds__(kMeshThreads) void k_mesh(MeshArgs m) {
+    __shared__ uint32_t tab[256 * kMeshCaseBytes / 4];
+    for (uint32_t i = threadIdx.x; i < 256 * kMeshCaseBytes / 4; i += blockDim.x) tab[i] = m.table[i];
+    __syncthreads();
+    auto tb = [&](uint32_t cs, uint32_t k) { return (tab[cs * (kMeshCaseBytes / 4) + k / 4] >> (8 * (k % 4))) & 255u; };
+    const unsigned long long n_cubes = (unsigned long long)m.nc[0] * m.nc[1] * m.nc[2];
+    const unsigned long long plane = (unsigned long long)m.nx * m.ny;
+    const uint32_t l = lane();
+    // the block walks the cubes in lock step (the wave scan needs every lane)
+    for (unsigned long long base = (unsigned long long)blockIdx.x * blockDim.x; base < n_cubes;
+         base += (unsigned long long)gridDim.x * blockDim.x) {
+        const unsigned long long q = base + threadIdx.x;
+        const bool live = q < n_cubes;
+        uint32_t i = 0, j = 0, k = 0, cs = 0;
+        int d[8];
+        if (live) {
+            i = (uint32_t)(q % m.nc[0]);
+            j = (uint32_t)((q / m.nc[0]) % m.nc[1]);
+            k = (uint32_t)(q / ((unsigned long long)m.nc[0] * m.nc[1]));
+            i += m.lo[0];
+            j += m.lo[1];
+            k += m.lo[2];
+            const unsigned long long v0 = i + (unsigned long long)m.nx * j + plane * k;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const unsigned long long v = v0 + (c & 1) + (unsigned long long)m.nx * ((c >> 1) & 1) + plane * (c >> 2);
+                const uint32_t mk = m.mask[v], pk = m.packed[v];
+                const int n = __popc(mk);
+                d[c] = (pk >> 31) ? n : -n;
+                cs |= (d[c] < 0 ? 1u : 0u) << c;
+            }
+        }
+        const uint32_t n_t = live ? tb(cs, 0) : 0u;
+        const uint32_t incl = wave_incl_scan_u32(n_t);
+        unsigned long long first = 0;
+        const uint32_t total = __shfl(incl, 63, 64);
+        if (total) {
+            if (l == 63u) first = atomicAdd(m.count, (unsigned long long)total);
+            first = __shfl(first, 63, 64);
+        }
+        if (n_t == 0u) continue;
+        unsigned long long slot = first + incl - n_t;
+        // vertex of crossed edge e
+        auto vtx = [&](uint32_t e, float &x, float &y, float &z) {
+            const uint32_t a = e >> 2, clo = mesh_low_corner(e), chi = clo | (1u << a);
+            const uint32_t u[3] = {i + (clo & 1u), j + ((clo >> 1) & 1u), k + (clo >> 2)};
+            float c[3];
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                const float h = (float)u[t] + 0.5f;
+                const float hs = h * m.s;
+                c[t] = m.origin[t] + hs;
+            }
+            const float dlo = (float)d[clo], dhi = (float)d[chi];
+            const float den = dlo - dhi;
+            const float tt = dlo / den;
+            const float ts = tt * m.s;
+            c[a] = c[a] + ts;
+            x = c[0];
+            y = c[1];
+            z = c[2];
+        };
+        auto put = [&](float ax, float ay, float az, float bx, float by, float bz, float cx, float cy, float cz) {
+            if (m.out && slot < m.cap) {
+                float *o = m.out + 9ull * slot;
+                o[0] = ax; o[1] = ay; o[2] = az;
+                o[3] = bx; o[4] = by; o[5] = bz;
+                o[6] = cx; o[7] = cy; o[8] = cz;
+            }
+            ++slot;
+        };
+        const uint32_t n_loops = tb(cs, 1);
+        uint32_t pos = 2;
+        for (uint32_t L = 0; L < n_loops; ++L) {
+            const uint32_t hdr = tb(cs, pos++), mm = hdr & 15u;
+            if (hdr & 16u) {
+                // fanned from the centre: the mean of the loop's vertices
+                float sx, sy, sz;
+                vtx(tb(cs, pos), sx, sy, sz);
+                for (uint32_t w = 1; w < mm; ++w) {
+                    float x, y, z;
+                    vtx(tb(cs, pos + w), x, y, z);
+                    sx = sx + x;
+                    sy = sy + y;
+                    sz = sz + z;
+                }
+                const float fm = (float)mm;
+                const float cx = sx / fm, cy = sy / fm, cz = sz / fm;
+                for (uint32_t w = 0; w < mm; ++w) {
+                    float ax, ay, az, bx, by, bz;
+                    vtx(tb(cs, pos + w), ax, ay, az);
+                    vtx(tb(cs, pos + (w + 1) % mm), bx, by, bz);
+                    put(cx, cy, cz, ax, ay, az, bx, by, bz);
+                }
+            } else {
+                float x0, y0, z0, px, py, pz;
+                vtx(tb(cs, pos), x0, y0, z0);
+                vtx(tb(cs, pos + 1), px, py, pz);
+                for (uint32_t w = 2; w < mm; ++w) {
+                    float x, y, z;
+                    vtx(tb(cs, pos + w), x, y, z);
+                    put(x0, y0, z0, px, py, pz, x, y, z);
+                    px = x;
+                    py = y;
+                    pz = z;
+                }
+            }
+            pos += mm;
+        }
+    }
+}
+
 // ================================================================ utility ===
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, uint64_t n) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) p[i] = v;
@@ -1555,6 +1684,14 @@ hipError_t launch_pipeline(const PipeArgs &a, const Tuning &t, uint32_t points_c
     }
     if (apply) hipLaunchKernelGGL(f, dim3(t.apply_blocks), dim3(t.threads), 0, st, a);
     if (post) k_download<<<kCopyBlocks, 256, 0, st>>>(a, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_mesh(const MeshArgs &m, hipStream_t st) {
+    const unsigned long long n = (unsigned long long)m.nc[0] * m.nc[1] * m.nc[2];
+    if (n == 0) return hipSuccess;
+    const uint32_t blocks = (uint32_t)std::min<unsigned long long>((n + kMeshThreads - 1) / kMeshThreads, 8192ull);
+    k_mesh<<<blocks, kMeshThreads, 0, st>>>(m);
     return hipGetLastError();
 }
 

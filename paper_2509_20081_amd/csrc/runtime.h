@@ -122,6 +122,9 @@ struct dbtsdf_grid {
     uint32_t brick_dims[3] = {0, 0, 0};
     std::unique_ptr<dbtsdf::Workspace> ws;
     hipEvent_t ev = nullptr;
+    // mesh export: the case table on the device and the triangle counter
+    uint32_t *mesh_table = nullptr;
+    unsigned long long *mesh_count = nullptr;
     bool poisoned = false;
     // set by the server, which orders all work on its grids itself: batches
     // then skip the event handshake with the grid's own stream
