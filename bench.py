@@ -277,6 +277,31 @@ def cpu_baseline(gdef, scans, kparams, budget_s=15.0):
                 scans_per_s=n / t_tot)
 
 
+def run_mesh(torch, g, dims, reps=3):
+    """Mesh export (Marching Cubes at iso 0) of the whole grid after the timed scans: HIP events on the
+    grid's stream around each extraction call (the call synchronises, so its host return is inside)."""
+    n = g.count_mesh()
+    out = torch.empty((max(n, 1), 3, 3), dtype=torch.float32, device="cuda")
+    g.extract_mesh(out=out)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.extract_mesh(out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    t = min(ms)
+    vox = dims[0] * dims[1] * dims[2]
+    nbytes = 8.0 * vox + 36.0 * n
+    return dict(triangles=n, ms=t, cubes_per_s=(dims[0] - 1) * (dims[1] - 1) * (dims[2] - 1) / (t * 1e-3),
+                roofline=dict(bound="hbm", achieved=nbytes / (t * 1e-3) / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
+                              frac=nbytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                              per_launch="8 B per voxel (both planes read once) + 36 B per triangle written"),
+                timing="HIP events around one extraction call (best of %d), whole grid" % reps)
+
+
 def copy_calibration(torch, nbytes=1 << 30):
     """A plain device copy of known size (for scaling HBM counters of a --pmc run)."""
     a = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda")
@@ -398,6 +423,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mesh", action="store_true", help="skip the mesh export leg")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--latency-scans", type=int, default=50)
     ap.add_argument("--serve-seconds", type=float, default=5.0)
@@ -461,6 +487,9 @@ def main():
     value = upd / dt
     log(f"plain: {args.steps} scans in {dt * 1e3:.1f} ms -> {value / 1e9:.1f} G voxel-updates/s; profile {prof}")
     plain_hash = grid_hash(torch, g) if not args.no_batched else None
+    mesh = None if args.no_mesh else run_mesh(torch, g, gdef["dims"])
+    if mesh:
+        log(f"mesh: {mesh}")
     g.close()
     torch.cuda.empty_cache()
 
@@ -566,6 +595,7 @@ def main():
         "scans_per_s": args.steps / dt,
         "mean_integrated_per_scan": float(np.mean([s["n_integrated"] for s in sd])),
         "batched": batched,
+        "mesh_export": mesh,
         "latency_ms": latency,
         "served": served,
         "c4_batching": c4,

@@ -1343,13 +1343,18 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const C
 // ========================================================== mesh export ===
 // Marching Cubes of the zero level of the signed distance d = (s ? +1 : -1) *
 // popcount(mask) (the mesh export at iso = 0.0 of the paper's pipeline, Sec.
-// III): one thread per cube of the box; a corner is inside when d < 0, i.e.
-// its sign bit is clear and its mask is not empty, so the case needs no
-// popcount. Crossed edges take their vertex at t = d_lo / (d_lo - d_hi) along
-// the edge, every coordinate one fp32 operation at a time. A wavefront
-// reserves room for its cubes' triangles with one atomic; the triangles of a
-// launch therefore come out in no fixed order.
+// III). A corner is inside when d < 0, i.e. its sign bit is clear and its mask
+// is not empty. Crossed edges take their vertex at t = d_lo / (d_lo - d_hi)
+// along the edge, every coordinate one fp32 operation at a time.
+// A wavefront takes a run of 64 voxels of one grid row pair (j, j + 1) and
+// walks it up through the box in z: each step loads one new layer (two rows,
+// both planes: four coalesced loads per lane) and takes the x + 1 corners from
+// the next lane, so lanes 0-62 hold cubes and every voxel is read about twice.
+// A wavefront walks its run twice: first counting its triangles, then, with
+// the room of the whole run reserved by one atomic, writing them; the
+// triangles of a call therefore come out in no fixed order.
 constexpr int kMeshThreads = 256;
+constexpr uint32_t kMeshRun = 63;     // cubes per wavefront run (lane 63 only lends its corners)
 
 __device__ __forceinline__ uint32_t mesh_low_corner(uint32_t e) {
     const uint32_t a = e >> 2, r = e & 3u;
@@ -1361,109 +1366,145 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh(MeshArgs m) {
     for (uint32_t i = threadIdx.x; i < 256 * kMeshCaseBytes / 4; i += blockDim.x) tab[i] = m.table[i];
     __syncthreads();
     auto tb = [&](uint32_t cs, uint32_t k) { return (tab[cs * (kMeshCaseBytes / 4) + k / 4] >> (8 * (k % 4))) & 255u; };
-    const unsigned long long n_cubes = (unsigned long long)m.nc[0] * m.nc[1] * m.nc[2];
-    const unsigned long long plane = (unsigned long long)m.nx * m.ny;
     const uint32_t l = lane();
-    // the block walks the cubes in lock step (the wave scan needs every lane)
-    for (unsigned long long base = (unsigned long long)blockIdx.x * blockDim.x; base < n_cubes;
-         base += (unsigned long long)gridDim.x * blockDim.x) {
-        const unsigned long long q = base + threadIdx.x;
-        const bool live = q < n_cubes;
-        uint32_t i = 0, j = 0, k = 0, cs = 0;
-        int d[8];
-        if (live) {
-            i = (uint32_t)(q % m.nc[0]);
-            j = (uint32_t)((q / m.nc[0]) % m.nc[1]);
-            k = (uint32_t)(q / ((unsigned long long)m.nc[0] * m.nc[1]));
-            i += m.lo[0];
-            j += m.lo[1];
-            k += m.lo[2];
-            const unsigned long long v0 = i + (unsigned long long)m.nx * j + plane * k;
+    const uint32_t runs_x = (m.nc[0] + kMeshRun - 1) / kMeshRun;
+    const uint64_t n_runs = (uint64_t)runs_x * m.nc[1];
+    const uint64_t plane = (uint64_t)m.nx * m.ny;
+    const uint32_t wpb = blockDim.x >> 6;
+    const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (uint64_t run = (uint64_t)blockIdx.x * wpb + wid; run < n_runs; run += (uint64_t)gridDim.x * wpb) {
+        const uint32_t rx = (uint32_t)(run % runs_x), ry = (uint32_t)(run / runs_x);
+        const uint32_t i = m.lo[0] + rx * kMeshRun + l;          // this lane's voxel column
+        const uint32_t j = m.lo[1] + ry;
+        const bool has_voxel = rx * kMeshRun + l <= m.nc[0];      // voxel i inside the box
+        const bool has_cube = l < kMeshRun && rx * kMeshRun + l < m.nc[0];
+        // d of the lane's two voxels (rows j, j + 1) in a layer
+        auto layer = [&](uint32_t k, int &a, int &b) {
+            a = b = 32;
+            if (!has_voxel) return;
+            const uint64_t v = i + (uint64_t)m.nx * j + plane * k;
+            const uint32_t ma = m.mask[v], pa = m.packed[v];
+            const uint32_t mb = m.mask[v + m.nx], pb = m.packed[v + m.nx];
+            a = (pa >> 31) ? __popc(ma) : -__popc(ma);
+            b = (pb >> 31) ? __popc(mb) : -__popc(mb);
+        };
+        // corners of the cube (i, j, k) from the layers k (pa, pb) and k + 1 (ca, cb)
+        auto corners = [&](int pa, int pb, int ca, int cb, int d[8]) {
+            d[0] = pa;
+            d[1] = __shfl_down(pa, 1, 64);
+            d[2] = pb;
+            d[3] = __shfl_down(pb, 1, 64);
+            d[4] = ca;
+            d[5] = __shfl_down(ca, 1, 64);
+            d[6] = cb;
+            d[7] = __shfl_down(cb, 1, 64);
+            uint32_t cs = 0;
 #pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                const unsigned long long v = v0 + (c & 1) + (unsigned long long)m.nx * ((c >> 1) & 1) + plane * (c >> 2);
-                const uint32_t mk = m.mask[v], pk = m.packed[v];
-                const int n = __popc(mk);
-                d[c] = (pk >> 31) ? n : -n;
-                cs |= (d[c] < 0 ? 1u : 0u) << c;
+            for (int c = 0; c < 8; ++c) cs |= (d[c] < 0 ? 1u : 0u) << c;
+            return cs;
+        };
+        // first walk: the run's triangles, so that one atomic reserves the
+        // room of the whole run (a counter per step would be one hot address)
+        uint32_t mine = 0;
+        {
+            int pa, pb;
+            layer(m.lo[2], pa, pb);
+            for (uint32_t kk = 0; kk < m.nc[2]; ++kk) {
+                int ca, cb, d[8];
+                layer(m.lo[2] + kk + 1, ca, cb);
+                const uint32_t cs = corners(pa, pb, ca, cb, d);
+                mine += has_cube ? tb(cs, 0) : 0u;
+                pa = ca;
+                pb = cb;
             }
         }
-        const uint32_t n_t = live ? tb(cs, 0) : 0u;
-        const uint32_t incl = wave_incl_scan_u32(n_t);
-        unsigned long long first = 0;
+        const uint32_t incl = wave_incl_scan_u32(mine);
         const uint32_t total = __shfl(incl, 63, 64);
-        if (total) {
-            if (l == 63u) first = atomicAdd(m.count, (unsigned long long)total);
-            first = __shfl(first, 63, 64);
-        }
-        if (n_t == 0u) continue;
-        unsigned long long slot = first + incl - n_t;
-        // vertex of crossed edge e
-        auto vtx = [&](uint32_t e, float &x, float &y, float &z) {
-            const uint32_t a = e >> 2, clo = mesh_low_corner(e), chi = clo | (1u << a);
-            const uint32_t u[3] = {i + (clo & 1u), j + ((clo >> 1) & 1u), k + (clo >> 2)};
-            float c[3];
+        if (total == 0u) continue;
+        unsigned long long first = 0;
+        if (l == 63u) first = atomicAdd(m.count, (unsigned long long)total);
+        first = __shfl(first, 63, 64);
+        if (!m.out) continue;   // counting only
+        unsigned long long slot = first + incl - mine;
+        // second walk: the triangles, each lane's in z order
+        int pa, pb;
+        layer(m.lo[2], pa, pb);
+        for (uint32_t kk = 0; kk < m.nc[2]; ++kk) {
+            const uint32_t k = m.lo[2] + kk;
+            int ca, cb, d[8];
+            layer(k + 1, ca, cb);
+            const uint32_t cs = corners(pa, pb, ca, cb, d);
+            pa = ca;
+            pb = cb;
+            const uint32_t n_t = has_cube ? tb(cs, 0) : 0u;
+            if (n_t == 0u) continue;
+            // vertex of crossed edge e
+            auto vtx = [&](uint32_t e, float &x, float &y, float &z) {
+                const uint32_t a = e >> 2, clo = mesh_low_corner(e), chi = clo | (1u << a);
+                const uint32_t u[3] = {i + (clo & 1u), j + ((clo >> 1) & 1u), k + (clo >> 2)};
+                float c[3];
 #pragma unroll
-            for (int t = 0; t < 3; ++t) {
-                const float h = (float)u[t] + 0.5f;
-                const float hs = h * m.s;
-                c[t] = m.origin[t] + hs;
-            }
-            const float dlo = (float)d[clo], dhi = (float)d[chi];
-            const float den = dlo - dhi;
-            const float tt = dlo / den;
-            const float ts = tt * m.s;
-            c[a] = c[a] + ts;
-            x = c[0];
-            y = c[1];
-            z = c[2];
-        };
-        auto put = [&](float ax, float ay, float az, float bx, float by, float bz, float cx, float cy, float cz) {
-            if (m.out && slot < m.cap) {
-                float *o = m.out + 9ull * slot;
-                o[0] = ax; o[1] = ay; o[2] = az;
-                o[3] = bx; o[4] = by; o[5] = bz;
-                o[6] = cx; o[7] = cy; o[8] = cz;
-            }
-            ++slot;
-        };
-        const uint32_t n_loops = tb(cs, 1);
-        uint32_t pos = 2;
-        for (uint32_t L = 0; L < n_loops; ++L) {
-            const uint32_t hdr = tb(cs, pos++), mm = hdr & 15u;
-            if (hdr & 16u) {
-                // fanned from the centre: the mean of the loop's vertices
-                float sx, sy, sz;
-                vtx(tb(cs, pos), sx, sy, sz);
-                for (uint32_t w = 1; w < mm; ++w) {
-                    float x, y, z;
-                    vtx(tb(cs, pos + w), x, y, z);
-                    sx = sx + x;
-                    sy = sy + y;
-                    sz = sz + z;
+                for (int t = 0; t < 3; ++t) {
+                    const float h = (float)u[t] + 0.5f;
+                    const float hs = h * m.s;
+                    c[t] = m.origin[t] + hs;
                 }
-                const float fm = (float)mm;
-                const float cx = sx / fm, cy = sy / fm, cz = sz / fm;
-                for (uint32_t w = 0; w < mm; ++w) {
-                    float ax, ay, az, bx, by, bz;
-                    vtx(tb(cs, pos + w), ax, ay, az);
-                    vtx(tb(cs, pos + (w + 1) % mm), bx, by, bz);
-                    put(cx, cy, cz, ax, ay, az, bx, by, bz);
+                const float dlo = (float)d[clo], dhi = (float)d[chi];
+                const float den = dlo - dhi;
+                const float tt = dlo / den;
+                const float ts = tt * m.s;
+                c[a] = c[a] + ts;
+                x = c[0];
+                y = c[1];
+                z = c[2];
+            };
+            auto put = [&](float ax, float ay, float az, float bx, float by, float bz, float cx, float cy, float cz) {
+                if (slot < m.cap) {
+                    float *o = m.out + 9ull * slot;
+                    o[0] = ax; o[1] = ay; o[2] = az;
+                    o[3] = bx; o[4] = by; o[5] = bz;
+                    o[6] = cx; o[7] = cy; o[8] = cz;
                 }
-            } else {
-                float x0, y0, z0, px, py, pz;
-                vtx(tb(cs, pos), x0, y0, z0);
-                vtx(tb(cs, pos + 1), px, py, pz);
-                for (uint32_t w = 2; w < mm; ++w) {
-                    float x, y, z;
-                    vtx(tb(cs, pos + w), x, y, z);
-                    put(x0, y0, z0, px, py, pz, x, y, z);
-                    px = x;
-                    py = y;
-                    pz = z;
+                ++slot;
+            };
+            const uint32_t n_loops = tb(cs, 1);
+            uint32_t pos = 2;
+            for (uint32_t L = 0; L < n_loops; ++L) {
+                const uint32_t hdr = tb(cs, pos++), mm = hdr & 15u;
+                if (hdr & 16u) {
+                    // fanned from the centre: the mean of the loop's vertices
+                    float sx, sy, sz;
+                    vtx(tb(cs, pos), sx, sy, sz);
+                    for (uint32_t w = 1; w < mm; ++w) {
+                        float x, y, z;
+                        vtx(tb(cs, pos + w), x, y, z);
+                        sx = sx + x;
+                        sy = sy + y;
+                        sz = sz + z;
+                    }
+                    const float fm = (float)mm;
+                    const float cx = sx / fm, cy = sy / fm, cz = sz / fm;
+                    for (uint32_t w = 0; w < mm; ++w) {
+                        float ax, ay, az, bx, by, bz;
+                        vtx(tb(cs, pos + w), ax, ay, az);
+                        vtx(tb(cs, pos + (w + 1) % mm), bx, by, bz);
+                        put(cx, cy, cz, ax, ay, az, bx, by, bz);
+                    }
+                } else {
+                    float x0, y0, z0, px, py, pz;
+                    vtx(tb(cs, pos), x0, y0, z0);
+                    vtx(tb(cs, pos + 1), px, py, pz);
+                    for (uint32_t w = 2; w < mm; ++w) {
+                        float x, y, z;
+                        vtx(tb(cs, pos + w), x, y, z);
+                        put(x0, y0, z0, px, py, pz, x, y, z);
+                        px = x;
+                        py = y;
+                        pz = z;
+                    }
                 }
+                pos += mm;
             }
-            pos += mm;
         }
     }
 }
@@ -1688,9 +1729,11 @@ hipError_t launch_pipeline(const PipeArgs &a, const Tuning &t, uint32_t points_c
 }
 
 hipError_t launch_mesh(const MeshArgs &m, hipStream_t st) {
-    const unsigned long long n = (unsigned long long)m.nc[0] * m.nc[1] * m.nc[2];
-    if (n == 0) return hipSuccess;
-    const uint32_t blocks = (uint32_t)std::min<unsigned long long>((n + kMeshThreads - 1) / kMeshThreads, 8192ull);
+    if ((unsigned long long)m.nc[0] * m.nc[1] * m.nc[2] == 0) return hipSuccess;
+    // one wavefront per run of kMeshRun cubes of a row pair
+    const unsigned long long runs = (unsigned long long)((m.nc[0] + kMeshRun - 1) / kMeshRun) * m.nc[1];
+    const unsigned long long wpb = kMeshThreads / 64;
+    const uint32_t blocks = (uint32_t)std::min<unsigned long long>((runs + wpb - 1) / wpb, 16384ull);
     k_mesh<<<blocks, kMeshThreads, 0, st>>>(m);
     return hipGetLastError();
 }
