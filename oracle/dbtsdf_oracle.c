@@ -38,6 +38,12 @@
  *     alternative kernel set, with exact integer shadows;
  *   - the shadow is {o : o.o <= r_s^2, o.u_b >= 0}, contact voxel and the planar
  *     face included;
+ *   - the conical shadow the paper contrasts with it (Sec. IV-A, no aperture
+ *     given) is {o : o.o <= r_s^2, o = 0 or the angle between o and u_b at
+ *     most alpha}: o.u_b >= |o| cos(alpha), with cos(alpha) computed in fp64
+ *     and snapped to 0 below 1e-12 (so alpha = 90 deg is the hemisphere);
+ *     cube bins test (o.s)^2 >= (o.o)(s.s) cos^2(alpha) with o.s >= 0 on the
+ *     integer direction s;
  *   - "first return" = lowest input index among valid, in-bounds returns;
  *   - non-finite or zero-range returns are skipped and counted;
  *   - the front end is fp32, one IEEE operation at a time, no FMA contraction
@@ -52,6 +58,8 @@
 #define ORC_BIN_CUBE26 1
 #define ORC_METRIC_L2 0
 #define ORC_METRIC_L1 1
+#define ORC_SHADOW_HEMISPHERE 0
+#define ORC_SHADOW_CONE 1
 
 typedef struct {
     uint32_t kernel_size;     /* K, odd */
@@ -66,6 +74,8 @@ typedef struct {
     uint32_t hit_threshold;   /* T */
     uint32_t hit_max;         /* H_max */
     uint32_t dedup;           /* 1 = integrate only the first return per voxel per scan */
+    uint32_t shadow_model;    /* ORC_SHADOW_* */
+    float cone_deg;           /* half-angle alpha of the conical shadow, degrees in (0, 90] */
 } orc_params;
 
 typedef struct {
@@ -210,6 +220,12 @@ static int params_ok(const orc_params *p)
         return 0;
     if (p->hit_max < 1 || p->hit_max > 65535)
         return 0;
+    if (p->shadow_model == ORC_SHADOW_CONE) {
+        if (!(p->cone_deg > 0.0f && p->cone_deg <= 90.0f))
+            return 0;
+    } else if (p->shadow_model != ORC_SHADOW_HEMISPHERE) {
+        return 0;
+    }
     return 1;
 }
 
@@ -272,26 +288,37 @@ orc_ctx *orc_create(const orc_params *p)
         }
     }
 
-    /* hemispherical shadow: o.o <= r_s^2 and o.u_b >= 0 */
+    /* shadow: o.o <= r_s^2 and o behind the contact voxel: o.u_b >= 0
+     * (hemisphere), or within alpha of u_b (cone) */
     c->shadow_k = (uint8_t *)calloc((size_t)c->n_bins * K * K * K, 1);
-    for (b = 0; b < (int)c->n_bins; b++) {
+    {
+        const int cone = p->shadow_model == ORC_SHADOW_CONE;
+        const double cos_a = cone ? snap(cos((double)p->cone_deg * M_PI / 180.0)) : 0.0;
+        for (b = 0; b < (int)c->n_bins; b++) {
         for (dz = -R; dz <= R; dz++)
             for (dy = -R; dy <= R; dy++)
                 for (dx = -R; dx <= R; dx++) {
-                    int in_ball = (dx * dx + dy * dy + dz * dz) <= p->shadow_r2;
+                    int oo = dx * dx + dy * dy + dz * dz;
+                    int in_ball = oo <= p->shadow_r2;
                     int behind;
                     if (p->binning == ORC_BIN_CUBE26) {
                         int idx = b >= 13 ? b + 1 : b;
                         int sx = idx / 9 - 1, sy = (idx / 3) % 3 - 1, sz = idx % 3 - 1;
-                        behind = (dx * sx + dy * sy + dz * sz) >= 0;
+                        int os = dx * sx + dy * sy + dz * sz;
+                        behind = os >= 0;
+                        if (cone && behind) {
+                            int ss = sx * sx + sy * sy + sz * sz;
+                            behind = (double)os * (double)os >= (double)(oo * ss) * (cos_a * cos_a);
+                        }
                     } else {
                         double dot = dx * c->dirs[3 * b + 0] + dy * c->dirs[3 * b + 1] +
                                      dz * c->dirs[3 * b + 2];
-                        behind = dot >= -1e-9;
+                        behind = cone ? dot >= sqrt((double)oo) * cos_a - 1e-9 : dot >= -1e-9;
                     }
                     if (p->shadow_r2 >= 0 && in_ball && behind)
                         c->shadow_k[(size_t)b * K * K * K + ((dz + R) * K + (dy + R)) * K + (dx + R)] = 1;
                 }
+        }
     }
     return c;
 }

@@ -17,6 +17,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 BINNING = {"azel": 0, "cube26": 1}
 METRIC = {"l2": 0, "l1": 1}
+SHADOW = {"hemisphere": 0, "cone": 1}
 
 
 class _Params(C.Structure):
@@ -25,6 +26,7 @@ class _Params(C.Structure):
         ("bins_el", C.c_uint32), ("shadow_r2", C.c_int32), ("metric", C.c_uint32),
         ("dims", C.c_uint32 * 3), ("voxel_size", C.c_float), ("origin", C.c_float * 3),
         ("hit_threshold", C.c_uint32), ("hit_max", C.c_uint32), ("dedup", C.c_uint32),
+        ("shadow_model", C.c_uint32), ("cone_deg", C.c_float),
     ]
 
 
@@ -72,7 +74,7 @@ class Oracle:
 
     def __init__(self, dims, voxel_size, origin=(0.0, 0.0, 0.0), kernel_size=11, binning="cube26",
                  bins_az=40, bins_el=40, shadow_r2=9, metric="l2", hit_threshold=5,
-                 hit_max=65535, dedup=True):
+                 hit_max=65535, dedup=True, shadow_model="hemisphere", cone_deg=90.0):
         lib = _load()
         p = _Params()
         p.kernel_size = kernel_size
@@ -87,6 +89,8 @@ class Oracle:
         p.hit_threshold = hit_threshold
         p.hit_max = hit_max
         p.dedup = 1 if dedup else 0
+        p.shadow_model = SHADOW[shadow_model]
+        p.cone_deg = cone_deg
         self._p = p
         self._ctx = lib.orc_create(C.byref(p))
         if not self._ctx:

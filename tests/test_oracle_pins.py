@@ -442,3 +442,62 @@ def test_synthetic_config_scan_front_end_matches_numpy():
     assert np.array_equal(so, sb) and np.array_equal(bo, bb)
     assert np.array_equal(vo[so == 0], vb[sb == 0])
     assert (so == 0).sum() > 5000
+
+
+# ------------------------------------------------------ conical shadow ---
+def _shadows(**kw):
+    o = Oracle(dims=(16, 16, 16), voxel_size=1.0, kernel_size=11, shadow_r2=9, **kw)
+    _, sh, dirs = o.tables()
+    return sh.astype(bool), dirs
+
+
+def _cube_kind(d):
+    return int(np.count_nonzero(np.abs(d) > 1e-9))   # 1 face, 2 edge, 3 corner
+
+
+def test_cone_of_90_degrees_is_the_hemisphere():
+    """Sec. IV-A contrasts the hemispherical shadow with a conical one; a cone of half-angle 90 degrees
+    is the hemisphere itself, planar face included, for both binnings."""
+    for kw in (dict(binning="cube26"), dict(binning="azel", bins_az=8, bins_el=5)):
+        hemi, _ = _shadows(**kw)
+        cone, _ = _shadows(shadow_model="cone", cone_deg=90.0, **kw)
+        assert np.array_equal(hemi, cone)
+
+
+def test_narrow_cone_keeps_the_lattice_points_on_the_ray():
+    """Half-angle 1 degree, r_s = 3: only the voxels on the beam's own line behind the contact voxel:
+    0..3 steps along a face direction, 0..2 along an edge (|(2,2,0)|^2 = 8), 0..1 along a corner."""
+    sh, dirs = _shadows(shadow_model="cone", cone_deg=1.0)
+    R = 5
+    for b in range(26):
+        s = np.rint(dirs[b] / np.abs(dirs[b]).max()).astype(int)
+        want = np.zeros_like(sh[b])
+        for k in range(4):
+            o = k * s
+            if o @ o <= 9:
+                want[o[2] + R, o[1] + R, o[0] + R] = True
+        assert np.array_equal(sh[b], want), b
+        assert sh[b].sum() == {1: 4, 2: 3, 3: 2}[_cube_kind(dirs[b])]
+
+
+def test_cone_sizes_by_hand():
+    """Face direction, r_s = 3: cells with o_x >= 0 and o_y^2 + o_z^2 <= tan^2(alpha) o_x^2 in the ball.
+    40 deg (tan^2 = 0.704): 1 + 1 + 9 + 1 = 12; 50 deg (tan^2 = 1.420): 1 + 5 + 21 + 1 = 28."""
+    for deg, want in ((40.0, 12), (50.0, 28)):
+        sh, dirs = _shadows(shadow_model="cone", cone_deg=deg)
+        faces = [int(sh[b].sum()) for b in range(26) if _cube_kind(dirs[b]) == 1]
+        assert faces == [want] * 6
+
+
+def test_cones_nest_and_bad_angles_are_rejected():
+    for kw in (dict(binning="cube26"), dict(binning="azel", bins_az=8, bins_el=5)):
+        prev = None
+        for deg in (5.0, 20.0, 35.0, 60.0, 90.0):
+            sh, _ = _shadows(shadow_model="cone", cone_deg=deg, **kw)
+            assert sh[:, 5, 5, 5].all()          # the contact voxel is always in
+            if prev is not None:
+                assert not (prev & ~sh).any()
+            prev = sh
+    for deg in (0.0, -3.0, 90.5):
+        with pytest.raises(ValueError):
+            Oracle(dims=(16, 16, 16), voxel_size=1.0, kernel_size=5, shadow_model="cone", cone_deg=deg)
