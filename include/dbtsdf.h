@@ -56,6 +56,12 @@ typedef enum {
     DBTSDF_BIN_CUBE26 = 1  /* 26 lattice directions: 8 azimuths x 3 elevations + 2 poles */
 } dbtsdf_binning;
 
+/* Shape of the shadow (occupied evidence) behind the contact voxel. */
+typedef enum {
+    DBTSDF_SHADOW_HEMISPHERE = 0,  /* Sec. III-B: {o : o.o <= r_s^2, o.u_b >= 0} (default) */
+    DBTSDF_SHADOW_CONE = 1         /* the conical alternative of Sec. IV-A: o.u_b >= |o| cos(alpha) */
+} dbtsdf_shadow_model;
+
 /* Distance measured by the eq. 3 mask. */
 typedef enum {
     DBTSDF_DIST_L2 = 0,    /* eq. 3: n = ceil(sqrt(x^2 + y^2 + z^2)) (default) */
@@ -72,6 +78,14 @@ typedef enum {
  *                (contact voxel and planar face included); negative = no shadow
  *                (the unsigned D-LIO distance field).
  *   metric       dbtsdf_metric.
+ *   shadow_model dbtsdf_shadow_model (0, the hemisphere, when zero-initialised).
+ *   cone_deg     DBTSDF_SHADOW_CONE only: half-angle alpha in degrees, in (0, 90].
+ *                The cone is {o : o.o <= r_s^2, o = 0 or o.u_b >= |o| cos(alpha)}
+ *                with cos(alpha) in fp64, taken as 0 below 1e-12 (90 degrees is
+ *                the hemisphere); cube bins test (o.s)^2 >= (o.o)(s.s) cos^2(alpha)
+ *                and o.s >= 0 on their integer direction s, AZEL bins
+ *                o.u_b >= |o| cos(alpha) - 1e-9 in fp64 (the paper gives no
+ *                aperture).
  */
 typedef struct {
     uint32_t kernel_size;
@@ -80,6 +94,8 @@ typedef struct {
     uint32_t bins_el;
     int32_t shadow_r2;
     uint32_t metric;
+    uint32_t shadow_model;
+    float cone_deg;
 } dbtsdf_kernel_params;
 
 /* Grid flags. */

@@ -27,6 +27,7 @@ __all__ = ["KernelSet", "Grid", "Batch", "Server", "DbtsdfError", "now_ns", "lib
 
 _BINNING = {"azel": L.BIN_AZEL, "cube26": L.BIN_CUBE26}
 _METRIC = {"l2": L.DIST_L2, "l1": L.DIST_L1}
+_SHADOW = {"hemisphere": 0, "cone": 1}
 _STRATEGY = {"auto": L.STRATEGY_AUTO, "brick": L.STRATEGY_BRICK, "atomic": L.STRATEGY_ATOMIC}
 _STRATEGY_NAME = {v: k for k, v in _STRATEGY.items()}
 
@@ -108,8 +109,9 @@ class KernelSet:
     """Directional kernels (Sec. III-B): eq. 3 masks, per-bin hemispherical shadows."""
 
     def __init__(self, kernel_size: int = 11, binning: str = "cube26", bins_az: int = 40, bins_el: int = 40,
-                 shadow_r2: int = 9, metric: str = "l2"):
-        p = L.KernelParams(kernel_size, _BINNING[binning], bins_az, bins_el, shadow_r2, _METRIC[metric])
+                 shadow_r2: int = 9, metric: str = "l2", shadow_model: str = "hemisphere", cone_deg: float = 90.0):
+        p = L.KernelParams(kernel_size, _BINNING[binning], bins_az, bins_el, shadow_r2, _METRIC[metric],
+                           _SHADOW[shadow_model], cone_deg)
         h = C.c_void_p()
         self._lib = L.lib()  # held so that destruction at interpreter exit still finds it
         L.check(self._lib.dbtsdf_kernel_set_create(C.byref(p), C.byref(h)), "kernel_set_create")

@@ -19,7 +19,8 @@ STRATEGY_AUTO, STRATEGY_BRICK, STRATEGY_ATOMIC = 0, 1, 2
 
 class KernelParams(C.Structure):
     _fields_ = [("kernel_size", C.c_uint32), ("binning", C.c_uint32), ("bins_az", C.c_uint32),
-                ("bins_el", C.c_uint32), ("shadow_r2", C.c_int32), ("metric", C.c_uint32)]
+                ("bins_el", C.c_uint32), ("shadow_r2", C.c_int32), ("metric", C.c_uint32),
+                ("shadow_model", C.c_uint32), ("cone_deg", C.c_float)]
 
 
 class GridParams(C.Structure):

@@ -80,6 +80,7 @@ static dbtsdf_status make_device_tables(const KernelSet &ks, std::shared_ptr<Dev
     t.bins_az = ks.p.bins_az;
     t.bins_el = ks.p.bins_el;
     t.metric = ks.p.metric;
+    t.shadow_model = ks.p.shadow_model;
     out = std::move(d);
     return DBTSDF_OK;
 }

@@ -83,6 +83,7 @@ struct DevTables {
     int32_t K, R;
     int32_t shadow_r2;       // r_s^2, negative = no shadow
     uint32_t binning, bins_az, bins_el, metric;
+    uint32_t shadow_model;   // dbtsdf_shadow_model
 };
 
 struct DevGrid {

@@ -93,6 +93,11 @@ KernelSet *build_kernel_set(const dbtsdf_kernel_params &p, std::string *err) {
     } else if (p.binning != DBTSDF_BIN_CUBE26) {
         return fail("unknown binning");
     }
+    if (p.shadow_model == DBTSDF_SHADOW_CONE) {
+        if (!(p.cone_deg > 0.0f && p.cone_deg <= 90.0f)) return fail("cone_deg must be in (0, 90]");
+    } else if (p.shadow_model != DBTSDF_SHADOW_HEMISPHERE) {
+        return fail("unknown shadow model");
+    }
 
     KernelSet *ks = new KernelSet();
     ks->p = p;
@@ -161,7 +166,10 @@ KernelSet *build_kernel_set(const dbtsdf_kernel_params &p, std::string *err) {
         ks->el_neg.assign(1, 0u);
     }
 
-    // hemispherical shadows: inside the r_s ball and not in front of the contact voxel
+    // shadows: inside the r_s ball and not in front of the contact voxel
+    // (hemisphere), or within the half-angle of the bin direction (cone)
+    const bool cone = p.shadow_model == DBTSDF_SHADOW_CONE;
+    const double cos_a = cone ? zero_tiny(cos((double)p.cone_deg * M_PI / 180.0)) : 0.0;
     ks->shadow.assign((size_t)ks->n_bins * K3, 0);
     ks->sh_start.assign(ks->n_bins + 1, 0);
     for (uint32_t b = 0; b < ks->n_bins; ++b) {
@@ -170,12 +178,17 @@ KernelSet *build_kernel_set(const dbtsdf_kernel_params &p, std::string *err) {
         for (int z = -R; z <= R; ++z)
             for (int y = -R; y <= R; ++y)
                 for (int x = -R; x <= R; ++x) {
-                    if (x * x + y * y + z * z > p.shadow_r2) continue;
+                    const int r2 = x * x + y * y + z * z;
+                    if (r2 > p.shadow_r2) continue;
                     bool back;
-                    if (p.binning == DBTSDF_BIN_CUBE26)
-                        back = x * cube[b][0] + y * cube[b][1] + z * cube[b][2] >= 0;
-                    else
-                        back = x * ks->dirs[3 * b] + y * ks->dirs[3 * b + 1] + z * ks->dirs[3 * b + 2] >= -1e-9;
+                    if (p.binning == DBTSDF_BIN_CUBE26) {
+                        const int dot = x * cube[b][0] + y * cube[b][1] + z * cube[b][2];
+                        const int s2 = cube[b][0] * cube[b][0] + cube[b][1] * cube[b][1] + cube[b][2] * cube[b][2];
+                        back = dot >= 0 && (!cone || (double)dot * (double)dot >= (double)(r2 * s2) * (cos_a * cos_a));
+                    } else {
+                        const double dot = x * ks->dirs[3 * b] + y * ks->dirs[3 * b + 1] + z * ks->dirs[3 * b + 2];
+                        back = cone ? dot >= sqrt((double)r2) * cos_a - 1e-9 : dot >= -1e-9;
+                    }
                     if (!back) continue;
                     ks->shadow[(size_t)b * K3 + ((size_t)(z + R) * K + (y + R)) * K + (x + R)] = 1;
                     ks->sh_off.push_back((uint32_t)(x + R) | ((uint32_t)(y + R) << 8) | ((uint32_t)(z + R) << 16));

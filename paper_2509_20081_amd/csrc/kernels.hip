@@ -652,7 +652,9 @@ __global__ __launch_bounds__(THREADS) void k_apply_brick(PipeArgs a) {
     for (uint32_t q = threadIdx.x; q < t.n_q; q += THREADS) lut[q] = t.mask_by_q[q];
     const int R = RR > 0 ? RR : t.R;
     const bool l1 = t.metric == DBTSDF_DIST_L1;
-    const bool cube = t.binning == DBTSDF_BIN_CUBE26;
+    // cube bins with the hemispherical shadow take it row by row from the
+    // integer test; every other shadow (AZEL bins, cones) from the bin's list
+    const bool cube = t.binning == DBTSDF_BIN_CUBE26 && t.shadow_model == DBTSDF_SHADOW_HEMISPHERE;
     const int r2 = t.shadow_r2;
     const uint32_t n_work = a.ctrl->n_work;
     const uint32_t w = threadIdx.x >> 6, l = lane();

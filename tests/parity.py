@@ -7,7 +7,7 @@ import numpy as np
 from oracle import brute
 from oracle.oracle import Oracle
 
-KW_KERNEL = ("kernel_size", "binning", "bins_az", "bins_el", "shadow_r2", "metric")
+KW_KERNEL = ("kernel_size", "binning", "bins_az", "bins_el", "shadow_r2", "metric", "shadow_model", "cone_deg")
 KW_GRID = ("hit_threshold", "hit_max", "dedup")
 
 

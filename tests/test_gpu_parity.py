@@ -54,6 +54,10 @@ TINY_CASES = [
     dict(seed=7, K=21, dims=(60, 60, 60), binning="cube26", shadow_r2=25, hit_threshold=2),
     dict(seed=8, K=37, dims=(80, 70, 75), binning="cube26", shadow_r2=36, hit_threshold=4),
     dict(seed=9, K=5, dims=(30, 30, 30), binning="cube26", shadow_r2=-1),
+    dict(seed=10, K=11, dims=(48, 48, 40), binning="cube26", shadow_r2=9, hit_threshold=2, shadow_model="cone",
+         cone_deg=35.0),
+    dict(seed=11, K=7, dims=(44, 40, 36), binning="azel", bins_az=8, bins_el=5, shadow_r2=9, shadow_model="cone",
+         cone_deg=50.0),
 ]
 
 TUNINGS = [

@@ -72,6 +72,23 @@ def test_kernel_tables_match_oracle(db, K, binning, r2, metric):
     assert np.allclose(d, od, rtol=0, atol=1e-15)
 
 
+@pytest.mark.parametrize("kw", [
+    dict(kernel_size=11, binning="cube26", shadow_r2=9, cone_deg=30.0),
+    dict(kernel_size=11, binning="cube26", shadow_r2=9, cone_deg=45.0),
+    dict(kernel_size=11, binning="cube26", shadow_r2=16, cone_deg=90.0),
+    dict(kernel_size=9, binning="azel", bins_az=8, bins_el=5, shadow_r2=9, cone_deg=25.0),
+    dict(kernel_size=21, binning="azel", shadow_r2=16, cone_deg=60.0),
+], ids=["cube30", "cube45", "cube90", "azel25", "azel40x40_60"])
+def test_cone_shadows_match_oracle(db, kw):
+    """The conical shadow sets of the library equal the oracle's, boundary cases (45 degrees) included."""
+    ks = db.KernelSet(shadow_model="cone", **kw)
+    _, s, _ = ks.export()
+    K = kw["kernel_size"]
+    o = Oracle(dims=(K, K, K), voxel_size=1.0, shadow_model="cone", **kw)
+    _, osh, _ = o.tables()
+    assert s.tobytes() == osh.tobytes()
+
+
 def test_host_bins_match_oracle(db):
     rng = np.random.default_rng(4)
     dirs = rng.normal(size=(3000, 3)).astype(np.float32)
@@ -89,6 +106,7 @@ def test_host_bins_match_oracle(db):
 @pytest.mark.parametrize("kw", [
     dict(kernel_size=4), dict(kernel_size=1), dict(kernel_size=39), dict(kernel_size=23, metric="l1"),
     dict(binning="azel", bins_az=41), dict(binning="azel", bins_az=0),
+    dict(shadow_model="cone", cone_deg=0.0), dict(shadow_model="cone", cone_deg=91.0),
 ])
 def test_kernel_set_validation(db, kw):
     with pytest.raises(db.DbtsdfError):
