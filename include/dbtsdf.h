@@ -267,6 +267,17 @@ dbtsdf_status dbtsdf_integrate_scan(dbtsdf_grid *g, const float pose[16], const 
                                     int points_on_device, dbtsdf_scan_stats *stats);
 
 /*
+ * dbtsdf_integrate_scan with the sequential downsampling of Sec. IV-B (DS =
+ * every): only returns 0, every, 2 every, ... of the n given are taken, in
+ * that order (so "first return" is among them), and the statistics count
+ * those (n_in = ceil(n / every)). every = 1 is dbtsdf_integrate_scan. Host
+ * points are staged whole. Errors as dbtsdf_integrate_scan; every = 0 is
+ * INVALID_ARG.
+ */
+dbtsdf_status dbtsdf_integrate_scan_every(dbtsdf_grid *g, const float pose[16], const float *points, uint64_t n,
+                                          uint32_t every, int points_on_device, dbtsdf_scan_stats *stats);
+
+/*
  * Wait for all work on the grid's stream, deliver pending statistics.
  * Errors: DEVICE (the grid becomes poisoned), POISONED.
  */

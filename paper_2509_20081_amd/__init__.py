@@ -198,13 +198,18 @@ class Grid:
         self._h = h
 
     # -- integration --------------------------------------------------------
-    def integrate(self, pose, points) -> Stats:
-        """Enqueue one scan; the returned Stats are filled at the next sync()."""
+    def integrate(self, pose, points, every: int = 1) -> Stats:
+        """Enqueue one scan (every > 1: only every `every`-th return, in order, the paper's sequential
+        downsampling); the returned Stats are filled at the next sync()."""
         pose = _f32(pose, (16,))
         ptr, n, on_dev, keep = _points_arg(points)
         st = Stats()
-        rc = L.lib().dbtsdf_integrate_scan(self._h, pose.ctypes.data_as(C.c_void_p), ptr, n, on_dev,
-                                           C.byref(st._c))
+        if every == 1:
+            rc = L.lib().dbtsdf_integrate_scan(self._h, pose.ctypes.data_as(C.c_void_p), ptr, n, on_dev,
+                                               C.byref(st._c))
+        else:
+            rc = L.lib().dbtsdf_integrate_scan_every(self._h, pose.ctypes.data_as(C.c_void_p), ptr, n, int(every),
+                                                     on_dev, C.byref(st._c))
         L.check(rc, "integrate_scan")
         self._pending.append((st, keep if on_dev else None))
         return st

@@ -80,6 +80,7 @@ SIGNATURES = {
     "dbtsdf_read_voxels": (C.c_int, [P, P, P, P, P]),
     "dbtsdf_read_distance": (C.c_int, [P, P, P, P]),
     "dbtsdf_write_voxels": (C.c_int, [P, P, P]),
+    "dbtsdf_integrate_scan_every": (C.c_int, [P, P, P, U64, U32, C.c_int, P]),
     "dbtsdf_extract_mesh": (C.c_int, [P, P, P, P, U64, C.POINTER(U64)]),
     "dbtsdf_destroy_grid": (None, [P]),
     "dbtsdf_set_profiling": (C.c_int, [P, C.c_int]),

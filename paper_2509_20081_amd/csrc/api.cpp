@@ -492,6 +492,7 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
         d.n = (uint32_t)s.n;
         d.grid = gidx[s.grid];
         d.dedup = (gp.flags & DBTSDF_DEDUP_FIRST) ? 1u : 0u;
+        d.step = s.step;
         std::memcpy(&hs[i], &d, sizeof(d));
         begin += (uint32_t)s.n;
         PendingStat p{s.stats, (uint32_t)i, -1, s.n, k3};
@@ -788,7 +789,13 @@ dbtsdf_status dbtsdf_set_tuning(dbtsdf_grid *g, const dbtsdf_tuning *t) {
 
 dbtsdf_status dbtsdf_integrate_scan(dbtsdf_grid *g, const float pose[16], const float *points, uint64_t n,
                                     int points_on_device, dbtsdf_scan_stats *stats) {
+    return dbtsdf_integrate_scan_every(g, pose, points, n, 1, points_on_device, stats);
+}
+
+dbtsdf_status dbtsdf_integrate_scan_every(dbtsdf_grid *g, const float pose[16], const float *points, uint64_t n,
+                                          uint32_t every, int points_on_device, dbtsdf_scan_stats *stats) {
     if (!g || !pose) return invalid("NULL argument");
+    if (every == 0) return invalid("every must be >= 1");
     if (g->poisoned) {
         set_error("grid is poisoned by an earlier device error");
         return DBTSDF_ERR_POISONED;
@@ -811,7 +818,7 @@ dbtsdf_status dbtsdf_integrate_scan(dbtsdf_grid *g, const float pose[16], const 
         if (e != hipSuccess) return check_hip(e, "staging host points", g);
         dev = g->ws->staging;
     }
-    std::vector<ScanIn> v{ScanIn{g, pose, dev, n, stats}};
+    std::vector<ScanIn> v{ScanIn{g, pose, dev, (n + every - 1) / every, stats, every}};
     return enqueue_scans(*g->ws, g->stream, v, false, true);
 }
 

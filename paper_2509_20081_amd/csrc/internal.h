@@ -103,11 +103,13 @@ struct DevScan {
     float trans[3];
     float origin[3];
     float inv_s;           // fl32(1 / voxel_size)
-    const float *pts;      // n x 3 fp32 on the device
+    const float *pts;      // the scan's points: point j is pts[3 j step .. 3 j step + 2], fp32, device
     uint32_t begin;        // offset of the scan's first point in the call
-    uint32_t n;
+    uint32_t n;            // points taken (every step-th of the array)
     uint32_t grid;         // index into DevGrid array
     uint32_t dedup;
+    uint32_t step;         // sequential downsampling: every step-th return of the array
+    uint32_t pad;
 };
 
 // Per-scan counters (u64) and per-grid traffic counters.

@@ -325,9 +325,10 @@ __global__ __launch_bounds__(kPtThreads) void k_front(PipeArgs a, const CallInfo
         const DevScan &sc = scans[s];
         const DevGrid &g = ONE ? g_one : grids[sc.grid];
         const uint32_t j = i - sc.begin;
-        const float px = sc.pts[3 * (size_t)j + 0];
-        const float py = sc.pts[3 * (size_t)j + 1];
-        const float pz = sc.pts[3 * (size_t)j + 2];
+        const float *pp = sc.pts + 3 * (size_t)j * sc.step;
+        const float px = pp[0];
+        const float py = pp[1];
+        const float pz = pp[2];
         int vx = 0, vy = 0, vz = 0, bin = 0;
         const uint32_t st = front_end(sc, g, a.tab, px, py, pz, vx, vy, vz, bin);
         uint32_t slot = kNoSlot;

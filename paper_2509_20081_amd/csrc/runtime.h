@@ -147,8 +147,9 @@ struct ScanIn {
     dbtsdf_grid *grid;
     const float *pose;     // 16 floats, host
     const float *points;   // device pointer (after staging)
-    uint64_t n;
+    uint64_t n;            // points taken
     dbtsdf_scan_stats *stats;
+    uint32_t step = 1;     // every step-th point of the array
 };
 
 // Validates and enqueues one call (plain or batched) on stream st using ws.

@@ -295,6 +295,27 @@ def test_profiling_period_mixes_call_forms(db, strategy):
     assert g.read_profile()["calls"] == 0
 
 
+@pytest.mark.parametrize("every", [2, 3, 7])
+@pytest.mark.parametrize("host", [False, True])
+def test_sequential_downsampling(db, every, host):
+    """DS = every (Sec. IV-B): the grid and statistics equal the oracle's on every `every`-th return."""
+    dims = (96, 96, 64)
+    origin = (-4.8, -4.8, -1.2)
+    o, g, _ = P.make_pair(dims, 0.1, origin, **synth.KERNEL_DEFAULTS)
+    m, p = o.new_grid()
+    pose, full = next(synth.config_scans(1, 0, [0]))
+    for k in range(2):
+        pts = full[: 9000 + 3037 * k]
+        ref = o.integrate(m, p, pose, np.ascontiguousarray(pts[::every]))
+        st = g.integrate(pose, pts if host else P.to_device(pts), every=every)
+        g.sync()
+        P.assert_stats_equal(st.as_dict(), ref, traffic=False, what=f"DS={every} scan {k}")
+    gm, gp = P.gpu_planes(g)
+    P.assert_grids_equal(gm, gp, m, p, what=f"DS={every}")
+    with pytest.raises(db.DbtsdfError):
+        g.integrate(pose, P.to_device(pts), every=0)
+
+
 def test_config2_full_grid_three_scans(db):
     """1024x1024x256 @ 0.05 m, 64x1024 scans along the trajectory: whole grid after 3 scans."""
     (o, g, _), gdef = _config_grid_pair(db, 2, count_traffic=True)
