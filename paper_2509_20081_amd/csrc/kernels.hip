@@ -1353,9 +1353,9 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const C
 // walks it up through the box in z: each step loads one new layer (two rows,
 // both planes: four coalesced loads per lane) and takes the x + 1 corners from
 // the next lane, so lanes 0-62 hold cubes and every voxel is read about twice.
-// A wavefront walks its run twice: first counting its triangles, then, with
-// the room of the whole run reserved by one atomic, writing them; the
-// triangles of a call therefore come out in no fixed order.
+// A wavefront walks each 64-step chunk of its run twice: counting, then, with
+// the chunk's room reserved by one atomic, writing the triangles of the steps
+// that have any; the triangles of a call therefore come out in no fixed order.
 constexpr int kMeshThreads = 256;
 constexpr uint32_t kMeshRun = 63;     // cubes per wavefront run (lane 63 only lends its corners)
 
@@ -1406,39 +1406,50 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh(MeshArgs m) {
             for (int c = 0; c < 8; ++c) cs |= (d[c] < 0 ? 1u : 0u) << c;
             return cs;
         };
-        // first walk: the run's triangles, so that one atomic reserves the
-        // room of the whole run (a counter per step would be one hot address)
-        uint32_t mine = 0;
-        {
-            int pa, pb;
-            layer(m.lo[2], pa, pb);
-            for (uint32_t kk = 0; kk < m.nc[2]; ++kk) {
-                int ca, cb, d[8];
-                layer(m.lo[2] + kk + 1, ca, cb);
-                const uint32_t cs = corners(pa, pb, ca, cb, d);
-                mine += has_cube ? tb(cs, 0) : 0u;
-                pa = ca;
-                pb = cb;
+        // The run goes up in chunks of 64 steps. A first walk counts the
+        // chunk's triangles and notes the steps where any lane has some;
+        // one atomic reserves the chunk's room (a counter bumped per step
+        // would be one hot address); a second walk writes the triangles,
+        // visiting only the noted steps.
+        for (uint32_t k0 = 0; k0 < m.nc[2]; k0 += 64u) {
+            const uint32_t kn = min(64u, m.nc[2] - k0);
+            uint32_t mine = 0;
+            unsigned long long steps = 0;   // wave-uniform: bit s = step k0 + s has triangles
+            {
+                int pa, pb;
+                layer(m.lo[2] + k0, pa, pb);
+                for (uint32_t s = 0; s < kn; ++s) {
+                    int ca, cb, d[8];
+                    layer(m.lo[2] + k0 + s + 1, ca, cb);
+                    const uint32_t cs = corners(pa, pb, ca, cb, d);
+                    const uint32_t n_t = has_cube ? tb(cs, 0) : 0u;
+                    mine += n_t;
+                    if (__ballot(n_t != 0u)) steps |= 1ull << s;
+                    pa = ca;
+                    pb = cb;
+                }
             }
-        }
-        const uint32_t incl = wave_incl_scan_u32(mine);
-        const uint32_t total = __shfl(incl, 63, 64);
-        if (total == 0u) continue;
-        unsigned long long first = 0;
-        if (l == 63u) first = atomicAdd(m.count, (unsigned long long)total);
-        first = __shfl(first, 63, 64);
-        if (!m.out) continue;   // counting only
-        unsigned long long slot = first + incl - mine;
-        // second walk: the triangles, each lane's in z order
-        int pa, pb;
-        layer(m.lo[2], pa, pb);
-        for (uint32_t kk = 0; kk < m.nc[2]; ++kk) {
-            const uint32_t k = m.lo[2] + kk;
+            const uint32_t incl = wave_incl_scan_u32(mine);
+            const uint32_t total = __shfl(incl, 63, 64);
+            if (total == 0u) continue;
+            unsigned long long first = 0;
+            if (l == 63u) first = atomicAdd(m.count, (unsigned long long)total);
+            first = __shfl(first, 63, 64);
+            if (!m.out) continue;   // counting only
+            unsigned long long slot = first + incl - mine;
+            uint32_t loaded = 0xFFFFFFFEu;   // step whose upper layer (pa, pb) holds (none yet)
+            int pa = 0, pb = 0;
+            while (steps) {
+            const uint32_t s = (uint32_t)__builtin_ctzll(steps);
+            steps &= steps - 1ull;
+            const uint32_t k = m.lo[2] + k0 + s;
+            if (loaded + 1u != s) layer(k, pa, pb);
             int ca, cb, d[8];
             layer(k + 1, ca, cb);
             const uint32_t cs = corners(pa, pb, ca, cb, d);
             pa = ca;
             pb = cb;
+            loaded = s;
             const uint32_t n_t = has_cube ? tb(cs, 0) : 0u;
             if (n_t == 0u) continue;
             // vertex of crossed edge e
@@ -1507,6 +1518,7 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh(MeshArgs m) {
                     }
                 }
                 pos += mm;
+            }
             }
         }
     }
