@@ -229,7 +229,11 @@ dbtsdf_status dbtsdf_create_grid(const dbtsdf_grid_params *params, const dbtsdf_
 /*
  * As dbtsdf_create_grid, on caller-owned device planes (each Nx*Ny*Nz uint32,
  * 16-byte aligned, e.g. torch tensors). The planes are filled with the initial
- * state; they must outlive the grid and are not freed by it.
+ * state; they must outlive the grid and are not freed by it. The caller may
+ * read them at any time but changes them only through this library (or
+ * follows its own writes with dbtsdf_write_voxels or dbtsdf_reset_grid): the
+ * per-point strategy relies on planes that integration alone has written
+ * (see dbtsdf_write_voxels).
  */
 dbtsdf_status dbtsdf_create_grid_on(const dbtsdf_grid_params *params, const dbtsdf_kernel_set *ks,
                                     void *hip_stream, void *mask_dev, void *packed_dev,
@@ -329,6 +333,12 @@ dbtsdf_status dbtsdf_extract_mesh(dbtsdf_grid *g, const uint32_t lo[3], const ui
  * planes that break the representation: a mask not of the form 2^n - 1, bits
  * 16-30 of packed set, a counter above hit_max, or a sign that disagrees with
  * the counter (sign 0 iff 1 <= T <= hit_max and h >= T). Synchronous.
+ * Integration relies on this: a return whose voxel an earlier call integrated
+ * (its mask reads 0) has its whole eq. 4 window at least as tight already,
+ * since that earlier return stamped the same masks, so the per-point strategy
+ * skips the window (the shadow counters are still updated). Written planes
+ * need not hold such windows, so after this call the grid integrates every
+ * window in full until dbtsdf_reset_grid.
  */
 dbtsdf_status dbtsdf_write_voxels(dbtsdf_grid *g, const uint32_t *mask_in, const uint32_t *packed_in);
 

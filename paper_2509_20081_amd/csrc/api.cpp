@@ -470,6 +470,7 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
         d.T = g->params.hit_threshold;
         d.hmax = g->params.hit_max;
         d.traffic_slot = (uint32_t)i;
+        d.revisit_skip = g->revisit_skip ? 1u : 0u;
         std::memcpy(&hg[i], &d, sizeof(d));
     }
     DevScan *hs = (DevScan *)(h + scans_off);
@@ -743,7 +744,9 @@ dbtsdf_status dbtsdf_grid_planes(const dbtsdf_grid *g, void **mask_dev, void **p
 dbtsdf_status dbtsdf_reset_grid(dbtsdf_grid *g) {
     if (!g) return invalid("NULL grid");
     if (g->poisoned) return DBTSDF_ERR_POISONED;
-    return check_hip(launch_grid_init(g->mask, g->packed, g->n_voxels, g->stream), "resetting the grid", g);
+    const dbtsdf_status s = check_hip(launch_grid_init(g->mask, g->packed, g->n_voxels, g->stream), "resetting the grid", g);
+    if (s == DBTSDF_OK) g->revisit_skip = true;
+    return s;
 }
 
 dbtsdf_status dbtsdf_get_tuning(const dbtsdf_grid *g, dbtsdf_tuning *out) {
@@ -942,6 +945,7 @@ dbtsdf_status dbtsdf_write_voxels(dbtsdf_grid *g, const uint32_t *mask_in, const
         if (occupied != (can_flip && h >= T)) return invalid("sign disagrees with the hit counter");
     }
     hipError_t e = hipStreamSynchronize(g->stream);
+    g->revisit_skip = false;  // written planes need not hold whole windows around integrated voxels
     if (e == hipSuccess) e = hipMemcpy(g->mask, mask_in, g->n_voxels * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(g->packed, packed_in, g->n_voxels * 4, hipMemcpyHostToDevice);
     return check_hip(e, "writing voxels", g);

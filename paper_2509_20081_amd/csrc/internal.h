@@ -25,6 +25,11 @@ constexpr uint32_t kMaxAtomicGrids = 1u << 16;  // per-point strategy: grid inde
 // bit 30 set by the select pass on returns that are integrated
 constexpr uint32_t kStOk = 0, kStInvalid = 1, kStOob = 2;
 constexpr uint32_t kRecSurvivor = 1u << 30;
+// survivor record word (per-point strategy): bin in bits 0-15 (bits 0-14 and
+// the revisit flag in bit 15 when the row kernel runs: at most 31 bins), grid
+// index in bits 16-31
+constexpr uint32_t kRecRevisit = 1u << 15;
+constexpr uint32_t kRowBinMask = kRecRevisit - 1u;
 
 // ------------------------------------------------------- host kernel set ---
 struct KernelSet {
@@ -95,7 +100,7 @@ struct DevGrid {
     uint32_t nbx, nby, nbz;
     uint32_t T, hmax;
     uint32_t traffic_slot; // index into traffic counters
-    uint32_t pad;
+    uint32_t revisit_skip; // the planes hold only what integration wrote (see k_select_atomic)
 };
 
 struct DevScan {

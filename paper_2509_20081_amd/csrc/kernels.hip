@@ -964,6 +964,20 @@ __global__ __launch_bounds__(kSelThreads) void k_select_atomic(PipeArgs a, const
             }
             if (surv) a.rec[i].w = r.w | kRecSurvivor;
         }
+        // A return whose voxel an earlier call integrated needs no eq. 4
+        // window: that return stamped the same masks over the same window
+        // (the masks depend on the offset only), and AND only lowers them. Its
+        // voxel reads mask 0 (n = 0 only at distance 0; dedup keeps one
+        // return per voxel in a scan, so this call has not written it). The
+        // row kernel then skips the window loads (bit 15 of the record word).
+        uint32_t revisit = 0u;
+        if (surv && a.row_kernel) {
+            const DevGrid &g = a.grids[a.scans[s].grid];
+            if (g.revisit_skip) {
+                const size_t v = (size_t)r.x + (size_t)g.nx * ((size_t)r.y + (size_t)g.ny * (size_t)r.z);
+                revisit = g.mask[v] == 0u ? kRecRevisit : 0u;
+            }
+        }
         uint32_t c[SC_N];
         c[SC_INVALID] = st == kStInvalid;
         c[SC_OOB] = st == kStOob;
@@ -996,7 +1010,9 @@ __global__ __launch_bounds__(kSelThreads) void k_select_atomic(PipeArgs a, const
             __syncthreads();
             // the record word carries the bin (bits 0-15) and the grid (bits
             // 16-31; calls of more grids take the brick strategy)
-            if (surv) a.surv_rec[s_base + pos] = make_uint4(r.x, r.y, r.z, (r.w & 0xFFFFu) | (a.scans[s].grid << 16));
+            if (surv)
+                a.surv_rec[s_base + pos] =
+                    make_uint4(r.x, r.y, r.z, (r.w & 0xFFFFu) | revisit | (a.scans[s].grid << 16));
         }
         __syncthreads();  // s_red and s_base are reused by the next round
     }
@@ -1240,7 +1256,8 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const C
             pbase[p] = reinterpret_cast<const char __attribute__((address_space(1))) *>(
                 glob(g[p].packed) + row0 + (size_t)(r[p].x - (uint32_t)R));
             sel[p] = 4u * qd + 3u - ((r[p].x - (uint32_t)R) & 3u);
-            const bool qon = live[p] && x0 + 4u * qd <= r[p].x + (uint32_t)R;
+            // a return in a voxel integrated by an earlier call skips its window
+            const bool qon = live[p] && !(r[p].w & kRecRevisit) && x0 + 4u * qd <= r[p].x + (uint32_t)R;
             const uint32_t sy = 4u * g[p].nx, sz = 4u * g[p].nx * g[p].ny;  // row strides in bytes
 #pragma unroll
             for (int k = 0; k < kQuadIters; ++k) {
@@ -1257,7 +1274,7 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const C
         bool son[NP][kShadowIters];
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-            const uint32_t bin = r[p].w & 0xFFFFu;
+            const uint32_t bin = r[p].w & kRowBinMask;
             const uint32_t s0 = sh_rng[bin], s1 = live[p] ? sh_rng[bin + 1] : s0;
 #pragma unroll
             for (int k = 0; k < kShadowIters; ++k) {
@@ -1275,7 +1292,7 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const C
                     bool in = rx >= -3 && rx <= 3 && ry >= -3 && ry <= 3 && rz >= -3 && rz <= 3;
                     if (in) {
                         const uint32_t idx = (uint32_t)((rx + 3) + 7 * (ry + 3) + 49 * (rz + 3));
-                        in = ((sh_bits[(r[q].w & 0xFFFFu) * kShadowSetWords + idx / 32u] >> (idx % 32u)) & 1u) != 0u;
+                        in = ((sh_bits[(r[q].w & kRowBinMask) * kShadowSetWords + idx / 32u] >> (idx % 32u)) & 1u) != 0u;
                     }
                     if (q < p) son[p][k] = son[p][k] && !in;
                     else c += in ? 1u : 0u;

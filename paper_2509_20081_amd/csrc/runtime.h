@@ -122,6 +122,10 @@ struct dbtsdf_grid {
     uint32_t brick_dims[3] = {0, 0, 0};
     std::unique_ptr<dbtsdf::Workspace> ws;
     hipEvent_t ev = nullptr;
+    // the planes were changed only by integration since creation or the last
+    // reset (a return in a voxel integrated by an earlier call can then skip
+    // its eq. 4 window); dbtsdf_write_voxels clears it
+    bool revisit_skip = true;
     // mesh export: the case table on the device and the triangle counter
     uint32_t *mesh_table = nullptr;
     unsigned long long *mesh_count = nullptr;

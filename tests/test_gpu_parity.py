@@ -542,6 +542,37 @@ def test_readout_and_restore(db):
         g.read_voxels((0, 0, 0), (41, 1, 1))
 
 
+def test_written_planes_integrate_every_window(db):
+    """Planes written with zero masks at voxels whose windows were never stamped (not a state integration
+    makes): returns landing there still get their whole eq. 4 window, as in the oracle; after a reset the
+    grid integrates normally again."""
+    dims = (48, 48, 40)
+    o, g, _ = P.make_pair(dims, 1.0, (0.0, 0.0, 0.0), **synth.KERNEL_DEFAULTS)
+    g.set_tuning(strategy="atomic")
+    rng = np.random.default_rng(17)
+    pose = synth.random_pose(rng, np.array([20.0, 20.0, 16.0]), np.array([28.0, 28.0, 24.0]))
+    pts = synth.random_cloud(rng, 600, -np.full(3, 12.0), np.full(3, 12.0))
+    vox, _, st = o.front_end(pose, pts)
+    m, p = o.new_grid()
+    ok = vox[st == 0]
+    m[ok[:, 2], ok[:, 1], ok[:, 0]] = 0          # "integrated" centres without their windows
+    g.write_voxels(m, p)
+    ref = o.integrate(m, p, pose, pts)
+    assert ref["n_integrated"] > 100
+    g.integrate(pose, P.to_device(pts))
+    g.sync()
+    gm, gp = P.gpu_planes(g)
+    P.assert_grids_equal(gm, gp, m, p, what="after writing planes")
+    g.reset()
+    m, p = o.new_grid()
+    for k in range(2):
+        o.integrate(m, p, pose, pts)
+        g.integrate(pose, P.to_device(pts))
+    g.sync()
+    gm, gp = P.gpu_planes(g)
+    P.assert_grids_equal(gm, gp, m, p, what="after reset, twice")
+
+
 def test_argument_errors_leave_grid_unchanged(db):
     dims = (24, 24, 24)
     o, g, ks = P.make_pair(dims, 1.0, (0, 0, 0), kernel_size=5)
