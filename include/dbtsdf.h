@@ -262,9 +262,10 @@ dbtsdf_status dbtsdf_set_tuning(dbtsdf_grid *g, const dbtsdf_tuning *t);
  *            dbtsdf_sync() (it must stay valid until then).
  * Non-finite and zero-range points are not errors: they are counted.
  * Front end arithmetic is fp32, one IEEE operation per step, no contraction.
- * The passes of a call are replayed from a HIP graph captured (on a private
- * stream of the grid) the first time a call of that shape is made, and
- * launched on the grid's stream.
+ * The passes of a call are launched on the grid's stream: directly with the
+ * per-point strategy (three passes), or, with the brick strategy, replayed
+ * from a HIP graph captured (on a private stream of the grid) the first time
+ * a call of that shape is made.
  * Errors: INVALID_ARG, OUT_OF_RANGE (n too large), OUT_OF_MEMORY, DEVICE, POISONED.
  */
 dbtsdf_status dbtsdf_integrate_scan(dbtsdf_grid *g, const float pose[16], const float *points, uint64_t n,

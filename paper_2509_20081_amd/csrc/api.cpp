@@ -545,10 +545,12 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
     a.single_scan = plain && live.size() == 1 && scans_off % 16 == 0 ? 1u : 0u;
     a.row_kernel = row_kernel ? 1u : 0u;
 
-    // plain calls, and batches that ask for it, replay captured graphs (one
-    // host call instead of one per pass); with profiling on, events bracket
-    // the call and its apply kernel
-    const bool graphs = plain || use_graph;
+    // batches that ask for it, and plain brick-strategy calls (nine passes),
+    // replay captured graphs (one host call instead of one per pass); plain
+    // per-point calls launch their three passes directly, which measured
+    // faster than a graph launch; with profiling on, events bracket the call
+    // and its apply kernel
+    const bool graphs = use_graph || (plain && tun.strategy != DBTSDF_STRATEGY_ATOMIC);
     slot.prof = 0;
     auto run_part = [&](int part) -> hipError_t {
         if (!graphs) return launch_pipeline(a, tun, ws.points_cap, st, part);

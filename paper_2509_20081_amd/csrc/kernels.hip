@@ -1,8 +1,8 @@
 // gfx950 kernels of DB-TSDF scan integration (Sec. III-C of the paper).
 //
 // One call integrates a set of scans (one for the plain entry point, many for
-// the batched one) through this pass sequence on one stream, replayed from a
-// captured graph:
+// the batched one) through this pass sequence on one stream (launched
+// directly, or replayed from a captured graph):
 //
 //   k_upload   the call's descriptors from its pinned host ring slot
 //   k_reset    zero the per-call counters

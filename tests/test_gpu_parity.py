@@ -213,9 +213,10 @@ def test_paper_kernel_set_config1(db, tuning):
 
 
 @pytest.mark.parametrize("strategy", ["atomic", "brick"])
-def test_plain_graph_replays_over_the_ring(db, strategy):
-    """20 plain calls into one grid (more than the 16 ring slots, so every slot's captured graph is
-    replayed again), eager work between calls: statistics and grid checked after every call."""
+def test_plain_calls_over_the_ring(db, strategy):
+    """20 plain calls into one grid (more than the 16 ring slots, so every slot's descriptors, and with the
+    brick strategy its captured graph, are used again), eager work between calls: statistics and grid
+    checked after every call."""
     import torch
     dims = (64, 64, 48)
     o, g, _ = P.make_pair(dims, 0.1, (0.0, 0.0, 0.0), **synth.KERNEL_DEFAULTS)
