@@ -246,3 +246,25 @@ def canonical(tris: np.ndarray) -> np.ndarray:
     rows = np.take_along_axis(t, idx[:, :, None], axis=1).reshape(-1, 9)
     order = np.lexsort(rows.view(np.uint32).T[::-1])
     return rows[order]
+
+
+def occupied_points(mask, packed, origin, voxel_size, lo=None, hi=None) -> np.ndarray:
+    """The map exported as a point cloud (the CSV/PCL export beside the mesh in
+    the paper's pipeline figure): the centres of the occupied contact voxels,
+    those a return landed in (mask 0) whose hit counter confirmed them (sign
+    0), in the box [lo, hi), x fastest, as (n, 3) fp32 with the coordinate
+    rule of M2. (The paper does not say which voxels the point export holds;
+    this is the reading.)"""
+    m = np.asarray(mask, np.uint32)
+    p = np.asarray(packed, np.uint32)
+    nz, ny, nx = m.shape
+    lo = (0, 0, 0) if lo is None else tuple(int(v) for v in lo)
+    hi = (nx, ny, nz) if hi is None else tuple(int(v) for v in hi)
+    sub = (m[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] == 0) & ((p[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] >> np.uint32(31)) == 0)
+    kz, ky, kx = np.nonzero(sub)
+    out = np.empty((len(kx), 3), np.float32)
+    for col, (k, base) in enumerate(((kx, lo[0]), (ky, lo[1]), (kz, lo[2]))):
+        u = (k + base).astype(np.float32)
+        out[:, col] = np.float32(origin[col]) + (u + np.float32(0.5)) * np.float32(voxel_size)
+    return out
+

@@ -159,3 +159,43 @@ def test_box_restricts_cubes():
     both = mesh.canonical(np.concatenate(parts))
     assert np.array_equal(full.view(np.uint32), both.view(np.uint32))
     assert len(mesh.extract_mesh(m, p, (0.0, 0.0, 0.0), 0.5, lo=(2, 2, 2), hi=(3, 8, 7))) == 0
+
+
+def test_point_export_of_the_hand_worked_scan(golden_dir):
+    """The hand-worked single return (T = 1): only its contact voxel has mask 0, and its shadow count
+    reached T, so the point export is that voxel's centre alone."""
+    import json
+    import os
+    from oracle.oracle import Oracle
+    gold = json.load(open(os.path.join(golden_dir, "hand_worked_scan.json")))
+    kw = {k: v for k, v in gold["kernel"].items()}
+    o = Oracle(dims=gold["grid"]["dims"], voxel_size=gold["grid"]["voxel_size"], origin=gold["grid"]["origin"], **kw)
+    m, p = o.new_grid()
+    pose = np.eye(4, dtype=np.float32)
+    pose[:3, 3] = gold["pose_translation"]
+    o.integrate(m, p, pose, np.array([gold["point"]], np.float32))
+    pts = mesh.occupied_points(m, p, gold["grid"]["origin"], gold["grid"]["voxel_size"])
+    v = gold["expect"]["voxel"]
+    assert pts.tolist() == [[v[0] + 0.5, v[1] + 0.5, v[2] + 0.5]]
+    # a hit below the threshold is not yet occupied
+    o2 = Oracle(dims=gold["grid"]["dims"], voxel_size=1.0, **dict(kw, hit_threshold=2))
+    m2, p2 = o2.new_grid()
+    o2.integrate(m2, p2, pose, np.array([gold["point"]], np.float32))
+    assert len(mesh.occupied_points(m2, p2, (0.0, 0.0, 0.0), 1.0)) == 0
+    o2.integrate(m2, p2, pose, np.array([gold["point"]], np.float32))
+    assert len(mesh.occupied_points(m2, p2, (0.0, 0.0, 0.0), 1.0)) == 1
+
+
+def test_point_export_coordinates_and_box():
+    m = np.full((3, 4, 5), 0xFFFFFFFF, np.uint32)
+    p = np.full((3, 4, 5), 0x80000000, np.uint32)
+    m[2, 1, 3], p[2, 1, 3] = 0, 5          # occupied contact voxel
+    m[0, 0, 0], p[0, 0, 0] = 0, 0x80000001  # hit once, still free
+    m[1, 3, 4], p[1, 3, 4] = 1, 5          # confirmed but not a contact voxel
+    pts = mesh.occupied_points(m, p, (1.0, -2.0, 0.5), 0.1)
+    want = [np.float32(np.float32(1.0) + np.float32(3.5) * np.float32(0.1)),
+            np.float32(np.float32(-2.0) + np.float32(1.5) * np.float32(0.1)),
+            np.float32(np.float32(0.5) + np.float32(2.5) * np.float32(0.1))]
+    assert pts.shape == (1, 3) and pts[0].tolist() == [float(w) for w in want]
+    assert len(mesh.occupied_points(m, p, (0.0, 0.0, 0.0), 1.0, lo=(0, 0, 0), hi=(3, 4, 3))) == 0
+
