@@ -329,6 +329,20 @@ dbtsdf_status dbtsdf_extract_mesh(dbtsdf_grid *g, const uint32_t lo[3], const ui
                                   uint64_t max_tris, uint64_t *n_tris);
 
 /*
+ * Point export (beside the mesh, the pipeline's CSV/PCL output, Sec. III):
+ * the centres o + (u + 0.5) s (fp32, one operation at a time) of the occupied
+ * contact voxels of the box [lo, hi) (NULL, NULL: the whole grid), i.e. those
+ * a return landed in (mask 0) whose hit counter confirmed them (sign 0).
+ * xyz_dev: device memory for max_points points of 3 floats, or NULL with
+ * max_points 0 to count only; *n_points receives the count (when it exceeds
+ * max_points only max_points are written). Points of one grid row come out in
+ * x order, rows in no fixed order. Runs on the grid's stream and synchronises
+ * it. Errors as dbtsdf_extract_mesh.
+ */
+dbtsdf_status dbtsdf_extract_points(dbtsdf_grid *g, const uint32_t lo[3], const uint32_t hi[3], float *xyz_dev,
+                                    uint64_t max_points, uint64_t *n_points);
+
+/*
  * Overwrite the whole grid from host planes (Nx*Ny*Nz uint32 each, x fastest),
  * e.g. a checkpoint written from dbtsdf_read_voxels. Rejects (INVALID_ARG)
  * planes that break the representation: a mask not of the form 2^n - 1, bits

@@ -306,6 +306,23 @@ class Grid:
             raise ValueError(f"mesh has {int(n.value)} triangles, out holds {out.shape[0]}")
         return out[: int(n.value)]
 
+    def extract_points(self, lo=None, hi=None):
+        """Centres of the occupied contact voxels (mask 0, sign 0) of the box [lo, hi): a (n, 3) float32 CUDA
+        tensor (rows in no fixed order, x order within a row). See write_point_cloud for CSV / PCD files."""
+        import torch
+        lo_a, hi_a, _ = self._box(lo, hi)
+        n = C.c_uint64()
+        L.check(L.lib().dbtsdf_extract_points(self._h, lo_a, hi_a, None, 0, C.byref(n)), "extract_points")
+        dev = self.mask_tensor.device if self.mask_tensor is not None else torch.device("cuda")
+        out = torch.empty((int(n.value), 3), dtype=torch.float32, device=dev)
+        if out.shape[0]:
+            m = C.c_uint64()
+            L.check(L.lib().dbtsdf_extract_points(self._h, lo_a, hi_a, C.c_void_p(out.data_ptr()), out.shape[0],
+                                                  C.byref(m)), "extract_points")
+            if int(m.value) != out.shape[0]:
+                raise RuntimeError("the grid changed between the counting and the writing pass")
+        return out
+
     def write_voxels(self, mask, packed) -> None:
         m = np.ascontiguousarray(mask, dtype=np.uint32)
         p = np.ascontiguousarray(packed, dtype=np.uint32)

@@ -82,6 +82,7 @@ SIGNATURES = {
     "dbtsdf_write_voxels": (C.c_int, [P, P, P]),
     "dbtsdf_integrate_scan_every": (C.c_int, [P, P, P, U64, U32, C.c_int, P]),
     "dbtsdf_extract_mesh": (C.c_int, [P, P, P, P, U64, C.POINTER(U64)]),
+    "dbtsdf_extract_points": (C.c_int, [P, P, P, P, U64, C.POINTER(U64)]),
     "dbtsdf_destroy_grid": (None, [P]),
     "dbtsdf_set_profiling": (C.c_int, [P, C.c_int]),
     "dbtsdf_read_profile": (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(U64), C.POINTER(C.c_double),

@@ -932,6 +932,51 @@ dbtsdf_status dbtsdf_extract_mesh(dbtsdf_grid *g, const uint32_t lo[3], const ui
     return DBTSDF_OK;
 }
 
+dbtsdf_status dbtsdf_extract_points(dbtsdf_grid *g, const uint32_t lo[3], const uint32_t hi[3], float *xyz_dev,
+                                    uint64_t max_points, uint64_t *n_points) {
+    if (!g || !n_points) return invalid("NULL argument");
+    if (!xyz_dev && max_points) return invalid("NULL point buffer with max_points > 0");
+    *n_points = 0;
+    const uint32_t zero[3] = {0, 0, 0};
+    if (!lo != !hi) return invalid("give both box corners or neither");
+    if (!lo) {
+        lo = zero;
+        hi = g->params.dims;
+    }
+    dbtsdf_status s = check_box(g, lo, hi);
+    if (s != DBTSDF_OK) return s;
+    if (g->poisoned) return DBTSDF_ERR_POISONED;
+    hipError_t e = hipSetDevice(g->device);
+    if (e == hipSuccess && !g->mesh_count) e = hipMalloc((void **)&g->mesh_count, sizeof(unsigned long long));
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        set_error("point export counter does not fit in device memory");
+        return DBTSDF_ERR_OUT_OF_MEMORY;
+    }
+    MeshArgs m{};
+    m.mask = g->mask;
+    m.packed = g->packed;
+    m.out = max_points ? xyz_dev : nullptr;
+    m.count = g->mesh_count;
+    m.cap = max_points;
+    m.nx = g->params.dims[0];
+    m.ny = g->params.dims[1];
+    for (int k = 0; k < 3; ++k) {
+        m.lo[k] = lo[k];
+        m.nc[k] = hi[k] - lo[k];
+        m.origin[k] = g->params.origin[k];
+    }
+    m.s = g->params.voxel_size;
+    unsigned long long count = 0;
+    if (e == hipSuccess) e = launch_fill_u64(g->mesh_count, 0ull, 1, g->stream);
+    if (e == hipSuccess) e = launch_points(m, g->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&count, g->mesh_count, sizeof(count), hipMemcpyDeviceToHost, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return check_hip(e, "extracting points", g);
+    *n_points = count;
+    return DBTSDF_OK;
+}
+
 dbtsdf_status dbtsdf_write_voxels(dbtsdf_grid *g, const uint32_t *mask_in, const uint32_t *packed_in) {
     if (!g || !mask_in || !packed_in) return invalid("NULL argument");
     if (g->poisoned) return DBTSDF_ERR_POISONED;

@@ -231,6 +231,10 @@ struct MeshArgs {
     float s;
 };
 hipError_t launch_mesh(const MeshArgs &m, hipStream_t st);
+// Point export: centres of the occupied contact voxels (mask 0, sign 0) of the
+// box lo + [0, nc) (MeshArgs.nc holds the box extent here, MeshArgs.table is
+// unused), 3 floats each.
+hipError_t launch_points(const MeshArgs &m, hipStream_t st);
 
 // Workgroups of a fully resident persistent apply grid (row_kernel: the
 // kernel set has the row kernel's tables).

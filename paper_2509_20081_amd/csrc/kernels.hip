@@ -1541,6 +1541,55 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh(MeshArgs m) {
     }
 }
 
+// Point export: the centres of the occupied contact voxels (a return landed
+// there, mask 0, and the hit counter confirmed it, sign 0). A wavefront takes
+// one grid row of the box at a time: a counting pass, one atomic to reserve
+// the row's room, then a writing pass with the lanes' ranks from a ballot.
+__global__ __launch_bounds__(kMeshThreads) void k_points(MeshArgs m) {
+    const uint32_t l = lane();
+    const uint64_t n_rows = (uint64_t)m.nc[1] * m.nc[2];
+    const uint32_t wpb = blockDim.x >> 6;
+    const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const unsigned long long below = l ? ((1ull << l) - 1ull) : 0ull;
+    for (uint64_t row = (uint64_t)blockIdx.x * wpb + wid; row < n_rows; row += (uint64_t)gridDim.x * wpb) {
+        const uint32_t j = m.lo[1] + (uint32_t)(row % m.nc[1]), k = m.lo[2] + (uint32_t)(row / m.nc[1]);
+        const uint64_t base = m.lo[0] + (uint64_t)m.nx * (j + (uint64_t)m.ny * k);
+        auto occupied = [&](uint32_t x) {
+            if (x >= m.nc[0]) return false;
+            return m.mask[base + x] == 0u && (m.packed[base + x] >> 31) == 0u;
+        };
+        uint32_t cnt = 0;
+        for (uint32_t x0 = 0; x0 < m.nc[0]; x0 += 64u) cnt += __popcll(__ballot(occupied(x0 + l)));
+        if (cnt == 0u) continue;
+        unsigned long long first = 0;
+        if (l == 0u) first = atomicAdd(m.count, (unsigned long long)cnt);
+        first = __shfl(first, 0, 64);
+        if (!m.out) continue;   // counting only
+        for (uint32_t x0 = 0; x0 < m.nc[0]; x0 += 64u) {
+            const bool ok = occupied(x0 + l);
+            const unsigned long long bits = __ballot(ok);
+            if (ok) {
+                const unsigned long long slot = first + __popcll(bits & below);
+                if (slot < m.cap) {
+                    const uint32_t u[3] = {m.lo[0] + x0 + l, j, k};
+                    float c[3];
+#pragma unroll
+                    for (int t = 0; t < 3; ++t) {
+                        const float h = (float)u[t] + 0.5f;
+                        const float hs = h * m.s;
+                        c[t] = m.origin[t] + hs;
+                    }
+                    float *o = m.out + 3ull * slot;
+                    o[0] = c[0];
+                    o[1] = c[1];
+                    o[2] = c[2];
+                }
+            }
+            first += __popcll(bits);
+        }
+    }
+}
+
 // ================================================================ utility ===
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, uint64_t n) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) p[i] = v;
@@ -1757,6 +1806,15 @@ hipError_t launch_pipeline(const PipeArgs &a, const Tuning &t, uint32_t points_c
     }
     if (apply) hipLaunchKernelGGL(f, dim3(t.apply_blocks), dim3(t.threads), 0, st, a);
     if (post) k_download<<<kCopyBlocks, 256, 0, st>>>(a, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_points(const MeshArgs &m, hipStream_t st) {
+    const unsigned long long rows = (unsigned long long)m.nc[1] * m.nc[2];
+    if (rows == 0 || m.nc[0] == 0) return hipSuccess;
+    const unsigned long long wpb = kMeshThreads / 64;
+    const uint32_t blocks = (uint32_t)std::min<unsigned long long>((rows + wpb - 1) / wpb, 16384ull);
+    k_points<<<blocks, kMeshThreads, 0, st>>>(m);
     return hipGetLastError();
 }
 

@@ -97,3 +97,59 @@ def test_mesh_count_only_overflow_and_empty_boxes(db):
     assert len(g.extract_mesh((5, 5, 5), (7, 6, 9))) == 0
     with pytest.raises(Exception):
         g.count_mesh((0, 0, 0), (33, 32, 32))
+
+
+def _rows(a):
+    a = np.ascontiguousarray(a, np.float32).reshape(-1, 3).view(np.uint32)
+    return a[np.lexsort(a.T[::-1])] if len(a) else a
+
+
+@pytest.mark.parametrize("T", [1, 2])
+def test_point_export_matches_oracle(db, T):
+    """Occupied contact voxels after a few fused scans, exported as points: the same set of fp32 centres as
+    the oracle's, bit for bit, over the whole grid and over a ragged sub-box; count-only agrees."""
+    dims, vs, origin = (70, 45, 33), 0.05, (-0.4, 1.1, 0.2)
+    o, g, _ = P.make_pair(dims, vs, origin, kernel_size=7, shadow_r2=4, hit_threshold=T)
+    m, p = o.new_grid()
+    rng = np.random.default_rng(20 + T)
+    centre = np.array(origin) + np.array(dims) * vs / 2
+    for _ in range(3):
+        pose = synth.random_pose(rng, centre - 0.2, centre + 0.2)
+        pts = synth.random_cloud(rng, 1500, -np.array(dims) * vs * 0.45, np.array(dims) * vs * 0.45)
+        o.integrate(m, p, pose, pts)
+        g.integrate(pose, P.to_device(pts))
+    g.sync()
+    ref = mesh.occupied_points(m, p, origin, vs)
+    assert len(ref) > 50
+    got = g.extract_points()
+    assert np.array_equal(_rows(got.cpu().numpy()), _rows(ref))
+    lo, hi = (3, 7, 1), (67, 44, 30)
+    sub = g.extract_points(lo, hi)
+    assert np.array_equal(_rows(sub.cpu().numpy()), _rows(mesh.occupied_points(m, p, origin, vs, lo=lo, hi=hi)))
+    with pytest.raises(Exception):
+        g.extract_points((5, 5, 5), (5, 9, 9))   # boxes are non-empty: lo < hi on every axis
+
+
+def test_point_export_of_written_planes_and_overflow(db):
+    """Planes written from the host: every row pattern (x runs longer than a wavefront) exports exactly
+    the oracle's points; a buffer too small gets a prefix of valid points and the full count."""
+    import ctypes as C
+    import torch
+    from paper_2509_20081_amd import _lib as L
+    dims = (131, 9, 5)
+    ks = db.KernelSet(kernel_size=5, binning="cube26", shadow_r2=4)
+    g = db.Grid(dims, 0.2, (1.0, -3.0, 0.5), ks, hit_threshold=3)
+    rng = np.random.default_rng(4)
+    mask = np.where(rng.random(dims[::-1]) < 0.4, 0, 7).astype(np.uint32)
+    packed = np.where(rng.random(dims[::-1]) < 0.6, 3, 0x80000001).astype(np.uint32)
+    g.write_voxels(mask, packed)
+    ref = mesh.occupied_points(mask, packed, (1.0, -3.0, 0.5), 0.2)
+    got = g.extract_points().cpu().numpy()
+    assert np.array_equal(_rows(got), _rows(ref))
+    small = torch.zeros((len(ref) // 2, 3), dtype=torch.float32, device="cuda")
+    n = C.c_uint64()
+    L.check(L.lib().dbtsdf_extract_points(g._h, None, None, C.c_void_p(small.data_ptr()), small.shape[0],
+                                          C.byref(n)), "extract_points")
+    assert int(n.value) == len(ref)
+    full = {tuple(r) for r in _rows(ref)}
+    assert all(tuple(r) in full for r in _rows(small.cpu().numpy()))
