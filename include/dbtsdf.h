@@ -147,7 +147,10 @@ typedef struct {
 typedef enum {
     DBTSDF_STRATEGY_AUTO = 0,   /* the default: DBTSDF_STRATEGY_ATOMIC (dbtsdf_autotune measures instead) */
     DBTSDF_STRATEGY_BRICK = 1,  /* returns bucketed by grid brick; one workgroup owns a brick in LDS */
-    DBTSDF_STRATEGY_ATOMIC = 2  /* one wavefront per return; 32-bit global atomics */
+    DBTSDF_STRATEGY_ATOMIC = 2, /* one wavefront per return; 32-bit global atomics */
+    DBTSDF_STRATEGY_SORT = 3    /* every change a return makes to a word becomes a (voxel key, contribution)
+                                   pair; the pairs are radix-sorted by key and a wavefront segmented reduction
+                                   applies eq. 4 and eqs. 5-6 once per voxel, with no atomics on the planes */
 } dbtsdf_strategy;
 
 /*
@@ -160,7 +163,13 @@ typedef enum {
  * chunk = most listed points one apply work unit takes from a brick; bricks
  * with more are split over several work units that merge with atomics
  * (0 = default 64, 0xFFFFFFFF = never split). With DBTSDF_STRATEGY_ATOMIC the
- * brick is ignored. Any valid tuning gives bit-identical grids. A new grid
+ * brick is ignored. DBTSDF_STRATEGY_SORT ignores the brick, takes chunk as the
+ * most returns per round (0 or 0xFFFFFFFF: as many as its buffers allow), reads
+ * the survivor and pair counts back in the middle of each call (so its calls
+ * return once the pairs are sorted, and it never replays graphs), holds up to
+ * 2^28 pairs of 12 bytes twice over in device memory (allocated on first use,
+ * grown as calls need) and takes larger calls in several rounds of returns.
+ * Any valid tuning gives bit-identical grids. A new grid
  * starts with DBTSDF_STRATEGY_ATOMIC, brick 32x8x8, 256 threads, chunk 64.
  * A call that counts traffic (DBTSDF_COUNT_TRAFFIC) or spans more than 65536
  * grids runs with DBTSDF_STRATEGY_BRICK whatever the tuning says.

@@ -56,6 +56,8 @@ static hipError_t upload(DeviceTables &d, const std::vector<T> &v, const T **out
 static dbtsdf_status make_device_tables(const KernelSet &ks, std::shared_ptr<DeviceTables> &out) {
     auto d = std::make_shared<DeviceTables>();
     d->params = ks.p;
+    for (size_t b = 0; b + 1 < ks.sh_start.size(); ++b)
+        d->max_shadow = std::max(d->max_shadow, ks.sh_start[b + 1] - ks.sh_start[b]);
     DevTables &t = d->t;
     hipError_t e = upload(*d, ks.mask_by_q, &t.mask_by_q);
     if (e == hipSuccess) e = upload(*d, ks.sh_start, &t.sh_start);
@@ -135,6 +137,7 @@ void Workspace::drop_graphs() {
 
 void Workspace::release() {
     drop_graphs();
+    free_sort_buffers(sorter);
     void *ptrs[] = {d_desc, rec, pslot, hkeys, hvals, items, item_off, item_cnt, entries, ctr, staging, rank, work};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -550,9 +553,34 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
     // per-point calls launch their three passes directly, which measured
     // faster than a graph launch; with profiling on, events bracket the call
     // and its apply kernel
-    const bool graphs = use_graph || (plain && tun.strategy != DBTSDF_STRATEGY_ATOMIC);
+    // (the sort strategy reads counts back in the middle of its apply and
+    // launches directly)
+    const bool sort = tun.strategy == DBTSDF_STRATEGY_SORT;
+    const bool graphs = !sort && (use_graph || (plain && tun.strategy != DBTSDF_STRATEGY_ATOMIC));
+    SortPlan plan{};
+    if (sort) {
+        uint64_t max_vox = 0;
+        for (dbtsdf_grid *g : grids) max_vox = std::max<uint64_t>(max_vox, g->n_voxels);
+        while ((1ull << plan.shift) < max_vox) ++plan.shift;
+        uint32_t gbits = 0;
+        while ((1ull << gbits) < grids.size()) ++gbits;
+        plan.end_bit = plan.shift + gbits;
+        if (plan.end_bit == 0) plan.end_bit = 1;
+        plan.emit_blocks = tun.apply_blocks;
+        plan.pairs_per_point = k3 + g0->tables->max_shadow;
+        plan.round_survivors = tun.chunk;
+    }
+    auto apply_part = [&]() -> hipError_t {
+        return sort ? sort_apply(ws, a, plan, st) : launch_pipeline(a, tun, ws.points_cap, st, kPartApply);
+    };
     slot.prof = 0;
     auto run_part = [&](int part) -> hipError_t {
+        if (sort) {
+            hipError_t se = hipSuccess;
+            if (part == kPartAll || part == kPartPre) se = launch_pipeline(a, tun, ws.points_cap, st, kPartPre);
+            if (se == hipSuccess && (part == kPartAll || part == kPartApply)) se = apply_part();
+            return se;
+        }
         if (!graphs) return launch_pipeline(a, tun, ws.points_cap, st, part);
         hipGraphExec_t ex = nullptr;
         hipError_t ge = pipeline_graph(ws, a, tun, part, &ex);
@@ -571,7 +599,7 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
         e = hipEventRecord(slot.pe[0], st);
         if (e == hipSuccess) e = run_part(kPartPre);
         if (e == hipSuccess) e = hipEventRecord(slot.pe[1], st);
-        if (e == hipSuccess) e = launch_pipeline(a, tun, ws.points_cap, st, kPartApply);
+        if (e == hipSuccess) e = apply_part();
         if (e == hipSuccess) e = hipEventRecord(slot.pe[2], st);
         if (e == hipSuccess && pipeline_has_post(tun)) e = run_part(kPartPost);
         slot.prof = 2;
@@ -773,7 +801,9 @@ dbtsdf_status dbtsdf_set_tuning(dbtsdf_grid *g, const dbtsdf_tuning *t) {
     n.threads = t->block_threads;
     n.apply_blocks = t->apply_blocks;
     n.chunk = t->chunk == 0 ? Tuning{}.chunk : (t->chunk == 0xFFFFFFFFu ? 0u : t->chunk);
-    if (n.strategy == DBTSDF_STRATEGY_ATOMIC) {
+    // the sort strategy's chunk: most survivors per round (0: as many as the pair buffers allow)
+    if (n.strategy == DBTSDF_STRATEGY_SORT) n.chunk = t->chunk == 0xFFFFFFFFu ? 0u : t->chunk;
+    if (n.strategy == DBTSDF_STRATEGY_ATOMIC || n.strategy == DBTSDF_STRATEGY_SORT) {
         if (n.bx == 0) {
             n.bx = g->tuning.bx;
             n.by = g->tuning.by;

@@ -174,6 +174,22 @@ struct PipeArgs {
     uint32_t scans_cap;      // counters layout: scans_cap * SC_N scan counters first
 };
 
+// Sort strategy: every change a return makes to a voxel word becomes a pair
+// (key = grid << shift | voxel index, contribution). A contribution is an
+// eq. 3 mask (2^n - 1 with n <= 31, so bit 31 clear: an all-ones mask changes
+// no word and is never emitted) or kHitPair, one shadow hit.
+constexpr uint32_t kHitPair = 0xFFFFFFFFu;
+constexpr unsigned long long kSortMaxPairs = 1ull << 28;  // pairs of one round
+struct SortArgs {
+    unsigned long long *keys;
+    uint32_t *vals;
+    unsigned long long *count;   // pairs emitted this round (cleared by the host)
+    uint32_t shift;              // voxel-index bits of a key
+    uint32_t surv_lo, surv_hi;   // the survivors of this round
+};
+constexpr int kSortThreads = 256;
+const void *sort_emit_kernel();  // for occupancy queries (kSortThreads per workgroup)
+
 // ---------------------------------------------------------- launch config ---
 struct Tuning {
     uint32_t strategy = DBTSDF_STRATEGY_ATOMIC;  // the faster form on dense LiDAR scans
@@ -195,7 +211,10 @@ hipError_t launch_grid_init(uint32_t *mask, uint32_t *packed, uint64_t n, hipStr
 enum { kPartAll = 0, kPartPre = 1, kPartApply = 2, kPartPost = 3 };
 // The per-point strategy writes the statistics from its select pass: it has
 // no passes after the apply.
-inline bool pipeline_has_post(const Tuning &t) { return t.strategy != DBTSDF_STRATEGY_ATOMIC; }
+inline bool per_point_front(const Tuning &t) {
+    return t.strategy == DBTSDF_STRATEGY_ATOMIC || t.strategy == DBTSDF_STRATEGY_SORT;
+}
+inline bool pipeline_has_post(const Tuning &t) { return !per_point_front(t); }
 hipError_t launch_pipeline(const PipeArgs &a, const Tuning &t, uint32_t points_cap, hipStream_t st, int part);
 hipError_t launch_read_distance(const uint32_t *mask, const uint32_t *packed, int8_t *out, uint64_t n,
                                 hipStream_t st);

@@ -1710,7 +1710,7 @@ static apply_fn find_apply(const Tuning &t, int R) {
 }
 
 bool tuning_supported(const Tuning &t, int K) {
-    if (t.strategy == DBTSDF_STRATEGY_ATOMIC) return t.threads >= 64 && t.threads <= 1024 && (t.threads % 64) == 0;
+    if (per_point_front(t)) return t.threads >= 64 && t.threads <= 1024 && (t.threads % 64) == 0;
     if (t.strategy != DBTSDF_STRATEGY_BRICK) return false;
     return find_apply(t, (K - 1) / 2) != nullptr;
 }
@@ -1742,6 +1742,12 @@ static int apply_blocks_query(const Tuning &t, int K, bool row_kernel, int devic
     // kernel's real register and LDS use (a second round of workgroups would
     // start only when the first has finished its share)
     int per_cu = 0;
+    if (t.strategy == DBTSDF_STRATEGY_SORT) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sort_emit_kernel(), kSortThreads, 0) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        return cus * per_cu;
+    }
     if (t.strategy == DBTSDF_STRATEGY_ATOMIC) {
         const void *pk = row_kernel ? reinterpret_cast<const void *>(k_apply_points<true>)
                                          : reinterpret_cast<const void *>(k_apply_atomic);
@@ -1764,9 +1770,11 @@ hipError_t launch_pipeline(const PipeArgs &a, const Tuning &t, uint32_t points_c
     while ((uint64_t)stat_chunk * 512 < points_cap) stat_chunk *= 2;
     const bool all = part == kPartAll;
     const bool pre = all || part == kPartPre, apply = all || part == kPartApply, post = all || part == kPartPost;
-    if (t.strategy == DBTSDF_STRATEGY_ATOMIC) {
+    if (per_point_front(t)) {
         // three passes: front (one-scan calls copy their descriptors in and
         // clear the counters there), select (writes the statistics out), apply
+        // (the sort strategy's apply is sort_apply, which reads counts back)
+        if (apply && t.strategy == DBTSDF_STRATEGY_SORT) return hipErrorInvalidValue;
         if (pre) {
             if (a.single_scan) {
                 k_front<true><<<pb, kPtThreads, 0, st>>>(a, info);

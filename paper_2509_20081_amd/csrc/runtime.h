@@ -33,6 +33,7 @@ struct DeviceTables {
     DevTables t{};
     std::vector<void *> allocs;
     dbtsdf_kernel_params params{};
+    uint32_t max_shadow = 0;   // cells of the largest shadow set
     ~DeviceTables();
 };
 
@@ -59,6 +60,26 @@ struct RingSlot {
 
 struct GraphEntry {
     hipGraphExec_t exec = nullptr;
+};
+
+// Buffers of the sort strategy (allocated on its first call, grown as calls
+// need): pairs twice over for the radix sort, the pair counter and the sort's
+// temporary storage.
+struct SortBuffers {
+    unsigned long long *keys[2] = {nullptr, nullptr};
+    uint32_t *vals[2] = {nullptr, nullptr};
+    unsigned long long *count = nullptr;
+    void *tmp = nullptr;
+    size_t tmp_bytes = 0;
+    unsigned long long cap = 0;   // pairs each buffer holds
+};
+// The key layout and launch shape of one sort-strategy call.
+struct SortPlan {
+    uint32_t shift;               // voxel-index bits of a key (grid index above them)
+    uint32_t end_bit;             // key bits in use
+    uint32_t emit_blocks;
+    unsigned long long pairs_per_point;  // most pairs one return emits: K^3 + largest shadow set
+    uint32_t round_survivors;     // most survivors per round (0: as many as the buffers allow)
 };
 
 // Stream-ordered scratch for integrate calls (one per grid for the plain
@@ -88,6 +109,7 @@ struct Workspace {
     uint64_t captures = 0, replays = 0;
     uint32_t prof_every = 0;             // time every prof_every-th call (0: profiling off)
     uint64_t n_calls = 0;                // integrate calls enqueued on this workspace
+    SortBuffers sorter;
     double prof_call_ms = 0.0, prof_apply_ms = 0.0;
     uint64_t prof_calls = 0, prof_apply = 0;
 
@@ -101,6 +123,11 @@ struct Workspace {
     void drop_graphs();
     void release();
 };
+
+void free_sort_buffers(SortBuffers &b);
+// The sort strategy's apply (sort_reduce.hip): reads the survivor count back,
+// then per round of survivors emits, sorts and reduces the pairs on stream st.
+hipError_t sort_apply(Workspace &ws, const PipeArgs &a, const SortPlan &plan, hipStream_t st);
 
 }  // namespace dbtsdf
 

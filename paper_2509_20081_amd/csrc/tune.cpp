@@ -38,6 +38,11 @@ std::vector<Tuning> candidates(int K) {
     a.strategy = DBTSDF_STRATEGY_ATOMIC;
     a.threads = 256;
     out.push_back(a);
+    Tuning srt;
+    srt.strategy = DBTSDF_STRATEGY_SORT;
+    srt.threads = 256;
+    srt.chunk = 0;
+    out.push_back(srt);
     return out;
 }
 

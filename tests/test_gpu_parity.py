@@ -68,6 +68,8 @@ TUNINGS = [
     dict(strategy="brick", brick=(32, 16, 8), block_threads=256, chunk=3),      # many split bricks
     dict(strategy="brick", brick=(32, 16, 16), block_threads=512, chunk=None),  # never split
     dict(strategy="atomic", block_threads=256),
+    dict(strategy="sort"),
+    dict(strategy="sort", chunk=7),                                              # rounds of 7 returns
 ]
 
 
@@ -191,8 +193,9 @@ def test_config1_full_grid(db):
 PAPER_KERNEL = dict(kernel_size=21, binning="azel", bins_az=40, bins_el=40, shadow_r2=9)
 
 
-@pytest.mark.parametrize("tuning", [dict(strategy="atomic"), dict(strategy="brick", brick=(32, 8, 8), block_threads=256)],
-                         ids=["atomic", "brick32x8x8"])
+@pytest.mark.parametrize("tuning", [dict(strategy="atomic"), dict(strategy="brick", brick=(32, 8, 8), block_threads=256),
+                                    dict(strategy="sort")],
+                         ids=["atomic", "brick32x8x8", "sort"])
 def test_paper_kernel_set_config1(db, tuning):
     """The paper's own kernel set (Sec. III-B: K = 21, 40 x 40 direction bins) on the 16x1024 scan
     into 256^3 @ 0.1 m: whole grid and statistics against the oracle."""
@@ -212,7 +215,7 @@ def test_paper_kernel_set_config1(db, tuning):
     assert ref["n_integrated"] > 3000
 
 
-@pytest.mark.parametrize("strategy", ["atomic", "brick"])
+@pytest.mark.parametrize("strategy", ["atomic", "brick", "sort"])
 def test_plain_calls_over_the_ring(db, strategy):
     """20 plain calls into one grid (more than the 16 ring slots, so every slot's descriptors, and with the
     brick strategy its captured graph, are used again), eager work between calls: statistics and grid
@@ -237,7 +240,8 @@ def test_plain_calls_over_the_ring(db, strategy):
 
 @pytest.mark.parametrize("hit", [(2, 3), (1, 1), (5, 65535)])
 @pytest.mark.parametrize("dedup", [True, False])
-def test_dense_neighbouring_returns_saturate_exactly(db, hit, dedup):
+@pytest.mark.parametrize("strategy", ["atomic", "sort"])
+def test_dense_neighbouring_returns_saturate_exactly(db, hit, dedup, strategy):
     """Returns one voxel apart in input order (neighbours share most of their shadows, so the per-point
     kernel adds shared shadow cells once with their count) on a small hit cap: counters, signs and masks
     match the oracle scan after scan, through saturation."""
@@ -245,7 +249,7 @@ def test_dense_neighbouring_returns_saturate_exactly(db, hit, dedup):
     dims = (32, 32, 32)
     o, g, _ = P.make_pair(dims, 1.0, (0.0, 0.0, 0.0), kernel_size=7, binning="cube26", shadow_r2=9,
                           hit_threshold=T, hit_max=H, dedup=dedup)
-    g.set_tuning(strategy="atomic")
+    g.set_tuning(strategy=strategy)
     m, p = o.new_grid()
     rng = np.random.default_rng(23)
     sensor = np.array([16.5, 16.5, 16.5])
@@ -267,7 +271,7 @@ def test_dense_neighbouring_returns_saturate_exactly(db, hit, dedup):
     assert ref["n_integrated"] > 200
 
 
-@pytest.mark.parametrize("strategy", ["atomic", "brick"])
+@pytest.mark.parametrize("strategy", ["atomic", "brick", "sort"])
 def test_profiling_period_mixes_call_forms(db, strategy):
     """Profiling every 3rd call: timed calls (split launch) and untimed calls (one graph) interleave
     over the ring; the totals count the timed calls only and every call matches the oracle."""
@@ -461,7 +465,7 @@ def test_autotune_keeps_result_identical(db):
     (o, g, _), gdef = _config_grid_pair(db, 1)
     scans = [(pose, P.to_device(pts)) for pose, pts in synth.config_scans(1, 0, [0])]
     tun = g.autotune(scans, True)
-    assert tun["strategy"] in ("brick", "atomic")
+    assert tun["strategy"] in ("brick", "atomic", "sort")
     m, p = o.new_grid()
     for pose, pts in synth.config_scans(1, 0, [0]):
         o.integrate(m, p, pose, pts)
@@ -543,13 +547,14 @@ def test_readout_and_restore(db):
         g.read_voxels((0, 0, 0), (41, 1, 1))
 
 
-def test_written_planes_integrate_every_window(db):
+@pytest.mark.parametrize("strategy", ["atomic", "sort"])
+def test_written_planes_integrate_every_window(db, strategy):
     """Planes written with zero masks at voxels whose windows were never stamped (not a state integration
     makes): returns landing there still get their whole eq. 4 window, as in the oracle; after a reset the
     grid integrates normally again."""
     dims = (48, 48, 40)
     o, g, _ = P.make_pair(dims, 1.0, (0.0, 0.0, 0.0), **synth.KERNEL_DEFAULTS)
-    g.set_tuning(strategy="atomic")
+    g.set_tuning(strategy=strategy)
     rng = np.random.default_rng(17)
     pose = synth.random_pose(rng, np.array([20.0, 20.0, 16.0]), np.array([28.0, 28.0, 24.0]))
     pts = synth.random_cloud(rng, 600, -np.full(3, 12.0), np.full(3, 12.0))
@@ -593,3 +598,46 @@ def test_argument_errors_leave_grid_unchanged(db):
         g.set_tuning(strategy="brick", brick=(32, 8, 8), block_threads=512)
     gm, gp = P.gpu_planes(g)
     assert np.all(gm == 0xFFFFFFFF) and np.all(gp == 0x80000000)
+
+
+def test_sort_strategy_batches_of_many_grids(db):
+    """The sort strategy over one launch holding every scan of three maps of different sizes (the keys
+    carry the grid index above the voxel bits), in rounds of 50 returns and in one round, against the
+    oracle; statistics too."""
+    maps = []
+    for mid in range(3):
+        side = min(synth.config_grid(4, mid)["dims"][0], 192)
+        dims, vs, org = centred(4, mid, side)
+        maps.append((dims, vs, org, list(synth.config_scans(4, mid, range(3)))))
+    for chunk in (50, 0):
+        pairs = [P.make_pair(d, vs, org, **synth.KERNEL_DEFAULTS) for d, vs, org, _ in maps]
+        for _, g, _ in pairs:
+            g.set_tuning(strategy="sort", chunk=chunk)
+        b = db.Batch(use_graph=True)
+        items = [(pairs[i][1], pose, P.to_device(pts)) for i in range(3) for pose, pts in maps[i][3]]
+        stats = b.integrate(items)
+        b.sync()
+        assert b.graph_stats() == (0, 0)      # the sort strategy launches directly
+        k = 0
+        for i, (o, g, _) in enumerate(pairs):
+            m, p = o.new_grid()
+            for pose, pts in maps[i][3]:
+                ref = o.integrate(m, p, pose, pts)
+                P.assert_stats_equal(stats[k].as_dict(), ref, what=f"sort batch stats {k}")
+                k += 1
+            P.assert_grids_equal(*P.gpu_planes(g), m, p, what=f"sort batch map {i} chunk {chunk}")
+
+
+def test_sort_strategy_config2_three_scans(db):
+    """1024x1024x256 @ 0.05 m with the sort strategy (about 86 M pairs per scan on the empty grid): whole
+    grid after three scans equals the oracle, and the per-point atomic strategy's grid."""
+    (o, g, _), gdef = _config_grid_pair(db, 2)
+    g.set_tuning(strategy="sort")
+    m, p = o.new_grid()
+    for k, (pose, pts) in enumerate(synth.config_scans(2, 0, [0, 1, 2])):
+        ref = o.integrate(m, p, pose, pts)
+        st = g.integrate(pose, P.to_device(pts))
+        g.sync()
+        P.assert_stats_equal(st.as_dict(), ref, traffic=False, what=f"c2 sort scan {k}")
+    gm, gp = P.gpu_planes(g)
+    P.assert_grids_equal(gm, gp, m, p, what="c2 sort")
