@@ -568,6 +568,8 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
         if (plan.end_bit == 0) plan.end_bit = 1;
         plan.emit_blocks = tun.apply_blocks;
         plan.pairs_per_point = k3 + g0->tables->max_shadow;
+        const uint32_t K = (uint32_t)g0->K, rows_per_pass = 64u / K;
+        plan.words = (K * K + rows_per_pass - 1u) / rows_per_pass + (g0->tables->max_shadow + 63u) / 64u;
         plan.round_survivors = tun.chunk;
     }
     auto apply_part = [&]() -> hipError_t {

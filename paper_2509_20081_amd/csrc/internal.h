@@ -181,10 +181,13 @@ struct PipeArgs {
 constexpr uint32_t kHitPair = 0xFFFFFFFFu;
 constexpr unsigned long long kSortMaxPairs = 1ull << 28;  // pairs of one round
 struct SortArgs {
-    unsigned long long *keys;
+    void *keys;                  // uint32_t keys when they fit 31 bits, else unsigned long long
     uint32_t *vals;
-    unsigned long long *count;   // pairs emitted this round (cleared by the host)
+    unsigned long long *bits;    // per survivor of the round: need ballots of its window and shadow passes
+    uint32_t *cnt;               // per survivor of the round: pairs it emits
+    uint32_t *off;               // their exclusive sum: where its pairs start
     uint32_t shift;              // voxel-index bits of a key
+    uint32_t words;              // ballot words per survivor
     uint32_t surv_lo, surv_hi;   // the survivors of this round
 };
 constexpr int kSortThreads = 256;

@@ -68,10 +68,13 @@ struct GraphEntry {
 struct SortBuffers {
     unsigned long long *keys[2] = {nullptr, nullptr};
     uint32_t *vals[2] = {nullptr, nullptr};
-    unsigned long long *count = nullptr;
-    void *tmp = nullptr;
+    size_t cap = 0;               // pairs each buffer holds
+    uint32_t *cnt = nullptr, *off = nullptr;
+    size_t surv_cap = 0;          // entries of cnt and off
+    unsigned long long *bits = nullptr;
+    size_t bits_cap = 0;          // ballot words
+    void *tmp = nullptr;          // the scan's and the sort's temporary storage
     size_t tmp_bytes = 0;
-    unsigned long long cap = 0;   // pairs each buffer holds
 };
 // The key layout and launch shape of one sort-strategy call.
 struct SortPlan {
@@ -80,6 +83,7 @@ struct SortPlan {
     uint32_t emit_blocks;
     unsigned long long pairs_per_point;  // most pairs one return emits: K^3 + largest shadow set
     uint32_t round_survivors;     // most survivors per round (0: as many as the buffers allow)
+    uint32_t words;               // ballot words per survivor: window passes + shadow passes
 };
 
 // Stream-ordered scratch for integrate calls (one per grid for the plain
