@@ -47,7 +47,21 @@
  *   - "first return" = lowest input index among valid, in-bounds returns;
  *   - non-finite or zero-range returns are skipped and counted;
  *   - the front end is fp32, one IEEE operation at a time, no FMA contraction
- *     (build with -ffp-contract=off).
+ *     (build with -ffp-contract=off);
+ *   - motion compensation (Sec. III-C, "yaw-only or full SE(3)", no scheme
+ *     given): a sweep has a start pose (R0, t0) and an end pose (R1, t1), each
+ *     return a time fraction tau in [0, 1] (outside, or not a number: the
+ *     return is invalid). The rotation over the sweep, Q = R1 R0^T (fp64),
+ *     becomes a unit quaternion q with w >= 0 (Shepperd's method; for
+ *     yaw-only, the rotation about z that takes Q's x axis, projected on the
+ *     xy plane, to where Q takes it: q = (c, 0, 0, s) with (c, s) the unit
+ *     half-angle vector, (1, 0, 0, 0) when the projection vanishes), rounded
+ *     to fp32, and dt = t1 - t0 (fp32). Per return, in fp32: the normalised
+ *     linear interpolation between the identity and q, p(tau) = (1 - tau, 0,
+ *     0, 0) + tau q, taken as the rotation matrix M of a quaternion of any
+ *     length (2 / |p|^2 in place of 2), R(tau) = M R0 and t(tau) = t0 + tau dt;
+ *     the return is then transformed with (R(tau), t(tau)) as above. No sine,
+ *     cosine or square root sits on the per-return path.
  */
 #include <math.h>
 #include <stdint.h>
@@ -418,6 +432,131 @@ void orc_front_end(const orc_ctx *c, const float pose[16], const float *pts, uin
     }
 }
 
+/* ---- motion compensation (deskew) ---------------------------------------- */
+
+#define ORC_DESKEW_SE3 0
+#define ORC_DESKEW_YAW 1
+
+/* unit quaternion (w, x, y, z), w >= 0, of a rotation matrix (row-major),
+   Shepperd's method: the branch on the largest of the trace and the diagonal */
+static void quat_of_matrix(const double Q[9], double q[4])
+{
+    double tr = (Q[0] + Q[4]) + Q[8], S, n;
+    int k;
+    if (tr > 0.0) {
+        S = sqrt(tr + 1.0) * 2.0;
+        q[0] = 0.25 * S;
+        q[1] = (Q[7] - Q[5]) / S;
+        q[2] = (Q[2] - Q[6]) / S;
+        q[3] = (Q[3] - Q[1]) / S;
+    } else if (Q[0] > Q[4] && Q[0] > Q[8]) {
+        S = sqrt(((1.0 + Q[0]) - Q[4]) - Q[8]) * 2.0;
+        q[0] = (Q[7] - Q[5]) / S;
+        q[1] = 0.25 * S;
+        q[2] = (Q[1] + Q[3]) / S;
+        q[3] = (Q[2] + Q[6]) / S;
+    } else if (Q[4] > Q[8]) {
+        S = sqrt(((1.0 + Q[4]) - Q[0]) - Q[8]) * 2.0;
+        q[0] = (Q[2] - Q[6]) / S;
+        q[1] = (Q[1] + Q[3]) / S;
+        q[2] = 0.25 * S;
+        q[3] = (Q[5] + Q[7]) / S;
+    } else {
+        S = sqrt(((1.0 + Q[8]) - Q[0]) - Q[4]) * 2.0;
+        q[0] = (Q[3] - Q[1]) / S;
+        q[1] = (Q[2] + Q[6]) / S;
+        q[2] = (Q[5] + Q[7]) / S;
+        q[3] = 0.25 * S;
+    }
+    n = sqrt(((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]) + q[3] * q[3]);
+    for (k = 0; k < 4; k++)
+        q[k] = q[k] / n;
+    if (q[0] < 0.0)
+        for (k = 0; k < 4; k++)
+            q[k] = -q[k];
+}
+
+/* the sweep's constants: out[0..3] = q (fp32), out[4..6] = t1 - t0 (fp32) */
+int orc_deskew_constants(const float p0[16], const float p1[16], int mode, float out[7])
+{
+    double Q[9], q[4];
+    int i, j;
+    if (mode != ORC_DESKEW_SE3 && mode != ORC_DESKEW_YAW)
+        return 1;
+    for (i = 0; i < 16; i++)
+        if (!isfinite(p0[i]) || !isfinite(p1[i]))
+            return 1;
+    /* Q = R1 R0^T: Q_ij = sum_k R1_ik R0_jk */
+    for (i = 0; i < 3; i++)
+        for (j = 0; j < 3; j++)
+            Q[3 * i + j] = ((double)p1[4 * i + 0] * (double)p0[4 * j + 0] +
+                            (double)p1[4 * i + 1] * (double)p0[4 * j + 1]) +
+                           (double)p1[4 * i + 2] * (double)p0[4 * j + 2];
+    if (mode == ORC_DESKEW_SE3) {
+        quat_of_matrix(Q, q);
+    } else {
+        /* yaw: Q's x axis projected on the xy plane at angle psi; the half
+           angle's unit vector is proportional to (|v| + v_x, v_y) */
+        double L = sqrt(Q[0] * Q[0] + Q[3] * Q[3]);
+        double hx = L + Q[0], hy = Q[3], H = sqrt(hx * hx + hy * hy);
+        q[1] = 0.0;
+        q[2] = 0.0;
+        if (L == 0.0) {
+            q[0] = 1.0;
+            q[3] = 0.0;
+        } else if (H == 0.0) {
+            q[0] = 0.0; /* psi = 180 degrees */
+            q[3] = 1.0;
+        } else {
+            q[0] = hx / H;
+            q[3] = hy / H;
+        }
+    }
+    for (i = 0; i < 4; i++)
+        out[i] = (float)q[i];
+    for (i = 0; i < 3; i++)
+        out[4 + i] = p1[4 * i + 3] - p0[4 * i + 3];
+    return 0;
+}
+
+/* the pose of a return at time fraction tau (fp32, one operation at a time) */
+static void deskew_pose(const float p0[16], const float k[7], float tau, float pose[16])
+{
+    float a = 1.0f - tau;
+    float w = a + tau * k[0], x = tau * k[1], y = tau * k[2], z = tau * k[3];
+    float ww = w * w, xx = x * x, yy = y * y, zz = z * z;
+    float wx = w * x, wy = w * y, wz = w * z, xy = x * y, xz = x * z, yz = y * z;
+    float n2 = ((ww + xx) + yy) + zz;
+    float s2 = 2.0f / n2;
+    float M[9];
+    int i, j;
+    M[0] = 1.0f - s2 * (yy + zz);
+    M[1] = s2 * (xy - wz);
+    M[2] = s2 * (xz + wy);
+    M[3] = s2 * (xy + wz);
+    M[4] = 1.0f - s2 * (xx + zz);
+    M[5] = s2 * (yz - wx);
+    M[6] = s2 * (xz - wy);
+    M[7] = s2 * (yz + wx);
+    M[8] = 1.0f - s2 * (xx + yy);
+    for (i = 0; i < 3; i++) {
+        for (j = 0; j < 3; j++) {
+            float u = M[3 * i + 0] * p0[4 * 0 + j];
+            float v = M[3 * i + 1] * p0[4 * 1 + j];
+            float e = M[3 * i + 2] * p0[4 * 2 + j];
+            pose[4 * i + j] = (u + v) + e;
+        }
+        pose[4 * i + 3] = p0[4 * i + 3] + tau * k[4 + i];
+    }
+    pose[12] = 0.0f;
+    pose[13] = 0.0f;
+    pose[14] = 0.0f;
+    pose[15] = 1.0f;
+}
+
+/* per-return pose of a deskewed sweep, exported for the tests */
+void orc_deskew_pose(const float p0[16], const float k[7], float tau, float pose[16]) { deskew_pose(p0, k, tau, pose); }
+
 /* ---- per-scan "already integrated this voxel" set ----------------------- */
 
 static const uint64_t SEEN_EMPTY = ~(uint64_t)0;
@@ -463,8 +602,9 @@ static int bm_set(uint8_t *bm, uint64_t i)
 
 /* ---- one scan ----------------------------------------------------------- */
 
-int orc_integrate(orc_ctx *c, uint32_t *mask, uint32_t *packed, const float pose[16],
-                  const float *pts, uint64_t n, orc_stats *st, int count_traffic)
+/* one scan; with times, a deskewed sweep from pose to pose_end (mode ORC_DESKEW_*) */
+static int integrate(orc_ctx *c, uint32_t *mask, uint32_t *packed, const float pose[16], const float *pose_end,
+                     int mode, const float *times, const float *pts, uint64_t n, orc_stats *st, int count_traffic)
 {
     const int K = c->K, R = c->R;
     const uint64_t nx = c->p.dims[0], ny = c->p.dims[1], nz = c->p.dims[2];
@@ -474,9 +614,12 @@ int orc_integrate(orc_ctx *c, uint32_t *mask, uint32_t *packed, const float pose
     orc_stats s;
     int k;
 
+    float kdesk[7];
     for (k = 0; k < 16; k++)
         if (!isfinite(pose[k]))
             return 1;
+    if (times && orc_deskew_constants(pose, pose_end, mode, kdesk) != 0)
+        return 1;
     memset(&s, 0, sizeof(s));
     s.n_in = n;
     if (n == 0) {
@@ -499,8 +642,19 @@ int orc_integrate(orc_ctx *c, uint32_t *mask, uint32_t *packed, const float pose
 
     for (i = 0; i < n; i++) {
         int v[3], b, dx, dy, dz;
-        int res = front_end(c, pose, pts + 3 * i, v, &b);
+        int res;
         uint64_t key;
+        if (times) {
+            float tau = times[i], pp[16];
+            if (!(tau >= 0.0f && tau <= 1.0f)) {
+                res = ST_INVALID;
+            } else {
+                deskew_pose(pose, kdesk, tau, pp);
+                res = front_end(c, pp, pts + 3 * i, v, &b);
+            }
+        } else {
+            res = front_end(c, pose, pts + 3 * i, v, &b);
+        }
         const uint8_t *sh;
         if (res == ST_INVALID) {
             s.n_invalid++;
@@ -562,6 +716,19 @@ int orc_integrate(orc_ctx *c, uint32_t *mask, uint32_t *packed, const float pose
     if (st)
         *st = s;
     return 0;
+}
+
+int orc_integrate(orc_ctx *c, uint32_t *mask, uint32_t *packed, const float pose[16],
+                  const float *pts, uint64_t n, orc_stats *st, int count_traffic)
+{
+    return integrate(c, mask, packed, pose, NULL, 0, NULL, pts, n, st, count_traffic);
+}
+
+int orc_integrate_deskew(orc_ctx *c, uint32_t *mask, uint32_t *packed, const float pose_start[16],
+                         const float pose_end[16], int mode, const float *times, const float *pts, uint64_t n,
+                         orc_stats *st, int count_traffic)
+{
+    return integrate(c, mask, packed, pose_start, pose_end, mode, times, pts, n, st, count_traffic);
 }
 
 /* signed distance readout: (sign ? +1 : -1) * popcount(mask) */

@@ -18,6 +18,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 BINNING = {"azel": 0, "cube26": 1}
 METRIC = {"l2": 0, "l1": 1}
 SHADOW = {"hemisphere": 0, "cone": 1}
+DESKEW = {"se3": 0, "yaw": 1}
 
 
 class _Params(C.Structure):
@@ -61,6 +62,12 @@ def _load():
         lib.orc_integrate.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_void_p, C.c_uint64, C.POINTER(_Stats), C.c_int]
         lib.orc_read_distance.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        lib.orc_deskew_constants.restype = C.c_int
+        lib.orc_deskew_constants.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
+        lib.orc_deskew_pose.argtypes = [C.c_void_p, C.c_void_p, C.c_float, C.c_void_p]
+        lib.orc_integrate_deskew.restype = C.c_int
+        lib.orc_integrate_deskew.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
+                                             C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(_Stats), C.c_int]
         _lib = lib
     return _lib
 
@@ -155,8 +162,47 @@ class Oracle:
             raise ValueError("oracle: non-finite pose")
         return {n: int(getattr(st, n)) for n, _ in _Stats._fields_}
 
+    def integrate_deskew(self, mask, packed, pose_start, pose_end, pts, times, mode="se3",
+                         count_traffic=False) -> dict:
+        """One motion-compensated sweep: return i is placed with the pose at time fraction times[i]
+        between pose_start and pose_end (see ``deskew_constants``)."""
+        assert mask.dtype == np.uint32 and packed.dtype == np.uint32
+        assert mask.flags.c_contiguous and packed.flags.c_contiguous
+        p0 = np.ascontiguousarray(pose_start, dtype=np.float32).reshape(16)
+        p1 = np.ascontiguousarray(pose_end, dtype=np.float32).reshape(16)
+        pts = np.ascontiguousarray(pts, dtype=np.float32).reshape(-1, 3)
+        times = np.ascontiguousarray(times, dtype=np.float32).reshape(-1)
+        assert times.shape[0] == pts.shape[0]
+        st = _Stats()
+        rc = _lib.orc_integrate_deskew(self._ctx, _ptr(mask), _ptr(packed), _ptr(p0), _ptr(p1), DESKEW[mode],
+                                       _ptr(times), _ptr(pts), pts.shape[0], C.byref(st), 1 if count_traffic else 0)
+        if rc != 0:
+            raise ValueError("oracle: non-finite pose")
+        return {n: int(getattr(st, n)) for n, _ in _Stats._fields_}
+
     def read_distance(self, mask, packed):
         out = np.empty(mask.shape, dtype=np.int8)
         _lib.orc_read_distance(self._ctx, _ptr(np.ascontiguousarray(mask)),
                                _ptr(np.ascontiguousarray(packed)), _ptr(out))
         return out
+
+
+def deskew_constants(pose_start, pose_end, mode="se3") -> np.ndarray:
+    """The sweep's fp32 constants: q (w, x, y, z) of the rotation over the sweep (or its yaw), then t1 - t0."""
+    lib = _load()
+    p0 = np.ascontiguousarray(pose_start, dtype=np.float32).reshape(16)
+    p1 = np.ascontiguousarray(pose_end, dtype=np.float32).reshape(16)
+    out = np.zeros(7, np.float32)
+    if lib.orc_deskew_constants(_ptr(p0), _ptr(p1), DESKEW[mode], _ptr(out)) != 0:
+        raise ValueError("oracle: non-finite pose or unknown mode")
+    return out
+
+
+def deskew_pose(pose_start, constants, tau) -> np.ndarray:
+    """The 4 x 4 fp32 pose of a return at time fraction tau."""
+    lib = _load()
+    p0 = np.ascontiguousarray(pose_start, dtype=np.float32).reshape(16)
+    k = np.ascontiguousarray(constants, dtype=np.float32).reshape(7)
+    out = np.zeros(16, np.float32)
+    lib.orc_deskew_pose(_ptr(p0), _ptr(k), C.c_float(tau), _ptr(out))
+    return out.reshape(4, 4)
