@@ -291,6 +291,45 @@ dbtsdf_status dbtsdf_integrate_scan(dbtsdf_grid *g, const float pose[16], const 
 dbtsdf_status dbtsdf_integrate_scan_every(dbtsdf_grid *g, const float pose[16], const float *points, uint64_t n,
                                           uint32_t every, int points_on_device, dbtsdf_scan_stats *stats);
 
+/* Motion compensation of a sweep (Sec. III-C: yaw-only or full SE(3)). */
+typedef enum {
+    DBTSDF_DESKEW_SE3 = 0, /* the whole rotation over the sweep */
+    DBTSDF_DESKEW_YAW = 1  /* only its rotation about the map z axis */
+} dbtsdf_deskew;
+
+/*
+ * The constants of a sweep from pose_start (R0, t0) to pose_end (R1, t1),
+ * host memory, 4x4 row-major fp32 like the pose of dbtsdf_integrate_scan:
+ * out[0..3] = the unit quaternion (w, x, y, z), w >= 0, of the rotation over
+ * the sweep R1 R0^T (computed in fp64 by Shepperd's method, then rounded to
+ * fp32); with DBTSDF_DESKEW_YAW that of the rotation about z taking the
+ * projection of its x axis on the xy plane to where R1 R0^T takes it
+ * ((1, 0, 0, 0) when the projection vanishes); out[4..6] = t1 - t0 (fp32).
+ * Pure host code (no device call). Errors: INVALID_ARG (NULL, non-finite
+ * pose, unknown mode).
+ */
+dbtsdf_status dbtsdf_deskew_constants(const float pose_start[16], const float pose_end[16], int mode, float out[7]);
+
+/*
+ * dbtsdf_integrate_scan_every for a sweep whose returns were taken while the
+ * sensor moved: return j (of those taken) is transformed with the pose at its
+ * time fraction tau = times[j * every] in [0, 1] between pose_start (0) and
+ * pose_end (1): with q and dt the constants above, p = (1 - tau + tau q_w,
+ * tau q_x, tau q_y, tau q_z), M the rotation matrix of p scaled by 2 / |p|^2,
+ * R(tau) = M R0 and t(tau) = t0 + tau dt, all fp32 one operation at a time
+ * (the normalised linear interpolation of the rotation; no sine or square
+ * root per return). The direction for the bin is R(tau) times the point.
+ * A return whose tau is outside [0, 1] or not a number is invalid (counted
+ * in n_invalid). times: n floats beside the points, device memory when
+ * points_on_device, else host memory (staged whole). mode: dbtsdf_deskew.
+ * Deskewed sweeps take the general three-pass form (the descriptors are
+ * copied to the device by a pass of their own). Errors as
+ * dbtsdf_integrate_scan_every; NULL times or an unknown mode is INVALID_ARG.
+ */
+dbtsdf_status dbtsdf_integrate_scan_deskew(dbtsdf_grid *g, const float pose_start[16], const float pose_end[16],
+                                           const float *points, const float *times, uint64_t n, uint32_t every,
+                                           int mode, int points_on_device, dbtsdf_scan_stats *stats);
+
 /*
  * Wait for all work on the grid's stream, deliver pending statistics.
  * Errors: DEVICE (the grid becomes poisoned), POISONED.

@@ -73,6 +73,42 @@ def _points_arg(points):
     return arr.ctypes.data_as(C.c_void_p), int(arr.shape[0]), 0, arr
 
 
+def _times_arg(times, n, on_device):
+    """(pointer, keepalive) for n fp32 time fractions on the same side as the points."""
+    try:
+        import torch
+    except ImportError:  # pragma: no cover
+        torch = None
+    if torch is not None and isinstance(times, torch.Tensor):
+        if times.dtype != torch.float32 or times.numel() != n:
+            raise ValueError("times must hold one float32 per point")
+        times = times.contiguous().reshape(-1)
+        if bool(times.is_cuda) != bool(on_device):
+            raise ValueError("times must be where the points are")
+        if times.is_cuda:
+            return C.c_void_p(times.data_ptr()), times
+        times = times.numpy()
+    if on_device:
+        raise ValueError("times must be where the points are")
+    arr = _f32(times).reshape(-1)
+    if arr.shape[0] != n:
+        raise ValueError("times must hold one float32 per point")
+    return arr.ctypes.data_as(C.c_void_p), arr
+
+
+DESKEW = {"se3": 0, "yaw": 1}
+
+
+def deskew_constants(pose_start, pose_end, mode="se3"):
+    """The sweep's fp32 constants the library uses: quaternion (w, x, y, z) of the rotation over the sweep
+    (or of its yaw), then the end translation minus the start translation."""
+    out = np.zeros(7, np.float32)
+    p0, p1 = _f32(pose_start, (16,)), _f32(pose_end, (16,))
+    L.check(L.lib().dbtsdf_deskew_constants(p0.ctypes.data_as(C.c_void_p), p1.ctypes.data_as(C.c_void_p),
+                                            DESKEW[mode], out.ctypes.data_as(C.c_void_p)), "deskew_constants")
+    return out
+
+
 def _period(enable, every) -> int:
     if not enable:
         return 0
@@ -199,12 +235,25 @@ class Grid:
         self._h = h
 
     # -- integration --------------------------------------------------------
-    def integrate(self, pose, points, every: int = 1) -> Stats:
+    def integrate(self, pose, points, every: int = 1, pose_end=None, times=None, deskew="se3") -> Stats:
         """Enqueue one scan (every > 1: only every `every`-th return, in order, the paper's sequential
-        downsampling); the returned Stats are filled at the next sync()."""
+        downsampling); the returned Stats are filled at the next sync(). With pose_end and times (one time
+        fraction in [0, 1] per point, beside the points) the scan is a sweep from pose to pose_end,
+        motion-compensated ("se3" or "yaw")."""
         pose = _f32(pose, (16,))
         ptr, n, on_dev, keep = _points_arg(points)
         st = Stats()
+        if pose_end is not None:
+            if times is None:
+                raise ValueError("a deskewed sweep needs times")
+            p1 = _f32(pose_end, (16,))
+            tptr, tkeep = _times_arg(times, n, on_dev)
+            rc = L.lib().dbtsdf_integrate_scan_deskew(self._h, pose.ctypes.data_as(C.c_void_p),
+                                                      p1.ctypes.data_as(C.c_void_p), ptr, tptr, n, int(every),
+                                                      DESKEW[deskew], on_dev, C.byref(st._c))
+            L.check(rc, "integrate_scan_deskew")
+            self._pending.append((st, (keep, tkeep) if on_dev else None))
+            return st
         if every == 1:
             rc = L.lib().dbtsdf_integrate_scan(self._h, pose.ctypes.data_as(C.c_void_p), ptr, n, on_dev,
                                                C.byref(st._c))

@@ -497,6 +497,12 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
         d.grid = gidx[s.grid];
         d.dedup = (gp.flags & DBTSDF_DEDUP_FIRST) ? 1u : 0u;
         d.step = s.step;
+        if (s.times) {
+            d.deskew = 1;
+            d.times = s.times;
+            for (int k = 0; k < 4; ++k) d.dq[k] = s.dq[k];
+            for (int k = 0; k < 3; ++k) d.dt[k] = s.dt[k];
+        }
         std::memcpy(&hs[i], &d, sizeof(d));
         begin += (uint32_t)s.n;
         PendingStat p{s.stats, (uint32_t)i, -1, s.n, k3};
@@ -545,7 +551,7 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
     a.chunk = traffic ? 0u : tun.chunk;
     // the plain one-scan call has a kernel of its own (no per-point scan lookup)
     // (its front pass reads the scan descriptor from the host in 16-byte pieces)
-    a.single_scan = plain && live.size() == 1 && scans_off % 16 == 0 ? 1u : 0u;
+    a.single_scan = plain && live.size() == 1 && !live[0].times && scans_off % 16 == 0 ? 1u : 0u;
     a.row_kernel = row_kernel ? 1u : 0u;
 
     // batches that ask for it, and plain brick-strategy calls (nine passes),
@@ -829,8 +835,9 @@ dbtsdf_status dbtsdf_integrate_scan(dbtsdf_grid *g, const float pose[16], const 
     return dbtsdf_integrate_scan_every(g, pose, points, n, 1, points_on_device, stats);
 }
 
-dbtsdf_status dbtsdf_integrate_scan_every(dbtsdf_grid *g, const float pose[16], const float *points, uint64_t n,
-                                          uint32_t every, int points_on_device, dbtsdf_scan_stats *stats) {
+static dbtsdf_status integrate_plain(dbtsdf_grid *g, const float pose[16], const float *pose_end, int mode,
+                                     const float *points, const float *times, uint64_t n, uint32_t every,
+                                     int points_on_device, dbtsdf_scan_stats *stats) {
     if (!g || !pose) return invalid("NULL argument");
     if (every == 0) return invalid("every must be >= 1");
     if (g->poisoned) {
@@ -839,6 +846,11 @@ dbtsdf_status dbtsdf_integrate_scan_every(dbtsdf_grid *g, const float pose[16], 
     }
     for (int k = 0; k < 16; ++k)
         if (!std::isfinite(pose[k])) return invalid("pose must be finite");
+    float sweep[7] = {1.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    if (pose_end) {
+        if (!times) return invalid("NULL times");
+        if (!sweep_constants(pose, pose_end, mode, sweep)) return invalid("non-finite end pose or unknown deskew mode");
+    }
     if (n > kMaxPointsPerCall) {
         set_error("too many points in one call");
         return DBTSDF_ERR_OUT_OF_RANGE;
@@ -848,15 +860,38 @@ dbtsdf_status dbtsdf_integrate_scan_every(dbtsdf_grid *g, const float pose[16], 
         if (stats) *stats = dbtsdf_scan_stats{};
         return DBTSDF_OK;
     }
-    const float *dev = points;
+    const float *dev = points, *dev_t = times;
     if (!points_on_device) {
-        hipError_t e = g->ws->ensure_staging(3 * n, g->stream);
+        // points, then the time fractions, in one staging buffer
+        const size_t floats = pose_end ? 4 * n : 3 * n;
+        hipError_t e = g->ws->ensure_staging(floats, g->stream);
         if (e == hipSuccess) e = hipMemcpyAsync(g->ws->staging, points, 12 * n, hipMemcpyHostToDevice, g->stream);
+        if (e == hipSuccess && pose_end)
+            e = hipMemcpyAsync(g->ws->staging + 3 * n, times, 4 * n, hipMemcpyHostToDevice, g->stream);
         if (e != hipSuccess) return check_hip(e, "staging host points", g);
         dev = g->ws->staging;
+        dev_t = pose_end ? g->ws->staging + 3 * n : nullptr;
     }
-    std::vector<ScanIn> v{ScanIn{g, pose, dev, (n + every - 1) / every, stats, every}};
+    ScanIn in{g, pose, dev, (n + every - 1) / every, stats, every};
+    if (pose_end) {
+        in.times = dev_t;
+        for (int k = 0; k < 4; ++k) in.dq[k] = sweep[k];
+        for (int k = 0; k < 3; ++k) in.dt[k] = sweep[4 + k];
+    }
+    std::vector<ScanIn> v{in};
     return enqueue_scans(*g->ws, g->stream, v, false, true);
+}
+
+dbtsdf_status dbtsdf_integrate_scan_every(dbtsdf_grid *g, const float pose[16], const float *points, uint64_t n,
+                                          uint32_t every, int points_on_device, dbtsdf_scan_stats *stats) {
+    return integrate_plain(g, pose, nullptr, 0, points, nullptr, n, every, points_on_device, stats);
+}
+
+dbtsdf_status dbtsdf_integrate_scan_deskew(dbtsdf_grid *g, const float pose_start[16], const float pose_end[16],
+                                           const float *points, const float *times, uint64_t n, uint32_t every,
+                                           int mode, int points_on_device, dbtsdf_scan_stats *stats) {
+    if (!pose_end) return invalid("NULL argument");
+    return integrate_plain(g, pose_start, pose_end, mode, points, times, n, every, points_on_device, stats);
 }
 
 dbtsdf_status dbtsdf_sync(dbtsdf_grid *g) {

@@ -199,18 +199,67 @@ __device__ __forceinline__ int bin_azel(const DevTables &t, float dx, float dy, 
     return b_el * baz + b_az;
 }
 
+// The pose of a return at time fraction tau of a motion-compensated sweep
+// (Sec. III-C): the normalised linear interpolation between the identity and
+// the sweep's rotation quaternion q, as the rotation matrix of a quaternion
+// of any length (2 / |p|^2 in place of 2), applied after the start rotation;
+// the translation moves linearly. fp32, one operation at a time.
+__device__ __forceinline__ void sweep_pose(const DevScan &s, float tau, float rot[9], float tr[3]) {
+    const float a = 1.0f - tau;
+    const float qw = tau * s.dq[0];
+    const float w = a + qw, x = tau * s.dq[1], y = tau * s.dq[2], z = tau * s.dq[3];
+    const float ww = w * w, xx = x * x, yy = y * y, zz = z * z;
+    const float wx = w * x, wy = w * y, wz = w * z, xy = x * y, xz = x * z, yz = y * z;
+    const float n2 = ((ww + xx) + yy) + zz;
+    const float s2 = 2.0f / n2;
+    float m[9];
+    m[0] = 1.0f - s2 * (yy + zz);
+    m[1] = s2 * (xy - wz);
+    m[2] = s2 * (xz + wy);
+    m[3] = s2 * (xy + wz);
+    m[4] = 1.0f - s2 * (xx + zz);
+    m[5] = s2 * (yz - wx);
+    m[6] = s2 * (xz - wy);
+    m[7] = s2 * (yz + wx);
+    m[8] = 1.0f - s2 * (xx + yy);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const float u = m[3 * i + 0] * s.rot[j];
+            const float v = m[3 * i + 1] * s.rot[3 + j];
+            const float e = m[3 * i + 2] * s.rot[6 + j];
+            const float uv = u + v;
+            rot[3 * i + j] = uv + e;
+        }
+        const float step = tau * s.dt[i];
+        tr[i] = s.trans[i] + step;
+    }
+}
+
 __device__ __forceinline__ uint32_t front_end(const DevScan &s, const DevGrid &g, const DevTables &t, float px,
-                                              float py, float pz, int &vx, int &vy, int &vz, int &bin) {
+                                              float py, float pz, bool deskew, float tau, int &vx, int &vy, int &vz,
+                                              int &bin) {
     if (!__builtin_isfinite(px) || !__builtin_isfinite(py) || !__builtin_isfinite(pz)) return kStInvalid;
+    float rot[9], tr[3];
+    if (deskew) {
+        if (!(tau >= 0.0f && tau <= 1.0f)) return kStInvalid;
+        sweep_pose(s, tau, rot, tr);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) rot[k] = s.rot[k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) tr[k] = s.trans[k];
+    }
     float d[3], w[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const float a = s.rot[3 * k + 0] * px;
-        const float b = s.rot[3 * k + 1] * py;
-        const float c = s.rot[3 * k + 2] * pz;
+        const float a = rot[3 * k + 0] * px;
+        const float b = rot[3 * k + 1] * py;
+        const float c = rot[3 * k + 2] * pz;
         const float ab = a + b;
         d[k] = ab + c;
-        w[k] = d[k] + s.trans[k];
+        w[k] = d[k] + tr[k];
     }
     if (d[0] == 0.0f && d[1] == 0.0f && d[2] == 0.0f) return kStInvalid;
     const uint32_t dims[3] = {g.nx, g.ny, g.nz};
@@ -285,7 +334,7 @@ constexpr uint32_t kInfoWords = sizeof(CallInfo) / 8, kGridWords = sizeof(DevGri
                    kScanWords = sizeof(DevScan) / 8;
 constexpr uint32_t kOneDescWords = kInfoWords + kGridWords + kScanWords;
 static_assert(kOneDescWords <= 64 && kCtrlWords + SC_N + TC_N <= (uint32_t)kPtThreads - 128, "one pass of workgroup 0");
-static_assert(sizeof(CallInfo) == 16 && offsetof(DevGrid, nx) == 32 && sizeof(DevScan) <= 96,
+static_assert(sizeof(CallInfo) == 16 && offsetof(DevGrid, nx) == 32 && offsetof(DevScan, dq) == 96,
               "the one-scan front pass reads the descriptors in these 16-byte pieces");
 
 template <bool ONE>
@@ -329,8 +378,12 @@ __global__ __launch_bounds__(kPtThreads) void k_front(PipeArgs a, const CallInfo
         const float px = pp[0];
         const float py = pp[1];
         const float pz = pp[2];
+        // (the one-scan form never holds a deskewed sweep, and reads only the
+        // scan descriptor's first 96 bytes)
+        const bool deskew = !ONE && sc.deskew;
+        const float tau = deskew ? sc.times[(size_t)j * sc.step] : 0.0f;
         int vx = 0, vy = 0, vz = 0, bin = 0;
-        const uint32_t st = front_end(sc, g, a.tab, px, py, pz, vx, vy, vz, bin);
+        const uint32_t st = front_end(sc, g, a.tab, px, py, pz, deskew, tau, vx, vy, vz, bin);
         uint32_t slot = kNoSlot;
         if (st == kStOk && sc.dedup) {
             const unsigned long long lin = (unsigned long long)vx +

@@ -185,7 +185,15 @@ struct ScanIn {
     uint64_t n;            // points taken
     dbtsdf_scan_stats *stats;
     uint32_t step = 1;     // every step-th point of the array
+    // a motion-compensated sweep: per-return time fractions (device) and the
+    // sweep's constants (sweep_constants); pose is the start pose
+    const float *times = nullptr;
+    float dq[4] = {1.0f, 0.0f, 0.0f, 0.0f};
+    float dt[3] = {0.0f, 0.0f, 0.0f};
 };
+// The constants of a sweep (deskew.cpp): q (w, x, y, z) then t1 - t0; false
+// for a non-finite pose or an unknown mode.
+bool sweep_constants(const float p0[16], const float p1[16], int mode, float out[7]);
 
 // Validates and enqueues one call (plain or batched) on stream st using ws.
 dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &scans, bool use_graph, bool plain);

@@ -111,3 +111,35 @@ def test_host_bins_match_oracle(db):
 def test_kernel_set_validation(db, kw):
     with pytest.raises(db.DbtsdfError):
         db.KernelSet(**kw)
+
+
+def test_sweep_constants_match_oracle(db):
+    """The library's per-sweep deskew constants (host fp64, rounded to fp32) equal the oracle's bit for bit
+    over random pose pairs, small and large turns, both modes; bad arguments are rejected."""
+    import math
+    from oracle import oracle as O
+
+    def rot(axis, ang):
+        a = np.asarray(axis, float)
+        a /= np.linalg.norm(a)
+        K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+        return np.eye(3) + math.sin(ang) * K + (1 - math.cos(ang)) * (K @ K)
+
+    rng = np.random.default_rng(0)
+    for i in range(1500):
+        P0 = np.eye(4, dtype=np.float32)
+        P0[:3, :3] = rot(rng.normal(size=3), rng.uniform(0, 3.1))
+        P0[:3, 3] = rng.normal(size=3)
+        P1 = np.eye(4, dtype=np.float32)
+        turn = rot(rng.normal(size=3), rng.uniform(0, 0.2) if i % 2 else rng.uniform(0, 3.14))
+        P1[:3, :3] = turn @ P0[:3, :3]
+        P1[:3, 3] = rng.normal(size=3)
+        for mode in ("se3", "yaw"):
+            a, b = db.deskew_constants(P0, P1, mode), O.deskew_constants(P0, P1, mode)
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), (i, mode)
+    bad = np.eye(4, dtype=np.float32)
+    bad[0, 0] = np.nan
+    with pytest.raises(db.DbtsdfError):
+        db.deskew_constants(bad, np.eye(4))
+    with pytest.raises(KeyError):
+        db.deskew_constants(np.eye(4), np.eye(4), "roll")
