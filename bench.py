@@ -132,6 +132,40 @@ def run_plain(db, torch, gdef, ks, dev, warmup, steps, tuning, profile=True):
     return g, dt, stats, prof
 
 
+def run_deskew(db, torch, gdef, ks, dev, warmup, steps, tuning, mode="se3"):
+    """The plain form with every scan taken as a motion-compensated sweep from its pose to the next
+    scan's pose, time fraction rising along the point array (as a spinning sensor's): the cost of the
+    per-return pose against the plain calls."""
+    g = db.Grid(gdef["dims"], gdef["voxel_size"], gdef["origin"], ks, planes="torch")
+    if tuning:
+        g.set_tuning(**{k: v for k, v in tuning.items() if k != "apply_blocks"})
+    n_seq = len(dev)
+    times = {}
+    def sweep(k):
+        pose, pts = dev[k % n_seq]
+        end = dev[(k + 1) % n_seq][0] if (k + 1) % n_seq else pose
+        n = int(pts.shape[0])
+        if n not in times:
+            times[n] = torch.linspace(0.0, 1.0, n, dtype=torch.float32, device="cuda")
+        return pose, pts, end, times[n]
+    for k in range(warmup):
+        pose, pts, end, tt = sweep(k)
+        g.integrate(pose, pts, pose_end=end, times=tt, deskew=mode)
+    g.sync()
+    torch.cuda.synchronize()
+    args_k = [sweep(k) for k in range(warmup, warmup + steps)]
+    with no_gc():
+        t0 = time.perf_counter()
+        stats = [g.integrate(pose, pts, pose_end=end, times=tt, deskew=mode) for pose, pts, end, tt in args_k]
+        g.sync()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    upd = sum(s.as_dict()["voxel_updates"] for s in stats)
+    g.close()
+    return {"mode": mode, "value": upd / dt, "unit": "voxel-updates/s", "ms_per_scan": dt * 1e3 / steps,
+            "scans": steps, "times": "linear in the point index from 0 to 1; end pose = the next scan's pose"}
+
+
 def run_batched(db, torch, gdef, ks, dev, warmup, steps, tuning, per_launch):
     g = db.Grid(gdef["dims"], gdef["voxel_size"], gdef["origin"], ks, planes="torch")
     if tuning:
@@ -424,6 +458,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mesh", action="store_true", help="skip the mesh export leg")
+    ap.add_argument("--no-deskew", action="store_true", help="skip the motion-compensated sweep leg")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--latency-scans", type=int, default=50)
     ap.add_argument("--serve-seconds", type=float, default=5.0)
@@ -492,6 +527,13 @@ def main():
         log(f"mesh: {mesh}")
     g.close()
     torch.cuda.empty_cache()
+
+    deskew = None
+    if not args.no_deskew:
+        deskew = run_deskew(db, torch, gdef, ks, dev, args.warmup, min(args.steps, 100), tuning)
+        deskew["vs_plain_ms_per_scan"] = deskew["ms_per_scan"] / (dt * 1e3 / args.steps)
+        log(f"deskew: {deskew}")
+        torch.cuda.empty_cache()
 
     # ---- roofline of the dominant kernel (the brick merge / apply)
     tr = count_traffic(db, gdef, ks, dev, args.warmup, args.steps, tuning)
@@ -596,6 +638,7 @@ def main():
         "mean_integrated_per_scan": float(np.mean([s["n_integrated"] for s in sd])),
         "batched": batched,
         "mesh_export": mesh,
+        "deskew": deskew,
         "latency_ms": latency,
         "served": served,
         "c4_batching": c4,
