@@ -717,3 +717,45 @@ def test_deskewed_config1_sweep(db):
         P.assert_stats_equal(st.as_dict(), ref, traffic=False, what=f"c1 sweep {k}")
         assert ref["n_integrated"] > 3000
     P.assert_grids_equal(*P.gpu_planes(g), m, p, what="c1 sweeps")
+
+
+def test_sort_strategy_wide_keys(db):
+    """The sort strategy with keys wider than 31 bits (64-bit sort): one launch holding two scans into the
+    2048x2048x512 grid (2^31 voxels, 31 voxel bits) and a scan into a small grid (one grid bit above them),
+    the c3 scans in two rounds (their pairs pass 2^28). Sampled c3 voxels against the brute-force closed
+    form, the small grid whole against the oracle, and both grids' invariants."""
+    import torch
+    gdef = synth.config_grid(3)
+    ks = db.KernelSet(kernel_size=11, binning="cube26", shadow_r2=9)
+    big = db.Grid(gdef["dims"], gdef["voxel_size"], gdef["origin"], ks, planes="torch")
+    big.set_tuning(strategy="sort")
+    dims, K = gdef["dims"], 11
+    sdims = (40, 36, 32)
+    o, small, _ = P.make_pair(sdims, 0.1, (0.0, 0.0, 0.0), kernel_size=11, binning="cube26", shadow_r2=9)
+    small.set_tuning(strategy="sort")
+    rng = np.random.default_rng(41)
+    centre = np.array(sdims) * 0.1 / 2
+    spose = synth.random_pose(rng, centre - 0.2, centre + 0.2)
+    spts = synth.random_cloud(rng, 3000, -centre * 0.9, centre * 0.9)
+    items, integrated = [], []
+    for pose, pts in synth.config_scans(3, 0, [0, 1]):
+        items.append((big, pose, P.to_device(pts)))
+        integrated.append(_front_end_big(pose, pts, gdef, K))
+    items.append((small, spose, P.to_device(spts)))
+    b = db.Batch(use_graph=False)
+    stats = b.integrate(items)
+    b.sync()
+    m, p = o.new_grid()
+    ref = o.integrate(m, p, spose, spts)
+    P.assert_stats_equal(stats[2].as_dict(), ref, what="small grid in the wide-key batch")
+    P.assert_grids_equal(*P.gpu_planes(small), m, p, what="small grid in the wide-key batch")
+    smp = P.sample_voxels(np.random.default_rng(3), dims, K, integrated, n_near=2000, n_any=500)
+    sm, sp = brute.sampled_voxels(smp, dims, K, integrated, 9, 5, 65535)
+    idx = torch.from_numpy(smp[:, 2] * dims[1] * dims[0] + smp[:, 1] * dims[0] + smp[:, 0]).cuda()
+    gm = big.mask_tensor.view(-1)[idx].cpu().numpy().view(np.uint32)
+    gp = big.packed_tensor.view(-1)[idx].cpu().numpy().view(np.uint32)
+    P.assert_grids_equal(gm, gp, sm, sp, what="c3 sampled, wide-key sort")
+    _invariants_torch(big, 5, 65535)
+    big.close()
+    del big
+    torch.cuda.empty_cache()
