@@ -453,6 +453,19 @@ dbtsdf_status dbtsdf_batch_integrate(dbtsdf_batch *b, uint32_t n_scans, dbtsdf_g
                                      const float *poses, const float *const *points, const uint64_t *n,
                                      int points_on_device, dbtsdf_scan_stats *stats);
 
+/*
+ * dbtsdf_batch_integrate for motion-compensated sweeps (as
+ * dbtsdf_integrate_scan_deskew, every = 1): scan i runs from poses_start[16*i..]
+ * to poses_end[16*i..], return j at time fraction times[i][j]; times[i] lives
+ * where the points do (host arrays are copied before return). mode:
+ * dbtsdf_deskew, for every scan of the call. Errors as dbtsdf_batch_integrate;
+ * NULL times, a non-finite end pose or an unknown mode is INVALID_ARG.
+ */
+dbtsdf_status dbtsdf_batch_integrate_deskew(dbtsdf_batch *b, uint32_t n_scans, dbtsdf_grid *const *grids,
+                                            const float *poses_start, const float *poses_end, int mode,
+                                            const float *const *points, const float *const *times,
+                                            const uint64_t *n, int points_on_device, dbtsdf_scan_stats *stats);
+
 /* Wait for the batch context's stream and deliver statistics. */
 dbtsdf_status dbtsdf_batch_sync(dbtsdf_batch *b);
 

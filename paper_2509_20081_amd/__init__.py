@@ -423,6 +423,35 @@ class Batch:
         L.check(L.lib().dbtsdf_batch_integrate(self._h, n, grids, poses.ctypes.data_as(C.c_void_p), ptrs, counts,
                                                on_dev.pop(), stats), "batch_integrate")
         self._keep.append((stats, [a[3] for a in args]))
+        return self._stats_list(stats, n)
+
+    def integrate_sweeps(self, items, deskew="se3") -> list:
+        """items: [(grid, pose_start, pose_end, points, times)], motion-compensated sweeps in one launch;
+        points (and times beside them) all on the device or all on the host."""
+        n = len(items)
+        if n == 0:
+            return []
+        grids = (C.c_void_p * n)(*[it[0]._h for it in items])
+        p0 = np.stack([_f32(it[1], (16,)) for it in items]).astype(np.float32)
+        p1 = np.stack([_f32(it[2], (16,)) for it in items]).astype(np.float32)
+        args = [_points_arg(it[3]) for it in items]
+        on_dev = {a[2] for a in args}
+        if len(on_dev) != 1:
+            raise ValueError("batch points must be all on the device or all on the host")
+        on = on_dev.pop()
+        targs = [_times_arg(it[4], a[1], on) for it, a in zip(items, args)]
+        ptrs = (C.c_void_p * n)(*[a[0] for a in args])
+        tptrs = (C.c_void_p * n)(*[t[0] for t in targs])
+        counts = (C.c_uint64 * n)(*[a[1] for a in args])
+        stats = (L.ScanStats * n)()
+        L.check(L.lib().dbtsdf_batch_integrate_deskew(self._h, n, grids, p0.ctypes.data_as(C.c_void_p),
+                                                      p1.ctypes.data_as(C.c_void_p), DESKEW[deskew], ptrs, tptrs,
+                                                      counts, on, stats), "batch_integrate_deskew")
+        self._keep.append((stats, [a[3] for a in args], [t[1] for t in targs]))
+        return self._stats_list(stats, n)
+
+    @staticmethod
+    def _stats_list(stats, n):
         out = []
         for i in range(n):
             s = Stats()

@@ -85,6 +85,7 @@ SIGNATURES = {
     "dbtsdf_extract_points": (C.c_int, [P, P, P, P, U64, C.POINTER(U64)]),
     "dbtsdf_deskew_constants": (C.c_int, [P, P, C.c_int, P]),
     "dbtsdf_integrate_scan_deskew": (C.c_int, [P, P, P, P, P, U64, U32, C.c_int, C.c_int, P]),
+    "dbtsdf_batch_integrate_deskew": (C.c_int, [P, U32, P, P, P, C.c_int, P, P, P, C.c_int, P]),
     "dbtsdf_destroy_grid": (None, [P]),
     "dbtsdf_set_profiling": (C.c_int, [P, C.c_int]),
     "dbtsdf_read_profile": (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(U64), C.POINTER(C.c_double),

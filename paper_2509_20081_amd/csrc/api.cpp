@@ -1145,20 +1145,26 @@ dbtsdf_status dbtsdf_batch_create(void *hip_stream, int use_graph, dbtsdf_batch 
     return DBTSDF_OK;
 }
 
-dbtsdf_status dbtsdf_batch_integrate(dbtsdf_batch *b, uint32_t n_scans, dbtsdf_grid *const *grids, const float *poses,
-                                     const float *const *points, const uint64_t *n, int points_on_device,
-                                     dbtsdf_scan_stats *stats) {
+static dbtsdf_status batch_impl(dbtsdf_batch *b, uint32_t n_scans, dbtsdf_grid *const *grids, const float *poses,
+                                const float *poses_end, int mode, const float *const *points,
+                                const float *const *times, const uint64_t *n, int points_on_device,
+                                dbtsdf_scan_stats *stats) {
     if (!b) return invalid("NULL batch");
     if (n_scans == 0) return DBTSDF_OK;
     if (!grids || !poses || !points || !n) return invalid("NULL argument");
+    if (poses_end && !times) return invalid("NULL times");
+    std::vector<float> sweep(poses_end ? 7 * (size_t)n_scans : 0);
     uint64_t total = 0;
     for (uint32_t i = 0; i < n_scans; ++i) {
         if (!grids[i]) return invalid("NULL grid");
         if (grids[i]->device != b->device) return invalid("grid on another device than the batch");
         if (grids[i]->poisoned) return DBTSDF_ERR_POISONED;
         if (n[i] && !points[i]) return invalid("NULL points");
+        if (poses_end && n[i] && !times[i]) return invalid("NULL times");
         for (int k = 0; k < 16; ++k)
             if (!std::isfinite(poses[16 * (size_t)i + k])) return invalid("pose must be finite");
+        if (poses_end && !sweep_constants(poses + 16 * (size_t)i, poses_end + 16 * (size_t)i, mode, &sweep[7 * i]))
+            return invalid("non-finite end pose or unknown deskew mode");
         total += n[i];
     }
     if (total > kMaxPointsPerCall) {
@@ -1168,7 +1174,9 @@ dbtsdf_status dbtsdf_batch_integrate(dbtsdf_batch *b, uint32_t n_scans, dbtsdf_g
     std::vector<ScanIn> v(n_scans);
     float *stage = nullptr;
     if (!points_on_device) {
-        hipError_t e = b->ws->ensure_staging(3 * std::max<uint64_t>(total, 1), b->stream);
+        // every scan's points, then (sweeps) every scan's time fractions
+        const uint64_t floats = (poses_end ? 4 : 3) * std::max<uint64_t>(total, 1);
+        hipError_t e = b->ws->ensure_staging(floats, b->stream);
         if (e != hipSuccess) return check_hip(e, "allocating point staging");
         stage = b->ws->staging;
     }
@@ -1185,12 +1193,21 @@ dbtsdf_status dbtsdf_batch_integrate(dbtsdf_batch *b, uint32_t n_scans, dbtsdf_g
     uint64_t off = 0;
     for (uint32_t i = 0; i < n_scans; ++i) {
         const float *dev = points[i];
+        const float *dev_t = poses_end ? times[i] : nullptr;
         if (!points_on_device && n[i]) {
             hipError_t e = hipMemcpyAsync(stage + 3 * off, points[i], 12 * n[i], hipMemcpyHostToDevice, b->stream);
+            if (e == hipSuccess && poses_end)
+                e = hipMemcpyAsync(stage + 3 * total + off, times[i], 4 * n[i], hipMemcpyHostToDevice, b->stream);
             if (e != hipSuccess) return check_hip(e, "staging host points");
             dev = stage + 3 * off;
+            dev_t = poses_end ? stage + 3 * total + off : nullptr;
         }
         v[i] = ScanIn{grids[i], poses + 16 * (size_t)i, dev, n[i], stats ? &stats[i] : nullptr};
+        if (poses_end) {
+            v[i].times = dev_t;
+            for (int k = 0; k < 4; ++k) v[i].dq[k] = sweep[7 * i + k];
+            for (int k = 0; k < 3; ++k) v[i].dt[k] = sweep[7 * i + 4 + k];
+        }
         off += n[i];
     }
     dbtsdf_status s = enqueue_scans(*b->ws, b->stream, v, b->use_graph, false);
@@ -1199,6 +1216,20 @@ dbtsdf_status dbtsdf_batch_integrate(dbtsdf_batch *b, uint32_t n_scans, dbtsdf_g
     for (dbtsdf_grid *g : distinct)
         if (e == hipSuccess && g->stream != b->stream && !g->external_order) e = hipStreamWaitEvent(g->stream, b->ev, 0);
     return check_hip(e, "ordering grid work after the batch");
+}
+
+dbtsdf_status dbtsdf_batch_integrate(dbtsdf_batch *b, uint32_t n_scans, dbtsdf_grid *const *grids, const float *poses,
+                                     const float *const *points, const uint64_t *n, int points_on_device,
+                                     dbtsdf_scan_stats *stats) {
+    return batch_impl(b, n_scans, grids, poses, nullptr, 0, points, nullptr, n, points_on_device, stats);
+}
+
+dbtsdf_status dbtsdf_batch_integrate_deskew(dbtsdf_batch *b, uint32_t n_scans, dbtsdf_grid *const *grids,
+                                            const float *poses_start, const float *poses_end, int mode,
+                                            const float *const *points, const float *const *times, const uint64_t *n,
+                                            int points_on_device, dbtsdf_scan_stats *stats) {
+    if (!poses_end) return invalid("NULL argument");
+    return batch_impl(b, n_scans, grids, poses_start, poses_end, mode, points, times, n, points_on_device, stats);
 }
 
 dbtsdf_status dbtsdf_batch_sync(dbtsdf_batch *b) {
