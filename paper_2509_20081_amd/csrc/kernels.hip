@@ -1369,6 +1369,9 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const C
                 m[2] = (uint32_t)((int32_t)(v.y << 16) >> 16);
                 m[3] = (uint32_t)((int32_t)v.y >> 16);
             };
+            // a point that loaded no window (past the end, or a revisit) has
+            // nothing to compare
+            if (!live[p] || (r[p].w & kRecRevisit)) continue;
             bool need = false;
 #pragma unroll
             for (int k = 0; k < kQuadIters; ++k) {
