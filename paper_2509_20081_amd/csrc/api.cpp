@@ -553,6 +553,7 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
     // (its front pass reads the scan descriptor from the host in 16-byte pieces)
     a.single_scan = plain && live.size() == 1 && !live[0].times && scans_off % 16 == 0 ? 1u : 0u;
     a.row_kernel = row_kernel ? 1u : 0u;
+    a.revisit_ok = g0->tables->t.n_bins <= 32768u ? 1u : 0u;
 
     // batches that ask for it, and plain brick-strategy calls (nine passes),
     // replay captured graphs (one host call instead of one per pass); plain

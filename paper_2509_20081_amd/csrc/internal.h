@@ -26,9 +26,9 @@ constexpr uint32_t kMaxAtomicGrids = 1u << 16;  // per-point strategy: grid inde
 // bit 30 set by the select pass on returns that are integrated
 constexpr uint32_t kStOk = 0, kStInvalid = 1, kStOob = 2;
 constexpr uint32_t kRecSurvivor = 1u << 30;
-// survivor record word (per-point strategy): bin in bits 0-15 (bits 0-14 and
-// the revisit flag in bit 15 when the row kernel runs: at most 31 bins), grid
-// index in bits 16-31
+// survivor record word (per-point and sort strategies): bin in bits 0-15
+// (bits 0-14 and the revisit flag in bit 15 when the kernel set has at most
+// 32768 bins, PipeArgs::revisit_ok), grid index in bits 16-31
 constexpr uint32_t kRecRevisit = 1u << 15;
 constexpr uint32_t kRowBinMask = kRecRevisit - 1u;
 
@@ -174,6 +174,8 @@ struct PipeArgs {
                              // tables and every grid has Nx % 4 == 0 (16-byte aligned rows) and window
                              // byte offsets that fit 32 bits (8 R (1 + Nx + Nx Ny) < 2^32)
     uint32_t single_scan;    // the call holds exactly one scan (one grid)
+    uint32_t revisit_ok;     // the kernel set has at most 32768 bins: bit 15 of a survivor's record
+                             // word is free for the revisit flag (else the bin uses bits 0-15)
     // the call's descriptors are read from, and its counters written to, the
     // pinned host buffer of its ring slot by the first and last passes
     const uint2 *host_desc;  // CallInfo | DevGrid[grids_cap] | DevScan[n_scans]

@@ -1022,9 +1022,10 @@ __global__ __launch_bounds__(kSelThreads) void k_select_atomic(PipeArgs a, const
         // (the masks depend on the offset only), and AND only lowers them. Its
         // voxel reads mask 0 (n = 0 only at distance 0; dedup keeps one
         // return per voxel in a scan, so this call has not written it). The
-        // row kernel then skips the window loads (bit 15 of the record word).
+        // apply kernels then skip the window (bit 15 of the record word,
+        // free when the kernel set has at most 32768 bins).
         uint32_t revisit = 0u;
-        if (surv && a.row_kernel) {
+        if (surv && a.revisit_ok) {
             const DevGrid &g = a.grids[a.scans[s].grid];
             if (g.revisit_skip) {
                 const size_t v = (size_t)r.x + (size_t)g.nx * ((size_t)r.y + (size_t)g.ny * (size_t)r.z);
@@ -1132,13 +1133,15 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_atomic(PipeArgs a, const C
     for (uint32_t e = lo + slot * (blockDim.x >> 6) + (threadIdx.x >> 6); e < n_surv; e += waves) {
         const uint4 r = a.surv_rec[e];
         const DevGrid g = uniform_grid(a.grids[r.w >> 16]);
+        const bool revisit = a.revisit_ok && (r.w & kRecRevisit);
         // the window's first cell (x - R, y - R, z - R); the front end admitted
         // only points whose whole window lies in the grid
         const size_t corner = (size_t)(r.x - (uint32_t)R) +
                               (size_t)g.nx * ((size_t)(r.y - (uint32_t)R) + (size_t)g.ny * (size_t)(r.z - (uint32_t)R));
         gu32 *mb = glob(g.mask) + corner;
         gu32 *pb = glob(g.packed) + corner;
-        for (uint32_t r0 = 0; r0 < rows; r0 += rpi * kAtomicBatch) {
+        // (a return whose voxel an earlier call integrated skips its window)
+        for (uint32_t r0 = 0; !revisit && r0 < rows; r0 += rpi * kAtomicBatch) {
             uint32_t old[kAtomicBatch], m[kAtomicBatch];
             size_t off[kAtomicBatch];
             bool on[kAtomicBatch];
@@ -1158,7 +1161,7 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_atomic(PipeArgs a, const C
             for (int u = 0; u < kAtomicBatch; ++u)
                 if (on[u] && (old[u] & m[u]) != old[u]) g_and(mb + off[u], m[u]);
         }
-        const uint32_t bin = r.w & 0xFFFFu;
+        const uint32_t bin = r.w & (a.revisit_ok ? kRowBinMask : 0xFFFFu);
         const uint32_t s0 = t.sh_start[bin], s1 = t.sh_start[bin + 1];
         for (uint32_t j0 = s0; j0 < s1; j0 += 64u * kShadowBatch) {
             uint32_t ov[kShadowBatch];

@@ -127,7 +127,7 @@ __global__ __launch_bounds__(kSortThreads) void k_mark_pairs(PipeArgs a, SortArg
         const Surv v = load_surv(a, e, w.R);
         unsigned long long *bits = s.bits + (uint64_t)(e - s.surv_lo) * s.words;
         uint32_t total = 0;
-        if (!(v.r.w & kRecRevisit)) {
+        if (!(a.revisit_ok && (v.r.w & kRecRevisit))) {
             unsigned long long mine = 0;   // lane u keeps the ballot of pass p0 + u of each 64
             for (uint32_t u0 = 0; u0 < w.n_pass; u0 += kLoadBatch) {
                 uint32_t old[kLoadBatch], m[kLoadBatch];
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(kSortThreads) void k_mark_pairs(PipeArgs a, SortArg
                 }
             }
         }
-        const uint32_t bin = v.r.w & kRowBinMask;
+        const uint32_t bin = v.r.w & (a.revisit_ok ? kRowBinMask : 0xFFFFu);
         const uint32_t s0 = t.sh_start[bin], s1 = t.sh_start[bin + 1];
         const uint32_t n_sp = (s1 - s0 + 63u) / 64u;
         for (uint32_t p = 0; p < n_sp; ++p) {
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(kSortThreads) void k_emit_pairs(PipeArgs a, SortArg
         const unsigned long long *bits = s.bits + (uint64_t)(e - s.surv_lo) * s.words;
         uint32_t slot = __builtin_amdgcn_readfirstlane(s.off[e - s.surv_lo]);
         const unsigned long long kbase = ((unsigned long long)v.gi << s.shift) + v.corner;
-        if (!(v.r.w & kRecRevisit)) {
+        if (!(a.revisit_ok && (v.r.w & kRecRevisit))) {
             for (uint32_t p = 0; p < w.n_pass; ++p) {
                 const unsigned long long bal = wave_uniform64(bits[p]);
                 if ((bal >> w.l) & 1ull) {
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(kSortThreads) void k_emit_pairs(PipeArgs a, SortArg
                 slot += (uint32_t)__popcll(bal);
             }
         }
-        const uint32_t bin = v.r.w & kRowBinMask;
+        const uint32_t bin = v.r.w & (a.revisit_ok ? kRowBinMask : 0xFFFFu);
         const uint32_t s0 = t.sh_start[bin], s1 = t.sh_start[bin + 1];
         const uint32_t n_sp = (s1 - s0 + 63u) / 64u;
         for (uint32_t p = 0; p < n_sp; ++p) {

@@ -547,13 +547,17 @@ def test_readout_and_restore(db):
         g.read_voxels((0, 0, 0), (41, 1, 1))
 
 
+@pytest.mark.parametrize("kernel", ["row", "generic"])
 @pytest.mark.parametrize("strategy", ["atomic", "sort"])
-def test_written_planes_integrate_every_window(db, strategy):
+def test_written_planes_integrate_every_window(db, strategy, kernel):
     """Planes written with zero masks at voxels whose windows were never stamped (not a state integration
     makes): returns landing there still get their whole eq. 4 window, as in the oracle; after a reset the
     grid integrates normally again."""
     dims = (48, 48, 40)
-    o, g, _ = P.make_pair(dims, 1.0, (0.0, 0.0, 0.0), **synth.KERNEL_DEFAULTS)
+    kw = dict(synth.KERNEL_DEFAULTS)
+    if kernel == "generic":
+        kw.update(kernel_size=13)   # past the row kernel's tables: the generic per-point kernel
+    o, g, _ = P.make_pair(dims, 1.0, (0.0, 0.0, 0.0), **kw)
     g.set_tuning(strategy=strategy)
     rng = np.random.default_rng(17)
     pose = synth.random_pose(rng, np.array([20.0, 20.0, 16.0]), np.array([28.0, 28.0, 24.0]))
@@ -796,3 +800,33 @@ def test_batched_sweeps_match_oracle(db, use_graph):
             P.assert_stats_equal(stats[k].as_dict(), ref, what=f"round {rnd} scan {k}")
         for gi in range(3):
             P.assert_grids_equal(*P.gpu_planes(pairs[gi][1]), *refs[gi], what=f"round {rnd} grid {gi}")
+
+
+
+@pytest.mark.parametrize("strategy", ["atomic", "sort"])
+@pytest.mark.parametrize("kernel", [dict(kernel_size=13, binning="cube26", shadow_r2=9),
+                                    dict(kernel_size=11, binning="azel", bins_az=40, bins_el=40, shadow_r2=9),
+                                    dict(kernel_size=5, binning="azel", bins_az=256, bins_el=130, shadow_r2=4)],
+                         ids=["K13", "azel1600", "azel33280"])
+def test_revisits_with_generic_kernels(db, strategy, kernel):
+    """Scans that land again in voxels earlier calls integrated (the same cloud from nearby poses, then a
+    denser one), with kernel sets the row kernel does not cover: K = 13, 1600 bins (revisits skip their
+    window, the flag beside the bin) and 33280 bins (the bin takes all 16 bits, no skip). Statistics and
+    grid equal the oracle's after every call."""
+    dims = (56, 52, 48)
+    o, g, _ = P.make_pair(dims, 0.1, (0.0, 0.0, 0.0), hit_threshold=2, **kernel)
+    g.set_tuning(strategy=strategy)
+    m, p = o.new_grid()
+    rng = np.random.default_rng(61)
+    centre = np.array(dims) * 0.1 / 2
+    cloud = synth.random_cloud(rng, 1200, -centre * 0.8, centre * 0.8)
+    base = synth.random_pose(rng, centre - 0.1, centre + 0.1, max_angle=0.2)
+    for k in range(4):
+        pose = base.copy()
+        pose[:3, 3] += rng.uniform(-0.02, 0.02, 3).astype(np.float32)
+        pts = cloud if k < 3 else np.concatenate([cloud, synth.random_cloud(rng, 2000, -centre * 0.8, centre * 0.8)])
+        ref = o.integrate(m, p, pose, pts)
+        st = g.integrate(pose, P.to_device(pts))
+        g.sync()
+        P.assert_stats_equal(st.as_dict(), ref, traffic=False, what=f"call {k}")
+        P.assert_grids_equal(*P.gpu_planes(g), m, p, what=f"call {k}")
