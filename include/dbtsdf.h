@@ -322,8 +322,7 @@ dbtsdf_status dbtsdf_deskew_constants(const float pose_start[16], const float po
  * A return whose tau is outside [0, 1] or not a number is invalid (counted
  * in n_invalid). times: n floats beside the points, device memory when
  * points_on_device, else host memory (staged whole). mode: dbtsdf_deskew.
- * Deskewed sweeps take the general three-pass form (the descriptors are
- * copied to the device by a pass of their own). Errors as
+ * The passes are those of dbtsdf_integrate_scan. Errors as
  * dbtsdf_integrate_scan_every; NULL times or an unknown mode is INVALID_ARG.
  */
 dbtsdf_status dbtsdf_integrate_scan_deskew(dbtsdf_grid *g, const float pose_start[16], const float pose_end[16],

@@ -551,7 +551,7 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
     a.chunk = traffic ? 0u : tun.chunk;
     // the plain one-scan call has a kernel of its own (no per-point scan lookup)
     // (its front pass reads the scan descriptor from the host in 16-byte pieces)
-    a.single_scan = plain && live.size() == 1 && !live[0].times && scans_off % 16 == 0 ? 1u : 0u;
+    a.single_scan = plain && live.size() == 1 && scans_off % 16 == 0 ? 1u : 0u;
     a.row_kernel = row_kernel ? 1u : 0u;
     a.revisit_ok = g0->tables->t.n_bins <= 32768u ? 1u : 0u;
 

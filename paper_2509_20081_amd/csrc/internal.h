@@ -115,15 +115,14 @@ struct DevScan {
     uint32_t grid;         // index into DevGrid array
     uint32_t dedup;
     uint32_t step;         // sequential downsampling: every step-th return of the array
-    uint32_t deskew;       // 1: a motion-compensated sweep (the fields below); the one-scan
-                           // front pass reads only the 96 bytes above and never takes one
+    uint32_t deskew;       // 1: a motion-compensated sweep (the fields below)
     float dq[4];           // quaternion (w, x, y, z) of the rotation over the sweep, fp32
     float dt[3];           // end translation - start translation (rot, trans: the start pose)
     float pad1;
     const float *times;    // per return of the array: time fraction in [0, 1], device
     uint32_t pad2[2];
 };
-static_assert(sizeof(DevScan) % 16 == 0 && offsetof(DevScan, dq) == 96, "DevScan layout");
+static_assert(sizeof(DevScan) % 16 == 0, "DevScan is read in 16-byte pieces");
 
 // Per-scan counters (u64) and per-grid traffic counters.
 enum { SC_INVALID = 0, SC_OOB, SC_DUP, SC_INT, SC_SHADOW, SC_N };

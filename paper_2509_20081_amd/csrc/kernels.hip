@@ -327,19 +327,22 @@ __global__ __launch_bounds__(256) void k_download(PipeArgs a, const CallInfo *in
 // one-scan call (ONE) the passes that copy the descriptors in and clear the
 // counters are folded in: every workgroup reads what it needs of the call's
 // descriptors (the sizes, the grid's dimensions, the scan) straight from the
-// ring slot's pinned host buffer into LDS, in eight 16-byte reads, and
-// workgroup 0 also writes the whole device copy that the later passes read
-// and clears the counters (no pass before this one touches either).
+// ring slot's pinned host buffer into LDS, in eleven 16-byte reads issued
+// together, and workgroup 0 also writes the whole device copy that the later
+// passes read and clears the counters (no pass before this one touches
+// either).
 constexpr uint32_t kInfoWords = sizeof(CallInfo) / 8, kGridWords = sizeof(DevGrid) / 8,
                    kScanWords = sizeof(DevScan) / 8;
 constexpr uint32_t kOneDescWords = kInfoWords + kGridWords + kScanWords;
 static_assert(kOneDescWords <= 64 && kCtrlWords + SC_N + TC_N <= (uint32_t)kPtThreads - 128, "one pass of workgroup 0");
-static_assert(sizeof(CallInfo) == 16 && offsetof(DevGrid, nx) == 32 && offsetof(DevScan, dq) == 96,
+constexpr uint32_t kScanPieces = sizeof(DevScan) / 16;
+static_assert(sizeof(CallInfo) == 16 && offsetof(DevGrid, nx) == 32 && sizeof(DevScan) % 16 == 0 &&
+                  2 + kScanPieces <= 64,
               "the one-scan front pass reads the descriptors in these 16-byte pieces");
 
 template <bool ONE>
 __global__ __launch_bounds__(kPtThreads) void k_front(PipeArgs a, const CallInfo *info_dev) {
-    __shared__ uint4 s_desc[ONE ? 8 : 1];
+    __shared__ uint4 s_desc[ONE ? 2 + kScanPieces : 1];
     const CallInfo *info = info_dev;
     const DevScan *scans = a.scans;
     const DevGrid *grids = a.grids;
@@ -348,10 +351,9 @@ __global__ __launch_bounds__(kPtThreads) void k_front(PipeArgs a, const CallInfo
         const uint32_t t = threadIdx.x;
         // host layout: CallInfo, DevGrid[grids_cap] and, at desc_scans_off
         // (a multiple of 16), DevScan[n_scans]; piece 1 is the grid's
-        // nx, ny, nz (and nbx), pieces 2-7 the scan (the last runs 8 bytes
-        // into the next scan slot, which the buffer always holds)
+        // nx, ny, nz (and nbx), pieces 2 on the scan
         const uint4 *h16 = reinterpret_cast<const uint4 *>(a.host_desc);
-        if (t < 8u) s_desc[t] = h16[t == 0u ? 0u : t == 1u ? 3u : a.desc_scans_off / 16u + (t - 2u)];
+        if (t < 2u + kScanPieces) s_desc[t] = h16[t == 0u ? 0u : t == 1u ? 3u : a.desc_scans_off / 16u + (t - 2u)];
         if (blockIdx.x == 0) {
             if (t >= 64u && t < 64u + kOneDescWords) {
                 const uint32_t w = t - 64u;
@@ -378,9 +380,7 @@ __global__ __launch_bounds__(kPtThreads) void k_front(PipeArgs a, const CallInfo
         const float px = pp[0];
         const float py = pp[1];
         const float pz = pp[2];
-        // (the one-scan form never holds a deskewed sweep, and reads only the
-        // scan descriptor's first 96 bytes)
-        const bool deskew = !ONE && sc.deskew;
+        const bool deskew = sc.deskew != 0u;
         const float tau = deskew ? sc.times[(size_t)j * sc.step] : 0.0f;
         int vx = 0, vy = 0, vz = 0, bin = 0;
         const uint32_t st = front_end(sc, g, a.tab, px, py, pz, deskew, tau, vx, vy, vz, bin);
