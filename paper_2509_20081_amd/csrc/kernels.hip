@@ -1486,7 +1486,9 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh(MeshArgs m) {
         // chunk's triangles and notes the steps where any lane has some;
         // one atomic reserves the chunk's room (a counter bumped per step
         // would be one hot address); a second walk writes the triangles,
-        // visiting only the noted steps.
+        // visiting only the noted steps. Within the chunk the triangles of
+        // a step are contiguous, lane after lane, so the lanes' stores of
+        // one step fall on neighbouring lines.
         for (uint32_t k0 = 0; k0 < m.nc[2]; k0 += 64u) {
             const uint32_t kn = min(64u, m.nc[2] - k0);
             uint32_t mine = 0;
@@ -1512,7 +1514,7 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh(MeshArgs m) {
             if (l == 63u) first = atomicAdd(m.count, (unsigned long long)total);
             first = __shfl(first, 63, 64);
             if (!m.out) continue;   // counting only
-            unsigned long long slot = first + incl - mine;
+            unsigned long long run_base = first;   // first slot of the next noted step
             uint32_t loaded = 0xFFFFFFFEu;   // step whose upper layer (pa, pb) holds (none yet)
             int pa = 0, pb = 0;
             while (steps) {
@@ -1527,6 +1529,9 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh(MeshArgs m) {
             pb = cb;
             loaded = s;
             const uint32_t n_t = has_cube ? tb(cs, 0) : 0u;
+            const uint32_t inc_t = wave_incl_scan_u32(n_t);
+            unsigned long long slot = run_base + (inc_t - n_t);
+            run_base += __shfl(inc_t, 63, 64);
             if (n_t == 0u) continue;
             // vertex of crossed edge e
             auto vtx = [&](uint32_t e, float &x, float &y, float &z) {
