@@ -143,3 +143,23 @@ def test_sweep_constants_match_oracle(db):
         db.deskew_constants(bad, np.eye(4))
     with pytest.raises(KeyError):
         db.deskew_constants(np.eye(4), np.eye(4), "roll")
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """With the HIP library absent every entry point raises: there is no CPU fallback (checked in a child
+    process whose binding points at an empty directory)."""
+    import subprocess
+    import sys
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from paper_2509_20081_amd import _lib\n"
+        "_lib.LIB_PATH = %r\n"
+        "import paper_2509_20081_amd as db\n"
+        "try:\n"
+        "    db.KernelSet(kernel_size=5)\n"
+        "except RuntimeError as e:\n"
+        "    assert 'is not built' in str(e), e\n"
+        "    print('raised')\n"
+    ) % (os.path.dirname(os.path.dirname(os.path.abspath(__file__))), str(tmp_path / "libdbtsdf.so"))
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0 and out.stdout.strip() == "raised", (out.stdout, out.stderr)
