@@ -243,8 +243,14 @@ hipError_t launch_count_diff(const uint32_t *a, const uint32_t *b, uint64_t n, u
 // header (vertex count m | 16 when fanned from its centre) and its m edge
 // numbers, from the smallest.
 constexpr uint32_t kMeshCaseBytes = 24;
+// Per case, the same triangles listed one by one (in the loops' order): three
+// vertex codes each, an edge number (0-11), or kMeshCentre | p for the centre
+// of the loop whose header sits at byte p of the case's entry in b.
+constexpr uint32_t kMeshTriBytes = 24;   // at most 7 triangles per case
+constexpr uint8_t kMeshCentre = 0x80;
 struct MeshTable {
     uint8_t b[256][kMeshCaseBytes];
+    uint8_t tri[256][kMeshTriBytes];
 };
 const MeshTable &mesh_table();
 

@@ -1441,10 +1441,16 @@ __device__ __forceinline__ uint32_t mesh_low_corner(uint32_t e) {
 }
 
 __global__ __launch_bounds__(kMeshThreads) void k_mesh(MeshArgs m) {
-    __shared__ uint32_t tab[256 * kMeshCaseBytes / 4];
-    for (uint32_t i = threadIdx.x; i < 256 * kMeshCaseBytes / 4; i += blockDim.x) tab[i] = m.table[i];
+    constexpr uint32_t kTabWords = 256 * (kMeshCaseBytes + kMeshTriBytes) / 4;
+    static_assert(sizeof(MeshTable) == 4 * kTabWords, "MeshTable layout");
+    __shared__ uint32_t tab[kTabWords];
+    for (uint32_t i = threadIdx.x; i < kTabWords; i += blockDim.x) tab[i] = m.table[i];
     __syncthreads();
     auto tb = [&](uint32_t cs, uint32_t k) { return (tab[cs * (kMeshCaseBytes / 4) + k / 4] >> (8 * (k % 4))) & 255u; };
+    auto tt = [&](uint32_t cs, uint32_t k) {   // the triangle list (kMeshTriBytes per case, after b)
+        const uint32_t w = 256u * (kMeshCaseBytes / 4) + cs * (kMeshTriBytes / 4) + k / 4;
+        return (tab[w] >> (8 * (k % 4))) & 255u;
+    };
     const uint32_t l = lane();
     const uint32_t runs_x = (m.nc[0] + kMeshRun - 1) / kMeshRun;
     const uint64_t n_runs = (uint64_t)runs_x * m.nc[1];
@@ -1517,89 +1523,92 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh(MeshArgs m) {
             unsigned long long run_base = first;   // first slot of the next noted step
             uint32_t loaded = 0xFFFFFFFEu;   // step whose upper layer (pa, pb) holds (none yet)
             int pa = 0, pb = 0;
+            const uint32_t i0 = m.lo[0] + rx * kMeshRun;   // voxel column of lane 0
             while (steps) {
-            const uint32_t s = (uint32_t)__builtin_ctzll(steps);
-            steps &= steps - 1ull;
-            const uint32_t k = m.lo[2] + k0 + s;
-            if (loaded + 1u != s) layer(k, pa, pb);
-            int ca, cb, d[8];
-            layer(k + 1, ca, cb);
-            const uint32_t cs = corners(pa, pb, ca, cb, d);
-            pa = ca;
-            pb = cb;
-            loaded = s;
-            const uint32_t n_t = has_cube ? tb(cs, 0) : 0u;
-            const uint32_t inc_t = wave_incl_scan_u32(n_t);
-            unsigned long long slot = run_base + (inc_t - n_t);
-            run_base += __shfl(inc_t, 63, 64);
-            if (n_t == 0u) continue;
-            // vertex of crossed edge e
-            auto vtx = [&](uint32_t e, float &x, float &y, float &z) {
-                const uint32_t a = e >> 2, clo = mesh_low_corner(e), chi = clo | (1u << a);
-                const uint32_t u[3] = {i + (clo & 1u), j + ((clo >> 1) & 1u), k + (clo >> 2)};
-                float c[3];
+                const uint32_t s = (uint32_t)__builtin_ctzll(steps);
+                steps &= steps - 1ull;
+                const uint32_t k = m.lo[2] + k0 + s;
+                if (loaded + 1u != s) layer(k, pa, pb);
+                int ca, cb, d[8];
+                layer(k + 1, ca, cb);
+                const uint32_t cs = corners(pa, pb, ca, cb, d);
+                pa = ca;
+                pb = cb;
+                loaded = s;
+                const uint32_t n_t = has_cube ? tb(cs, 0) : 0u;
+                const uint32_t inc_t = wave_incl_scan_u32(n_t);
+                const uint32_t excl = inc_t - n_t;
+                const uint32_t tot = __shfl(inc_t, 63, 64);
+                // The step's triangles are written one per lane, so that the
+                // whole wavefront works and its stores are contiguous:
+                // triangle t belongs to the last cube (lane) c whose first
+                // triangle number excl[c] <= t, as its number t - excl[c].
+                for (uint32_t t0 = 0; t0 < tot; t0 += 64u) {
+                    const uint32_t t = t0 + l;
+                    uint32_t c = 0;
 #pragma unroll
-                for (int t = 0; t < 3; ++t) {
-                    const float h = (float)u[t] + 0.5f;
-                    const float hs = h * m.s;
-                    c[t] = m.origin[t] + hs;
-                }
-                const float dlo = (float)d[clo], dhi = (float)d[chi];
-                const float den = dlo - dhi;
-                const float tt = dlo / den;
-                const float ts = tt * m.s;
-                c[a] = c[a] + ts;
-                x = c[0];
-                y = c[1];
-                z = c[2];
-            };
-            auto put = [&](float ax, float ay, float az, float bx, float by, float bz, float cx, float cy, float cz) {
-                if (slot < m.cap) {
-                    float *o = m.out + 9ull * slot;
-                    o[0] = ax; o[1] = ay; o[2] = az;
-                    o[3] = bx; o[4] = by; o[5] = bz;
-                    o[6] = cx; o[7] = cy; o[8] = cz;
-                }
-                ++slot;
-            };
-            const uint32_t n_loops = tb(cs, 1);
-            uint32_t pos = 2;
-            for (uint32_t L = 0; L < n_loops; ++L) {
-                const uint32_t hdr = tb(cs, pos++), mm = hdr & 15u;
-                if (hdr & 16u) {
-                    // fanned from the centre: the mean of the loop's vertices
-                    float sx, sy, sz;
-                    vtx(tb(cs, pos), sx, sy, sz);
-                    for (uint32_t w = 1; w < mm; ++w) {
-                        float x, y, z;
-                        vtx(tb(cs, pos + w), x, y, z);
-                        sx = sx + x;
-                        sy = sy + y;
-                        sz = sz + z;
+                    for (uint32_t b = 32u; b; b >>= 1)
+                        if ((uint32_t)__shfl((int)excl, (int)(c + b), 64) <= t) c += b;
+                    const uint32_t jt = t - (uint32_t)__shfl((int)excl, (int)c, 64);
+                    const uint32_t ccs = (uint32_t)__shfl((int)cs, (int)c, 64);
+                    int dd[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) dd[q] = __shfl(d[q], (int)c, 64);
+                    if (t >= tot) continue;
+                    const uint32_t ic = i0 + c;
+                    // vertex of crossed edge e of cube (ic, j, k)
+                    auto vtx = [&](uint32_t e, float &x, float &y, float &z) {
+                        const uint32_t a = e >> 2, clo = mesh_low_corner(e), chi = clo | (1u << a);
+                        const uint32_t u[3] = {ic + (clo & 1u), j + ((clo >> 1) & 1u), k + (clo >> 2)};
+                        float cc[3];
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) {
+                            const float h = (float)u[q] + 0.5f;
+                            const float hs = h * m.s;
+                            cc[q] = m.origin[q] + hs;
+                        }
+                        const float dlo = (float)dd[clo], dhi = (float)dd[chi];
+                        const float den = dlo - dhi;
+                        const float tv = dlo / den;
+                        const float ts = tv * m.s;
+                        cc[a] = cc[a] + ts;
+                        x = cc[0];
+                        y = cc[1];
+                        z = cc[2];
+                    };
+                    float v[9];
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        const uint32_t code = tt(ccs, 3u * jt + (uint32_t)q);
+                        if (code & kMeshCentre) {
+                            // the centre of the loop whose header is at byte p: the
+                            // mean of its vertices, summed in loop order
+                            const uint32_t p = code & 127u, mm = tb(ccs, p) & 15u;
+                            float sx, sy, sz;
+                            vtx(tb(ccs, p + 1u), sx, sy, sz);
+                            for (uint32_t w = 1; w < mm; ++w) {
+                                float x, y, z;
+                                vtx(tb(ccs, p + 1u + w), x, y, z);
+                                sx = sx + x;
+                                sy = sy + y;
+                                sz = sz + z;
+                            }
+                            const float fm = (float)mm;
+                            v[3 * q + 0] = sx / fm;
+                            v[3 * q + 1] = sy / fm;
+                            v[3 * q + 2] = sz / fm;
+                        } else {
+                            vtx(code, v[3 * q + 0], v[3 * q + 1], v[3 * q + 2]);
+                        }
                     }
-                    const float fm = (float)mm;
-                    const float cx = sx / fm, cy = sy / fm, cz = sz / fm;
-                    for (uint32_t w = 0; w < mm; ++w) {
-                        float ax, ay, az, bx, by, bz;
-                        vtx(tb(cs, pos + w), ax, ay, az);
-                        vtx(tb(cs, pos + (w + 1) % mm), bx, by, bz);
-                        put(cx, cy, cz, ax, ay, az, bx, by, bz);
-                    }
-                } else {
-                    float x0, y0, z0, px, py, pz;
-                    vtx(tb(cs, pos), x0, y0, z0);
-                    vtx(tb(cs, pos + 1), px, py, pz);
-                    for (uint32_t w = 2; w < mm; ++w) {
-                        float x, y, z;
-                        vtx(tb(cs, pos + w), x, y, z);
-                        put(x0, y0, z0, px, py, pz, x, y, z);
-                        px = x;
-                        py = y;
-                        pz = z;
+                    const unsigned long long slot = run_base + t;
+                    if (slot < m.cap) {
+                        float *o = m.out + 9ull * slot;
+#pragma unroll
+                        for (int q = 0; q < 9; ++q) o[q] = v[q];
                     }
                 }
-                pos += mm;
-            }
+                run_base += tot;
             }
         }
     }

@@ -95,6 +95,31 @@ void build_case(int cs, uint8_t *out) {
     out[1] = (uint8_t)n_loops;
 }
 
+// The case's triangles one by one: a loop fanned from its first edge gives
+// (e_0, e_(w-1), e_w) for w = 2 .. m-1, one fanned from its centre C gives
+// (C, e_w, e_(w+1 mod m)) for w = 0 .. m-1.
+void list_triangles(const uint8_t *cs, uint8_t *tri) {
+    int pos = 2, t = 0;
+    for (int L = 0; L < cs[1]; ++L) {
+        const int hdr = pos, m = cs[pos] & 15;
+        const uint8_t *e = cs + pos + 1;
+        if (cs[pos] & 16) {
+            for (int w = 0; w < m; ++w, ++t) {
+                tri[3 * t + 0] = (uint8_t)(kMeshCentre | hdr);
+                tri[3 * t + 1] = e[w];
+                tri[3 * t + 2] = e[(w + 1) % m];
+            }
+        } else {
+            for (int w = 2; w < m; ++w, ++t) {
+                tri[3 * t + 0] = e[0];
+                tri[3 * t + 1] = e[w - 1];
+                tri[3 * t + 2] = e[w];
+            }
+        }
+        pos += 1 + m;
+    }
+}
+
 }  // namespace
 
 const MeshTable &mesh_table() {
@@ -103,7 +128,9 @@ const MeshTable &mesh_table() {
     std::call_once(once, [] {
         for (int cs = 0; cs < 256; ++cs) {
             std::fill(t.b[cs], t.b[cs] + kMeshCaseBytes, (uint8_t)0);
+            std::fill(t.tri[cs], t.tri[cs] + kMeshTriBytes, (uint8_t)0);
             build_case(cs, t.b[cs]);
+            list_triangles(t.b[cs], t.tri[cs]);
         }
     });
     return t;
