@@ -333,7 +333,30 @@ def run_mesh(torch, g, dims, reps=3):
                 roofline=dict(bound="hbm", achieved=nbytes / (t * 1e-3) / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
                               frac=nbytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS,
                               per_launch="8 B per voxel (both planes read once) + 36 B per triangle written"),
-                timing="HIP events around one extraction call (best of %d), whole grid" % reps)
+                timing="HIP events around one extraction call (best of %d), whole grid" % reps,
+                points=run_points(torch, g, dims, reps))
+
+
+def run_points(torch, g, dims, reps=3):
+    """Point export (centres of the occupied contact voxels) of the whole grid, one pass into a buffer
+    sized by a counting call, timed like the mesh export."""
+    n = int(g.extract_points().shape[0])
+    out = torch.empty((max(n, 1), 3), dtype=torch.float32, device="cuda")
+    g.extract_points(out=out)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.extract_points(out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    t = min(ms)
+    nbytes = 8.0 * dims[0] * dims[1] * dims[2] + 12.0 * n
+    return dict(points=n, ms=t, roofline=dict(bound="hbm", achieved=nbytes / (t * 1e-3) / 1e9, peak=HBM_PEAK_GBS,
+                                              unit="GB/s", frac=nbytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                              per_launch="8 B per voxel read + 12 B per point written"))
 
 
 def copy_calibration(torch, nbytes=1 << 30):

@@ -356,11 +356,23 @@ class Grid:
             raise ValueError(f"mesh has {int(n.value)} triangles, out holds {out.shape[0]}")
         return out[: int(n.value)]
 
-    def extract_points(self, lo=None, hi=None):
+    def extract_points(self, lo=None, hi=None, out=None):
         """Centres of the occupied contact voxels (mask 0, sign 0) of the box [lo, hi): a (n, 3) float32 CUDA
-        tensor (rows in no fixed order, x order within a row). See write_point_cloud for CSV / PCD files."""
+        tensor (rows in no fixed order, x order within a row). With `out` (a CUDA float32 (cap, 3) tensor)
+        one pass writes into it and returns the filled rows; ValueError if it is too small. See
+        write_point_cloud for CSV / PCD files."""
         import torch
         lo_a, hi_a, _ = self._box(lo, hi)
+        if out is not None:
+            if out.dtype != torch.float32 or not out.is_cuda or out.dim() != 2 or out.shape[1] != 3 \
+                    or not out.is_contiguous():
+                raise ValueError("out must be a contiguous (cap, 3) float32 CUDA tensor")
+            n = C.c_uint64()
+            L.check(L.lib().dbtsdf_extract_points(self._h, lo_a, hi_a, C.c_void_p(out.data_ptr()), out.shape[0],
+                                                  C.byref(n)), "extract_points")
+            if int(n.value) > out.shape[0]:
+                raise ValueError(f"the box holds {int(n.value)} points, out holds {out.shape[0]}")
+            return out[: int(n.value)]
         n = C.c_uint64()
         L.check(L.lib().dbtsdf_extract_points(self._h, lo_a, hi_a, None, 0, C.byref(n)), "extract_points")
         dev = self.mask_tensor.device if self.mask_tensor is not None else torch.device("cuda")

@@ -153,3 +153,10 @@ def test_point_export_of_written_planes_and_overflow(db):
     assert int(n.value) == len(ref)
     full = {tuple(r) for r in _rows(ref)}
     assert all(tuple(r) in full for r in _rows(small.cpu().numpy()))
+    # one pass into a caller's buffer; a buffer too small raises
+    buf = torch.full((len(ref) + 5, 3), -1.0, dtype=torch.float32, device="cuda")
+    got2 = g.extract_points(out=buf)
+    assert np.array_equal(_rows(got2.cpu().numpy()), _rows(ref))
+    assert bool((buf[len(ref):] == -1.0).all())
+    with pytest.raises(ValueError):
+        g.extract_points(out=torch.zeros((len(ref) - 1, 3), dtype=torch.float32, device="cuda"))
