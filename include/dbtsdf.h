@@ -25,8 +25,10 @@
  *   - No call throws; every failure is a dbtsdf_status.
  *   - Arguments are validated before anything is enqueued; on error the grid
  *     is unchanged.
- *   - Device work is enqueued on the grid's HIP stream and is asynchronous;
- *     results (grid contents, statistics) are valid after dbtsdf_sync().
+ *   - Device work is enqueued on the grid's HIP stream and is asynchronous
+ *     unless an entry point says otherwise (the exports, and integration
+ *     with DBTSDF_STRATEGY_SORT, wait for the stream); results (grid
+ *     contents, statistics) are valid after dbtsdf_sync().
  *   - A grid must not be used from two threads at once; different grids may.
  *   - Host pointers are only read during the call unless stated otherwise.
  */
