@@ -353,10 +353,12 @@ def run_points(torch, g, dims, reps=3):
         torch.cuda.synchronize()
         ms.append(e0.elapsed_time(e1))
     t = min(ms)
-    nbytes = 8.0 * dims[0] * dims[1] * dims[2] + 12.0 * n
+    n_zero = int((g.mask_tensor == 0).sum().item())   # voxels whose packed word the export must read
+    nbytes = 4.0 * dims[0] * dims[1] * dims[2] + 4.0 * n_zero + 12.0 * n
     return dict(points=n, ms=t, roofline=dict(bound="hbm", achieved=nbytes / (t * 1e-3) / 1e9, peak=HBM_PEAK_GBS,
                                               unit="GB/s", frac=nbytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                                              per_launch="8 B per voxel read + 12 B per point written"))
+                                              per_launch="4 B per voxel (mask) + 4 B per voxel of mask 0 (packed) "
+                                                         "read + 12 B per point written"))
 
 
 def copy_calibration(torch, nbytes=1 << 30):

@@ -1616,49 +1616,78 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh(MeshArgs m) {
 
 // Point export: the centres of the occupied contact voxels (a return landed
 // there, mask 0, and the hit counter confirmed it, sign 0). A wavefront takes
-// one grid row of the box at a time: a counting pass, one atomic to reserve
-// the row's room, then a writing pass with the lanes' ranks from a ballot.
+// kPointRows consecutive rows of the box: a counting pass (four 64-voxel
+// pieces of a row loaded together, ballots counted), one atomic to reserve
+// the group's room, then the writing pass with the lanes' ranks from the
+// ballots (its loads mostly hit the caches the counting pass filled).
+constexpr uint32_t kPointRows = 8;
 __global__ __launch_bounds__(kMeshThreads) void k_points(MeshArgs m) {
     const uint32_t l = lane();
     const uint64_t n_rows = (uint64_t)m.nc[1] * m.nc[2];
+    const uint64_t n_groups = (n_rows + kPointRows - 1) / kPointRows;
     const uint32_t wpb = blockDim.x >> 6;
     const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const unsigned long long below = l ? ((1ull << l) - 1ull) : 0ull;
-    for (uint64_t row = (uint64_t)blockIdx.x * wpb + wid; row < n_rows; row += (uint64_t)gridDim.x * wpb) {
-        const uint32_t j = m.lo[1] + (uint32_t)(row % m.nc[1]), k = m.lo[2] + (uint32_t)(row / m.nc[1]);
+    const uint32_t W = m.nc[0];
+    // ballots of the occupied voxels of row r, pieces x0 .. x0 + 255
+    auto ballots = [&](uint64_t r, uint32_t x0, unsigned long long bal[4]) {
+        const uint32_t j = m.lo[1] + (uint32_t)(r % m.nc[1]), k = m.lo[2] + (uint32_t)(r / m.nc[1]);
         const uint64_t base = m.lo[0] + (uint64_t)m.nx * (j + (uint64_t)m.ny * k);
-        auto occupied = [&](uint32_t x) {
-            if (x >= m.nc[0]) return false;
-            return m.mask[base + x] == 0u && (m.packed[base + x] >> 31) == 0u;
-        };
+        uint32_t mk[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t x = x0 + 64u * (uint32_t)u + l;
+            mk[u] = x < W ? m.mask[base + x] : 1u;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t x = x0 + 64u * (uint32_t)u + l;
+            const bool occ = mk[u] == 0u && (m.packed[base + x] >> 31) == 0u;   // packed read only where mask is 0
+            bal[u] = __ballot(occ);
+        }
+    };
+    for (uint64_t grp = (uint64_t)blockIdx.x * wpb + wid; grp < n_groups; grp += (uint64_t)gridDim.x * wpb) {
+        const uint64_t r0 = grp * kPointRows, r1 = min(r0 + kPointRows, n_rows);
         uint32_t cnt = 0;
-        for (uint32_t x0 = 0; x0 < m.nc[0]; x0 += 64u) cnt += __popcll(__ballot(occupied(x0 + l)));
+        for (uint64_t r = r0; r < r1; ++r)
+            for (uint32_t x0 = 0; x0 < W; x0 += 256u) {
+                unsigned long long bal[4];
+                ballots(r, x0, bal);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) cnt += (uint32_t)__popcll(bal[u]);
+            }
         if (cnt == 0u) continue;
         unsigned long long first = 0;
         if (l == 0u) first = atomicAdd(m.count, (unsigned long long)cnt);
         first = __shfl(first, 0, 64);
         if (!m.out) continue;   // counting only
-        for (uint32_t x0 = 0; x0 < m.nc[0]; x0 += 64u) {
-            const bool ok = occupied(x0 + l);
-            const unsigned long long bits = __ballot(ok);
-            if (ok) {
-                const unsigned long long slot = first + __popcll(bits & below);
-                if (slot < m.cap) {
-                    const uint32_t u[3] = {m.lo[0] + x0 + l, j, k};
-                    float c[3];
+        for (uint64_t r = r0; r < r1; ++r) {
+            const uint32_t j = m.lo[1] + (uint32_t)(r % m.nc[1]), k = m.lo[2] + (uint32_t)(r / m.nc[1]);
+            for (uint32_t x0 = 0; x0 < W; x0 += 256u) {
+                unsigned long long bal[4];
+                ballots(r, x0, bal);
 #pragma unroll
-                    for (int t = 0; t < 3; ++t) {
-                        const float h = (float)u[t] + 0.5f;
-                        const float hs = h * m.s;
-                        c[t] = m.origin[t] + hs;
+                for (int u = 0; u < 4; ++u) {
+                    if ((bal[u] >> l) & 1ull) {
+                        const unsigned long long slot = first + (unsigned long long)__popcll(bal[u] & below);
+                        if (slot < m.cap) {
+                            const uint32_t uu[3] = {m.lo[0] + x0 + 64u * (uint32_t)u + l, j, k};
+                            float c[3];
+#pragma unroll
+                            for (int t = 0; t < 3; ++t) {
+                                const float h = (float)uu[t] + 0.5f;
+                                const float hs = h * m.s;
+                                c[t] = m.origin[t] + hs;
+                            }
+                            float *o = m.out + 3ull * slot;
+                            o[0] = c[0];
+                            o[1] = c[1];
+                            o[2] = c[2];
+                        }
                     }
-                    float *o = m.out + 3ull * slot;
-                    o[0] = c[0];
-                    o[1] = c[1];
-                    o[2] = c[2];
+                    first += (unsigned long long)__popcll(bal[u]);
                 }
             }
-            first += __popcll(bits);
         }
     }
 }
@@ -1893,8 +1922,8 @@ hipError_t launch_pipeline(const PipeArgs &a, const Tuning &t, uint32_t points_c
 hipError_t launch_points(const MeshArgs &m, hipStream_t st) {
     const unsigned long long rows = (unsigned long long)m.nc[1] * m.nc[2];
     if (rows == 0 || m.nc[0] == 0) return hipSuccess;
-    const unsigned long long wpb = kMeshThreads / 64;
-    const uint32_t blocks = (uint32_t)std::min<unsigned long long>((rows + wpb - 1) / wpb, 16384ull);
+    const unsigned long long wpb = kMeshThreads / 64, groups = (rows + kPointRows - 1) / kPointRows;
+    const uint32_t blocks = (uint32_t)std::min<unsigned long long>((groups + wpb - 1) / wpb, 16384ull);
     k_points<<<blocks, kMeshThreads, 0, st>>>(m);
     return hipGetLastError();
 }
