@@ -830,3 +830,35 @@ def test_revisits_with_generic_kernels(db, strategy, kernel):
         g.sync()
         P.assert_stats_equal(st.as_dict(), ref, traffic=False, what=f"call {k}")
         P.assert_grids_equal(*P.gpu_planes(g), m, p, what=f"call {k}")
+
+
+def test_sweep_argument_errors_leave_grid_unchanged(db):
+    """Bad sweeps are rejected before anything is enqueued: NULL times, an unknown mode, a non-finite end
+    pose, time fractions on the other side of the points or of the wrong length; the grid is unchanged."""
+    import ctypes as C
+    import torch
+    from paper_2509_20081_amd import _lib as L
+    o, g, _ = P.make_pair((32, 32, 32), 0.1, (0.0, 0.0, 0.0), kernel_size=5, binning="cube26", shadow_r2=4)
+    before = [x.copy() for x in P.gpu_planes(g)]
+    pose = np.eye(4, dtype=np.float32)
+    pose[:3, 3] = 1.6
+    pts = P.to_device(synth.random_cloud(np.random.default_rng(3), 100, np.full(3, -1.0), np.full(3, 1.0)))
+    times = torch.linspace(0, 1, 100, device="cuda")
+    p0 = pose.ctypes.data_as(C.c_void_p)
+    bad_end = pose.copy()
+    bad_end[0, 3] = np.inf
+    st = L.ScanStats()
+    for end, tp, mode in ((pose, None, 0), (pose, times, 7), (bad_end, times, 0)):
+        rc = L.lib().dbtsdf_integrate_scan_deskew(g._h, p0, end.ctypes.data_as(C.c_void_p), C.c_void_p(pts.data_ptr()),
+                                                  None if tp is None else C.c_void_p(tp.data_ptr()), 100, 1, mode, 1,
+                                                  C.byref(st))
+        assert rc == 1   # DBTSDF_ERR_INVALID_ARG
+    with pytest.raises(ValueError):
+        g.integrate(pose, pts, pose_end=pose, times=times.cpu())          # host times, device points
+    with pytest.raises(ValueError):
+        g.integrate(pose, pts, pose_end=pose, times=times[:50])           # wrong length
+    with pytest.raises(ValueError):
+        g.integrate(pose, pts, pose_end=pose)                             # no times
+    g.sync()
+    after = P.gpu_planes(g)
+    assert np.array_equal(after[0], before[0]) and np.array_equal(after[1], before[1])
