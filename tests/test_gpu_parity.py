@@ -765,8 +765,9 @@ def test_sort_strategy_wide_keys(db):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("strategy", ["atomic", "sort"])
 @pytest.mark.parametrize("use_graph", [True, False])
-def test_batched_sweeps_match_oracle(db, use_graph):
+def test_batched_sweeps_match_oracle(db, use_graph, strategy):
     """Motion-compensated sweeps of three grids of different sizes in one launch (the same grid twice),
     device and then host points, graph-replayed or direct: statistics and grids equal the oracle's."""
     import torch
@@ -774,6 +775,8 @@ def test_batched_sweeps_match_oracle(db, use_graph):
     pairs = [P.make_pair(d, 0.1, (0.0, 0.0, 0.0), kernel_size=7, binning="cube26", shadow_r2=9, hit_threshold=2)
              for d in sizes]
     refs = [o.new_grid() for o, _, _ in pairs]
+    for _, g, _ in pairs:
+        g.set_tuning(strategy=strategy)
     rng = np.random.default_rng(51)
     b = db.Batch(use_graph=use_graph)
     for rnd in range(3):
