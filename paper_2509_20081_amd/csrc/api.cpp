@@ -8,6 +8,8 @@
 #include <cstring>
 #include <unordered_map>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "runtime.h"
 
 using namespace dbtsdf;
@@ -15,6 +17,15 @@ using namespace dbtsdf;
 namespace dbtsdf {
 
 static thread_local std::string g_err;
+
+// A roctx range over an entry point's host work (rocprofv3 --marker-trace
+// shows it beside the kernels it enqueued).
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 void set_error(const std::string &msg) { g_err = msg; }
 
 dbtsdf_status check_hip(hipError_t e, const char *what, dbtsdf_grid *g) {
@@ -839,6 +850,7 @@ dbtsdf_status dbtsdf_integrate_scan(dbtsdf_grid *g, const float pose[16], const 
 static dbtsdf_status integrate_plain(dbtsdf_grid *g, const float pose[16], const float *pose_end, int mode,
                                      const float *points, const float *times, uint64_t n, uint32_t every,
                                      int points_on_device, dbtsdf_scan_stats *stats) {
+    TraceRange trace_range("dbtsdf_integrate_scan");
     if (!g || !pose) return invalid("NULL argument");
     if (every == 0) return invalid("every must be >= 1");
     if (g->poisoned) {
@@ -896,6 +908,7 @@ dbtsdf_status dbtsdf_integrate_scan_deskew(dbtsdf_grid *g, const float pose_star
 }
 
 dbtsdf_status dbtsdf_sync(dbtsdf_grid *g) {
+    TraceRange trace_range("dbtsdf_sync");
     if (!g) return invalid("NULL grid");
     if (g->poisoned) return DBTSDF_ERR_POISONED;
     hipError_t e = hipStreamSynchronize(g->stream);
@@ -929,6 +942,7 @@ static dbtsdf_status gather(dbtsdf_grid *g, const uint32_t lo[3], const uint32_t
 
 dbtsdf_status dbtsdf_read_voxels(dbtsdf_grid *g, const uint32_t lo[3], const uint32_t hi[3], uint32_t *mask_out,
                                  uint32_t *packed_out) {
+    TraceRange trace_range("dbtsdf_read_voxels");
     dbtsdf_status s = check_box(g, lo, hi);
     if (s != DBTSDF_OK) return s;
     if (g->poisoned) return DBTSDF_ERR_POISONED;
@@ -947,6 +961,7 @@ dbtsdf_status dbtsdf_read_distance(dbtsdf_grid *g, const uint32_t lo[3], const u
 
 dbtsdf_status dbtsdf_extract_mesh(dbtsdf_grid *g, const uint32_t lo[3], const uint32_t hi[3], float *tris_dev,
                                   uint64_t max_tris, uint64_t *n_tris) {
+    TraceRange trace_range("dbtsdf_extract_mesh");
     if (!g || !n_tris) return invalid("NULL argument");
     if (!tris_dev && max_tris) return invalid("NULL triangle buffer with max_tris > 0");
     *n_tris = 0;
@@ -1002,6 +1017,7 @@ dbtsdf_status dbtsdf_extract_mesh(dbtsdf_grid *g, const uint32_t lo[3], const ui
 
 dbtsdf_status dbtsdf_extract_points(dbtsdf_grid *g, const uint32_t lo[3], const uint32_t hi[3], float *xyz_dev,
                                     uint64_t max_points, uint64_t *n_points) {
+    TraceRange trace_range("dbtsdf_extract_points");
     if (!g || !n_points) return invalid("NULL argument");
     if (!xyz_dev && max_points) return invalid("NULL point buffer with max_points > 0");
     *n_points = 0;
@@ -1150,6 +1166,7 @@ static dbtsdf_status batch_impl(dbtsdf_batch *b, uint32_t n_scans, dbtsdf_grid *
                                 const float *poses_end, int mode, const float *const *points,
                                 const float *const *times, const uint64_t *n, int points_on_device,
                                 dbtsdf_scan_stats *stats) {
+    TraceRange trace_range("dbtsdf_batch_integrate");
     if (!b) return invalid("NULL batch");
     if (n_scans == 0) return DBTSDF_OK;
     if (!grids || !poses || !points || !n) return invalid("NULL argument");
