@@ -865,3 +865,63 @@ def test_sweep_argument_errors_leave_grid_unchanged(db):
     g.sync()
     after = P.gpu_planes(g)
     assert np.array_equal(after[0], before[0]) and np.array_equal(after[1], before[1])
+
+
+def test_server_malformed_and_refused_scans(db):
+    """Serving with bad input: a non-finite pose, an unknown or removed map and a full queue are refused at
+    submit (nothing enqueued); scans with non-finite, zero-range and out-of-map returns, and an empty scan,
+    complete with the oracle's statistics; the map equals the oracle's grid after them."""
+    from paper_2509_20081_amd import _lib as L
+    from paper_2509_20081_amd.serve import Server
+    dims, vs, org = (64, 64, 48), 0.1, (0.0, 0.0, 0.0)
+    ks = db.KernelSet(kernel_size=7, binning="cube26", shadow_r2=9)
+    from oracle.oracle import Oracle
+    o = Oracle(dims, vs, org, kernel_size=7, binning="cube26", shadow_r2=9)
+    m, p = o.new_grid()
+    srv = Server(n_streams=2, max_batch_scans=4, queue_capacity=64)
+    mid = srv.add_map(dims, vs, org, ks)
+    gone = srv.add_map((32, 32, 32), vs, org, ks)
+    srv.remove_map(gone)
+    rng = np.random.default_rng(71)
+    pose = synth.random_pose(rng, np.array([3.0, 3.0, 2.2]), np.array([3.4, 3.4, 2.6]))
+    bad_pose = pose.copy()
+    bad_pose[1, 3] = np.nan
+    scans = []
+    for k in range(6):
+        pts = synth.random_cloud(rng, 800, np.full(3, -3.5), np.full(3, 3.5))
+        pts[::23] = np.nan                   # non-finite returns
+        pts[5::31] = 0.0                     # zero range
+        pts[7::29] *= 40.0                   # far outside the map
+        scans.append(pts if k != 3 else pts[:0])   # one empty scan
+    for bad in ((mid, bad_pose), (gone, pose), (mid + 7, pose)):
+        with pytest.raises(L.DbtsdfError):
+            srv.submit(bad[0], bad[1], scans[0])
+    tickets = [srv.submit(mid, pose, pts) for pts in scans]
+    srv.drain()
+    done = {c["ticket"]: c for c in srv.poll(100)}
+    assert sorted(done) == sorted(tickets)
+    for t, pts in zip(tickets, scans):
+        ref = o.integrate(m, p, pose, pts)
+        assert done[t]["status"] == 0
+        P.assert_stats_equal(done[t]["stats"], ref, traffic=False, what=f"ticket {t}")
+    view = srv.map_grid(mid, dims, ks)
+    got = view.read_voxels()
+    P.assert_grids_equal(got[0], got[1], m, p, what="served map after malformed scans")
+    # a full queue refuses with BUSY: 500 submits of tiny scans (microseconds each on the host) into a
+    # queue of 2 that one stream drains a scan per launch sequence (tens of microseconds each)
+    tiny = synth.random_cloud(rng, 8, np.full(3, -1.0), np.full(3, 1.0))
+    srv2 = Server(n_streams=1, max_batch_scans=1, queue_capacity=2)
+    mid2 = srv2.add_map(dims, vs, org, ks)
+    busy = accepted = 0
+    for _ in range(500):
+        try:
+            srv2.submit(mid2, pose, tiny)
+            accepted += 1
+        except L.DbtsdfError as e:
+            assert e.status == 6   # DBTSDF_ERR_BUSY
+            busy += 1
+    srv2.drain()
+    assert busy > 0 and accepted >= 2
+    assert len(srv2.poll(1000)) == accepted
+    srv2.close()
+    srv.close()
