@@ -155,6 +155,9 @@ class KernelSet:
         self._h = h
         self.kernel_size = kernel_size
         self.binning = binning
+        self.params = dict(kernel_size=int(kernel_size), binning=binning, bins_az=int(bins_az), bins_el=int(bins_el),
+                           shadow_r2=int(shadow_r2), metric=metric, shadow_model=shadow_model,
+                           cone_deg=float(cone_deg))
         self.n_bins = int(L.lib().dbtsdf_kernel_set_n_bins(h))
 
     def export(self):

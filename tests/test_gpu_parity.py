@@ -925,3 +925,36 @@ def test_server_malformed_and_refused_scans(db):
     assert len(srv2.poll(1000)) == accepted
     srv2.close()
     srv.close()
+
+
+def test_checkpoint_and_resume(db, tmp_path):
+    """A grid saved after some scans and loaded into a new grid holds the same planes; integrating the
+    remaining scans into the restored grid gives the oracle's grid for the whole sequence. A kernel set
+    with other parameters is refused; the file loads without pickle."""
+    from paper_2509_20081_amd.checkpoint import load_checkpoint, save_checkpoint
+    dims = (48, 44, 40)
+    o, g, ks = P.make_pair(dims, 0.1, (0.2, -0.1, 0.0), kernel_size=7, binning="cube26", shadow_r2=9,
+                           hit_threshold=3, dedup=False)
+    m, p = o.new_grid()
+    rng = np.random.default_rng(81)
+    centre = np.array((0.2, -0.1, 0.0)) + np.array(dims) * 0.1 / 2
+    scans = [(synth.random_pose(rng, centre - 0.2, centre + 0.2),
+              synth.random_cloud(rng, 900, -np.array(dims) * 0.04, np.array(dims) * 0.04)) for _ in range(5)]
+    for pose, pts in scans[:3]:
+        o.integrate(m, p, pose, pts)
+        g.integrate(pose, P.to_device(pts))
+    path = str(tmp_path / "grid.npz")
+    save_checkpoint(path, g)
+    with np.load(path, allow_pickle=False) as z:
+        assert z["mask"].dtype == np.uint32 and z["mask"].shape == dims[::-1]
+    g2 = load_checkpoint(path, planes="torch")
+    assert g2.kernel_set.params == ks.params and g2.dims == dims
+    P.assert_grids_equal(*P.gpu_planes(g2), m, p, what="restored")
+    for pose, pts in scans[3:]:
+        ref = o.integrate(m, p, pose, pts)
+        st = g2.integrate(pose, P.to_device(pts))
+        g2.sync()
+        P.assert_stats_equal(st.as_dict(), ref, traffic=False, what="resumed scan")
+    P.assert_grids_equal(*P.gpu_planes(g2), m, p, what="after resuming")
+    with pytest.raises(ValueError):
+        load_checkpoint(path, kernel_set=db.KernelSet(kernel_size=5, binning="cube26", shadow_r2=9))
