@@ -539,6 +539,18 @@ dbtsdf_status dbtsdf_server_map_grid(dbtsdf_server *s, uint32_t map_id, dbtsdf_g
 dbtsdf_status dbtsdf_server_submit(dbtsdf_server *s, uint32_t map_id, const float pose[16], const float *points,
                                    uint64_t n, uint64_t t_arrival_ns, uint64_t *ticket);
 
+/*
+ * Queue one motion-compensated sweep (as dbtsdf_integrate_scan_deskew):
+ * pose_start and pose_end host 4x4 fp32, mode a dbtsdf_deskew, n points and
+ * n time fractions in [0, 1] (host, copied before return). A launch holds
+ * only requests of one kind (plain scans, or sweeps of one mode); scans of
+ * one map still complete in arrival order. Errors as dbtsdf_server_submit;
+ * a non-finite end pose, NULL times or an unknown mode is INVALID_ARG.
+ */
+dbtsdf_status dbtsdf_server_submit_sweep(dbtsdf_server *s, uint32_t map_id, const float pose_start[16],
+                                         const float pose_end[16], int mode, const float *points, const float *times,
+                                         uint64_t n, uint64_t t_arrival_ns, uint64_t *ticket);
+
 /* Move up to max finished scans into out; *n_out receives the count. Non-blocking. */
 dbtsdf_status dbtsdf_server_poll(dbtsdf_server *s, dbtsdf_completion *out, uint32_t max, uint32_t *n_out);
 

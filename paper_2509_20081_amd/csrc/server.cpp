@@ -33,10 +33,12 @@ struct Request {
     uint64_t ticket = 0;
     uint32_t map = 0;
     float pose[16];
-    float *pts = nullptr;   // pinned host copy
+    float *pts = nullptr;   // pinned host copy: the points, then (a sweep) the time fractions
     size_t cap = 0;         // floats in pts
     uint64_t n = 0;
     uint64_t t_arrival = 0;
+    int kind = -1;          // -1: a plain scan; else a motion-compensated sweep of this dbtsdf_deskew mode
+    float pose_end[16];
 };
 
 struct MapSlot {
@@ -143,13 +145,17 @@ bool dbtsdf_server::launch_free_lanes() {
             if (queue.empty()) break;
             std::unordered_set<uint32_t> blocked;
             uint64_t pts = 0;
+            // one launch holds one kind of request (plain scans, or sweeps of
+            // one mode): the first picked sets it
+            int kind = 0;
             for (auto it = queue.begin(); it != queue.end() && pick.size() < cfg.max_batch_scans;) {
                 MapSlot &m = maps[it->map];
-                if (m.busy || blocked.count(it->map)) {
+                if (m.busy || blocked.count(it->map) || (!pick.empty() && it->kind != kind)) {
                     blocked.insert(it->map);  // keep per-map arrival order
                     ++it;
                     continue;
                 }
+                kind = it->kind;
                 if (!pick.empty() && pts + it->n > cfg.max_batch_points) break;
                 pts += it->n;
                 pick.push_back(*it);
@@ -162,18 +168,24 @@ bool dbtsdf_server::launch_free_lanes() {
         }
         if (pick.empty()) continue;
         const uint32_t n = (uint32_t)pick.size();
-        std::vector<float> poses(16 * (size_t)n);
-        std::vector<const float *> ptrs(n);
+        const int kind = pick[0].kind;
+        std::vector<float> poses(16 * (size_t)n), poses_end(kind >= 0 ? 16 * (size_t)n : 0);
+        std::vector<const float *> ptrs(n), times(n);
         std::vector<uint64_t> counts(n);
         for (uint32_t i = 0; i < n; ++i) {
             std::memcpy(&poses[16 * (size_t)i], pick[i].pose, sizeof(pick[i].pose));
+            if (kind >= 0) std::memcpy(&poses_end[16 * (size_t)i], pick[i].pose_end, sizeof(pick[i].pose_end));
             ptrs[i] = pick[i].pts;
+            times[i] = pick[i].pts + 3 * pick[i].n;
             counts[i] = pick[i].n;
         }
         ln.stats.assign(n, dbtsdf_scan_stats{});
         ln.t_launch = dbtsdf_now_ns();
-        dbtsdf_status s = dbtsdf_batch_integrate(ln.batch, n, grids.data(), poses.data(), ptrs.data(), counts.data(),
-                                                 0, ln.stats.data());
+        dbtsdf_status s =
+            kind < 0 ? dbtsdf_batch_integrate(ln.batch, n, grids.data(), poses.data(), ptrs.data(), counts.data(), 0,
+                                              ln.stats.data())
+                     : dbtsdf_batch_integrate_deskew(ln.batch, n, grids.data(), poses.data(), poses_end.data(), kind,
+                                                     ptrs.data(), times.data(), counts.data(), 0, ln.stats.data());
         hipError_t e = hipSuccess;
         if (s == DBTSDF_OK) e = hipEventRecord(ln.ev, ln.batch->stream);
         ln.reqs = std::move(pick);
@@ -307,17 +319,22 @@ dbtsdf_status dbtsdf_server_map_grid(dbtsdf_server *s, uint32_t map_id, dbtsdf_g
     return DBTSDF_OK;
 }
 
-dbtsdf_status dbtsdf_server_submit(dbtsdf_server *s, uint32_t map_id, const float pose[16], const float *points,
-                                   uint64_t n, uint64_t t_arrival_ns, uint64_t *ticket) {
-    if (!s || !pose || (n && !points)) {
+static dbtsdf_status submit_impl(dbtsdf_server *s, uint32_t map_id, const float pose[16], const float *pose_end,
+                                 int mode, const float *points, const float *times, uint64_t n,
+                                 uint64_t t_arrival_ns, uint64_t *ticket) {
+    if (!s || !pose || (n && !points) || (pose_end && n && !times)) {
         set_error("NULL argument");
         return DBTSDF_ERR_INVALID_ARG;
     }
     for (int k = 0; k < 16; ++k)
-        if (!std::isfinite(pose[k])) {
+        if (!std::isfinite(pose[k]) || (pose_end && !std::isfinite(pose_end[k]))) {
             set_error("pose must be finite");
             return DBTSDF_ERR_INVALID_ARG;
         }
+    if (pose_end && mode != DBTSDF_DESKEW_SE3 && mode != DBTSDF_DESKEW_YAW) {
+        set_error("unknown deskew mode");
+        return DBTSDF_ERR_INVALID_ARG;
+    }
     if (n > kMaxPointsPerCall) return DBTSDF_ERR_OUT_OF_RANGE;
     std::lock_guard<std::mutex> lk(s->mu);
     if (map_id >= s->maps.size() || !s->maps[map_id].grid || s->maps[map_id].removing) {
@@ -332,18 +349,36 @@ dbtsdf_status dbtsdf_server_submit(dbtsdf_server *s, uint32_t map_id, const floa
     r.ticket = s->next_ticket++;
     r.map = map_id;
     std::memcpy(r.pose, pose, sizeof(r.pose));
-    r.pts = s->take_buffer(3 * std::max<uint64_t>(n, 1), &r.cap);
+    r.kind = pose_end ? mode : -1;
+    if (pose_end) std::memcpy(r.pose_end, pose_end, sizeof(r.pose_end));
+    r.pts = s->take_buffer((pose_end ? 4 : 3) * std::max<uint64_t>(n, 1), &r.cap);
     if (!r.pts) {
         set_error("pinned staging allocation failed");
         return DBTSDF_ERR_OUT_OF_MEMORY;
     }
     if (n) std::memcpy(r.pts, points, 12 * n);
+    if (n && pose_end) std::memcpy(r.pts + 3 * n, times, 4 * n);
     r.n = n;
     r.t_arrival = t_arrival_ns;
     s->queue.push_back(r);
     ++s->submitted;
     if (ticket) *ticket = r.ticket;
     return DBTSDF_OK;
+}
+
+dbtsdf_status dbtsdf_server_submit(dbtsdf_server *s, uint32_t map_id, const float pose[16], const float *points,
+                                   uint64_t n, uint64_t t_arrival_ns, uint64_t *ticket) {
+    return submit_impl(s, map_id, pose, nullptr, 0, points, nullptr, n, t_arrival_ns, ticket);
+}
+
+dbtsdf_status dbtsdf_server_submit_sweep(dbtsdf_server *s, uint32_t map_id, const float pose_start[16],
+                                         const float pose_end[16], int mode, const float *points, const float *times,
+                                         uint64_t n, uint64_t t_arrival_ns, uint64_t *ticket) {
+    if (!pose_end) {
+        set_error("NULL argument");
+        return DBTSDF_ERR_INVALID_ARG;
+    }
+    return submit_impl(s, map_id, pose_start, pose_end, mode, points, times, n, t_arrival_ns, ticket);
 }
 
 dbtsdf_status dbtsdf_server_poll(dbtsdf_server *s, dbtsdf_completion *out, uint32_t max, uint32_t *n_out) {

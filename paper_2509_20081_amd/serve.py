@@ -63,6 +63,25 @@ class Server:
                                              C.byref(tk)), "server_submit")
         return int(tk.value)
 
+    def submit_sweep(self, map_id: int, pose_start, pose_end, points, times, deskew="se3",
+                     t_arrival_ns: int | None = None) -> int:
+        """Queue a motion-compensated sweep: return i at time fraction times[i] between the two poses."""
+        from . import DESKEW
+        p0 = np.ascontiguousarray(np.asarray(pose_start, np.float32).reshape(16))
+        p1 = np.ascontiguousarray(np.asarray(pose_end, np.float32).reshape(16))
+        pts = np.ascontiguousarray(np.asarray(points, np.float32).reshape(-1, 3))
+        tt = np.ascontiguousarray(np.asarray(times, np.float32).reshape(-1))
+        if tt.shape[0] != pts.shape[0]:
+            raise ValueError("times must hold one float32 per point")
+        if t_arrival_ns is None:
+            t_arrival_ns = int(L.lib().dbtsdf_now_ns())
+        tk = C.c_uint64()
+        L.check(L.lib().dbtsdf_server_submit_sweep(self._h, map_id, p0.ctypes.data_as(C.c_void_p),
+                                                   p1.ctypes.data_as(C.c_void_p), DESKEW[deskew],
+                                                   pts.ctypes.data_as(C.c_void_p), tt.ctypes.data_as(C.c_void_p),
+                                                   pts.shape[0], t_arrival_ns, C.byref(tk)), "server_submit_sweep")
+        return int(tk.value)
+
     def poll(self, max_n=1024) -> list[dict]:
         buf = (L.Completion * max_n)()
         n = C.c_uint32()

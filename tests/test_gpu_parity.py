@@ -958,3 +958,53 @@ def test_checkpoint_and_resume(db, tmp_path):
     P.assert_grids_equal(*P.gpu_planes(g2), m, p, what="after resuming")
     with pytest.raises(ValueError):
         load_checkpoint(path, kernel_set=db.KernelSet(kernel_size=5, binning="cube26", shadow_r2=9))
+
+
+def test_server_mixes_sweeps_and_plain_scans(db):
+    """Three maps served with plain scans and motion-compensated sweeps of both modes interleaved: every
+    completion carries the oracle's statistics and every map equals the oracle's grid."""
+    from oracle.oracle import Oracle
+    from paper_2509_20081_amd.serve import Server
+    dims, vs = (48, 44, 40), 0.1
+    kk = dict(kernel_size=7, binning="cube26", shadow_r2=9)
+    ks = db.KernelSet(**kk)
+    srv = Server(n_streams=2, max_batch_scans=4)
+    origins = [(0.0, 0.0, 0.0), (0.5, -0.3, 0.1), (-0.2, 0.4, 0.0)]
+    ids = [srv.add_map(dims, vs, org, ks, hit_threshold=2) for org in origins]
+    oracles = [Oracle(dims, vs, org, hit_threshold=2, **kk) for org in origins]
+    refs = [o.new_grid() for o in oracles]
+    rng = np.random.default_rng(91)
+    plan = {}
+    for k in range(6):
+        for i, org in enumerate(origins):
+            centre = np.array(org) + np.array(dims) * vs / 2
+            P0 = synth.random_pose(rng, centre - 0.2, centre + 0.2)
+            pts = synth.random_cloud(rng, int(rng.integers(200, 900)), -np.array(dims) * 0.04, np.array(dims) * 0.04)
+            kind = (k + i) % 3          # 0 plain, 1 se3 sweep, 2 yaw sweep
+            if kind == 0:
+                t = srv.submit(ids[i], P0, pts)
+                plan[t] = (i, P0, None, pts, None, None)
+            else:
+                P1 = P0.copy()
+                P1[:3, :3] = (_turn(rng.normal(size=3) if kind == 1 else (0.0, 0.0, 1.0), rng.uniform(-0.3, 0.3))
+                              @ P0[:3, :3].astype(float)).astype(np.float32)
+                P1[:3, 3] += rng.uniform(-0.1, 0.1, 3).astype(np.float32)
+                times = _sweep_times(rng, len(pts))
+                mode = "se3" if kind == 1 else "yaw"
+                t = srv.submit_sweep(ids[i], P0, P1, pts, times, deskew=mode)
+                plan[t] = (i, P0, P1, pts, times, mode)
+    srv.drain()
+    done = {c["ticket"]: c for c in srv.poll(100)}
+    assert sorted(done) == sorted(plan)
+    for t in sorted(plan):           # tickets rise with arrival, so this is each map's arrival order
+        i, P0, P1, pts, times, mode = plan[t]
+        if P1 is None:
+            ref = oracles[i].integrate(*refs[i], P0, pts)
+        else:
+            ref = oracles[i].integrate_deskew(*refs[i], P0, P1, pts, times, mode)
+        assert done[t]["status"] == 0
+        P.assert_stats_equal(done[t]["stats"], ref, traffic=False, what=f"ticket {t}")
+    for i in range(3):
+        got = srv.map_grid(ids[i], dims, ks).read_voxels()
+        P.assert_grids_equal(got[0], got[1], *refs[i], what=f"served map {i}")
+    srv.close()
