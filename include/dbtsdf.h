@@ -455,6 +455,18 @@ dbtsdf_status dbtsdf_batch_integrate(dbtsdf_batch *b, uint32_t n_scans, dbtsdf_g
                                      int points_on_device, dbtsdf_scan_stats *stats);
 
 /*
+ * The same for callers without a batch context: n_scans scans into grids[i]
+ * with poses[16*i..] and device points[i] (n[i] x 3 fp32), in one launch
+ * sequence on a context the library keeps per device (made on first use,
+ * calls through it serialised). Ordered after earlier work on each grid's
+ * stream and before later work there. With stats (n_scans entries) the call
+ * returns once the batch has finished and the statistics are filled in;
+ * with stats NULL it returns after enqueueing. Errors as dbtsdf_batch_integrate.
+ */
+dbtsdf_status dbtsdf_integrate_batch(uint32_t n_scans, dbtsdf_grid *const *grids, const float *poses,
+                                     const float *const *points, const uint64_t *n, dbtsdf_scan_stats *stats);
+
+/*
  * dbtsdf_batch_integrate for motion-compensated sweeps (as
  * dbtsdf_integrate_scan_deskew, every = 1): scan i runs from poses_start[16*i..]
  * to poses_end[16*i..], return j at time fraction times[i][j]; times[i] lives

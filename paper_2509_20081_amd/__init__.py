@@ -109,6 +109,30 @@ def deskew_constants(pose_start, pose_end, mode="se3"):
     return out
 
 
+def integrate_batch(items) -> list:
+    """items: [(grid, pose, cuda points)] in one launch sequence on the library's own batch context of the
+    grids' device; returns the filled Stats (the call waits for the batch)."""
+    n = len(items)
+    if n == 0:
+        return []
+    grids = (C.c_void_p * n)(*[g._h for g, _, _ in items])
+    poses = np.stack([_f32(p, (16,)) for _, p, _ in items]).astype(np.float32)
+    args = [_points_arg(pts) for _, _, pts in items]
+    if any(a[2] != 1 for a in args):
+        raise ValueError("integrate_batch takes device points")
+    ptrs = (C.c_void_p * n)(*[a[0] for a in args])
+    counts = (C.c_uint64 * n)(*[a[1] for a in args])
+    stats = (L.ScanStats * n)()
+    L.check(L.lib().dbtsdf_integrate_batch(n, grids, poses.ctypes.data_as(C.c_void_p), ptrs, counts, stats),
+            "integrate_batch")
+    out = []
+    for i in range(n):
+        s = Stats()
+        s._c = stats[i]
+        out.append(s)
+    return out
+
+
 def _period(enable, every) -> int:
     if not enable:
         return 0

@@ -104,6 +104,7 @@ SIGNATURES = {
     "dbtsdf_server_remove_map": (C.c_int, [P, U32]),
     "dbtsdf_server_map_grid": (C.c_int, [P, U32, PP]),
     "dbtsdf_server_submit": (C.c_int, [P, U32, P, P, U64, U64, C.POINTER(U64)]),
+    "dbtsdf_integrate_batch": (C.c_int, [U32, P, P, P, P, P]),
     "dbtsdf_server_submit_sweep": (C.c_int, [P, U32, P, P, C.c_int, P, P, U64, U64, C.POINTER(U64)]),
     "dbtsdf_server_poll": (C.c_int, [P, P, U32, C.POINTER(U32)]),
     "dbtsdf_server_drain": (C.c_int, [P]),

@@ -6,6 +6,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <unordered_map>
 
 #include <rocprofiler-sdk-roctx/roctx.h>
@@ -1240,6 +1242,34 @@ dbtsdf_status dbtsdf_batch_integrate(dbtsdf_batch *b, uint32_t n_scans, dbtsdf_g
                                      const float *const *points, const uint64_t *n, int points_on_device,
                                      dbtsdf_scan_stats *stats) {
     return batch_impl(b, n_scans, grids, poses, nullptr, 0, points, nullptr, n, points_on_device, stats);
+}
+
+// One batch context per device for dbtsdf_integrate_batch, made on first use
+// and kept until the process ends; calls through it are serialised.
+dbtsdf_status dbtsdf_integrate_batch(uint32_t n_scans, dbtsdf_grid *const *grids, const float *poses,
+                                     const float *const *points, const uint64_t *n, dbtsdf_scan_stats *stats) {
+    if (n_scans == 0) return DBTSDF_OK;
+    if (!grids || !grids[0]) return invalid("NULL argument");
+    static std::mutex mu;
+    static std::map<int, dbtsdf_batch *> contexts;
+    std::lock_guard<std::mutex> lk(mu);
+    dbtsdf_batch *&b = contexts[grids[0]->device];
+    if (!b) {
+        int cur = 0;
+        hipError_t e = hipGetDevice(&cur);
+        if (e == hipSuccess) e = hipSetDevice(grids[0]->device);
+        if (e != hipSuccess) return check_hip(e, "selecting the grids' device");
+        dbtsdf_status cs = dbtsdf_batch_create(nullptr, 1, &b);
+        (void)hipSetDevice(cur);
+        if (cs != DBTSDF_OK) {
+            b = nullptr;
+            return cs;
+        }
+    }
+    dbtsdf_status s = batch_impl(b, n_scans, grids, poses, nullptr, 0, points, nullptr, n, 1, stats);
+    // the statistics are delivered by the context's sync, which the caller cannot reach
+    if (s == DBTSDF_OK && stats) s = dbtsdf_batch_sync(b);
+    return s;
 }
 
 dbtsdf_status dbtsdf_batch_integrate_deskew(dbtsdf_batch *b, uint32_t n_scans, dbtsdf_grid *const *grids,

@@ -1008,3 +1008,27 @@ def test_server_mixes_sweeps_and_plain_scans(db):
         got = srv.map_grid(ids[i], dims, ks).read_voxels()
         P.assert_grids_equal(got[0], got[1], *refs[i], what=f"served map {i}")
     srv.close()
+
+
+def test_context_free_batch_matches_oracle(db):
+    """dbtsdf_integrate_batch (the library's own batch context): several grids, one of them twice, in one
+    launch; statistics are filled when the call returns and the grids equal the oracle's."""
+    sizes = [(40, 36, 32), (56, 40, 48)]
+    pairs = [P.make_pair(d, 0.1, (0.0, 0.0, 0.0), kernel_size=5, binning="cube26", shadow_r2=4, hit_threshold=2)
+             for d in sizes]
+    refs = [o.new_grid() for o, _, _ in pairs]
+    rng = np.random.default_rng(101)
+    for rnd in range(2):
+        items, plan = [], []
+        for gi in (0, 1, 0):
+            centre = np.array(sizes[gi]) * 0.1 / 2
+            pose = synth.random_pose(rng, centre - 0.2, centre + 0.2)
+            pts = synth.random_cloud(rng, int(rng.integers(100, 1200)), -centre * 0.9, centre * 0.9)
+            items.append((pairs[gi][1], pose, P.to_device(pts)))
+            plan.append((gi, pose, pts))
+        stats = db.integrate_batch(items)
+        for k, (gi, pose, pts) in enumerate(plan):
+            ref = pairs[gi][0].integrate(*refs[gi], pose, pts)
+            P.assert_stats_equal(stats[k].as_dict(), ref, what=f"round {rnd} scan {k}")
+        for gi in range(2):
+            P.assert_grids_equal(*P.gpu_planes(pairs[gi][1]), *refs[gi], what=f"round {rnd} grid {gi}")
