@@ -276,7 +276,8 @@ dbtsdf_status dbtsdf_set_tuning(dbtsdf_grid *g, const dbtsdf_tuning *t);
  * The passes of a call are launched on the grid's stream: directly with the
  * per-point strategy (three passes), or, with the brick strategy, replayed
  * from a HIP graph captured (on a private stream of the grid) the first time
- * a call of that shape is made.
+ * a call of that shape is made; the sort strategy launches directly and
+ * waits for the stream twice to size its sort (see dbtsdf_tuning).
  * Errors: INVALID_ARG, OUT_OF_RANGE (n too large), OUT_OF_MEMORY, DEVICE, POISONED.
  */
 dbtsdf_status dbtsdf_integrate_scan(dbtsdf_grid *g, const float pose[16], const float *points, uint64_t n,
