@@ -146,6 +146,71 @@ def test_azel_shadow_matches_definition():
         assert np.allclose(dirs[b], [math.cos(e) * math.cos(a), math.cos(e) * math.sin(a), math.sin(e)])
 
 
+@pytest.mark.parametrize("baz,bel", [(40, 40), (8, 5), (256, 130)])
+def test_azel_bin_centres_fall_in_their_own_bin(baz, bel):
+    """Every AZEL bin centre (eq. 2 grid: azimuth from +x counter-clockwise, elevation from the
+    nadir) lies in the middle of its own bin, half a bin from each boundary, so binning the
+    centre returns the bin. A centre table shifted by half a bin would sit on a boundary, one
+    counted from the zenith would land in the mirrored elevation row."""
+    o = Oracle(dims=(3,) * 3, voxel_size=1.0, kernel_size=3, binning="azel", bins_az=baz, bins_el=bel,
+               shadow_r2=1)
+    _, _, dirs = o.tables()
+    assert dirs.shape == (baz * bel, 3)
+    got = np.array([o.bin(d) for d in dirs])
+    assert np.array_equal(got, np.arange(baz * bel))
+
+
+def test_azel_two_by_one_reduces_to_cube26_y_faces(golden_dir):
+    """With 2 azimuth bins and 1 elevation bin, bin 0 spans azimuths [0, pi) around +y and bin 1
+    [pi, 2 pi) around -y (elevation centre 0). Their r_s = 3 hemispheres are the closed half-balls
+    dy >= 0 and dy <= 0: the same cell sets as the 26-direction shadows of +y and -y, which are
+    built from an exact integer dot product, 76 cells each (face entry of the golden table)."""
+    sizes = json.load(open(os.path.join(golden_dir, "cube26_shadow_sizes.json")))
+    face = sizes["face"][sizes["r_s"].index(3)]
+    az = Oracle(dims=(7,) * 3, voxel_size=1.0, kernel_size=7, binning="azel", bins_az=2, bins_el=1, shadow_r2=9)
+    cu = Oracle(dims=(7,) * 3, voxel_size=1.0, kernel_size=7, binning="cube26", shadow_r2=9)
+    _, sh_az, dirs = az.tables()
+    _, sh_cu, _ = cu.tables()
+    assert np.allclose(dirs[0], [0.0, 1.0, 0.0], atol=1e-15)
+    assert np.allclose(dirs[1], [0.0, -1.0, 0.0], atol=1e-15)
+    for b, y in ((0, 1), (1, -1)):
+        cb = cu.bin((0.0, float(y), 0.0))
+        assert np.array_equal(sh_az[b], sh_cu[cb])
+        assert int(sh_az[b].sum()) == face
+        # and the directions themselves: +y falls in bin 0, -y in bin 1
+        assert az.bin((0.0, float(y), 0.0)) == b
+
+
+def _ball_offsets(r2):
+    rng = range(-3, 4)
+    return [(x, y, z) for z in rng for y in rng for x in rng if x * x + y * y + z * z <= r2]
+
+
+def test_azel_tilted_bin_shadow_sizes_by_symmetry():
+    """Shadow sizes fixed by the ball's central symmetry (r_s^2 = 9: 123 lattice cells).
+
+    A direction u with no nonzero cell of the ball on its plane o.u = 0: of each pair o, -o exactly
+    one has o.u > 0, so the hemisphere holds the contact cell and half of the other 122: 62 cells.
+    The 40 x 40 bin (az 3, el 25), centre azimuth 31.5 deg, elevation 24.75 deg, is such a direction.
+
+    The 8 x 5 bin (az 0, el 2) has centre azimuth 22.5 deg and elevation 0: its plane holds the six
+    z-axis cells (dx cos 22.5 + dy sin 22.5 = 0 forces dx = dy = 0, tan 22.5 deg = sqrt 2 - 1 being
+    irrational), which the closed hemisphere keeps, and half of the other 116: 1 + 6 + 58 = 65."""
+    ball = _ball_offsets(9)
+    assert len(ball) == 123
+    for baz, bel, ia, ie, on_plane, want in ((40, 40, 3, 25, 0, 62), (8, 5, 0, 2, 6, 65)):
+        # the precondition of the count: which nonzero cells lie on the plane (angles as stated above)
+        a = math.radians((ia + 0.5) * 360.0 / baz)
+        e = math.radians(-90.0 + (ie + 0.5) * 180.0 / bel)
+        u = (math.cos(e) * math.cos(a), math.cos(e) * math.sin(a), math.sin(e))
+        flat = [c for c in ball if c != (0, 0, 0) and abs(c[0] * u[0] + c[1] * u[1] + c[2] * u[2]) < 1e-6]
+        assert len(flat) == on_plane
+        o = Oracle(dims=(7,) * 3, voxel_size=1.0, kernel_size=7, binning="azel", bins_az=baz, bins_el=bel,
+                   shadow_r2=9)
+        _, sh, _ = o.tables()
+        assert int(sh[ie * baz + ia].sum()) == want
+
+
 # --------------------------------------------------------- eq. 2 binning ---
 def test_azel_named_directions_eq2():
     o = Oracle(dims=(11,) * 3, voxel_size=1.0, kernel_size=11, binning="azel")
