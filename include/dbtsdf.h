@@ -403,7 +403,10 @@ dbtsdf_status dbtsdf_extract_points(dbtsdf_grid *g, const uint32_t lo[3], const 
  * since that earlier return stamped the same masks, so the per-point strategy
  * skips the window (the shadow counters are still updated). Written planes
  * need not hold such windows, so after this call the grid integrates every
- * window in full until dbtsdf_reset_grid.
+ * window in full until dbtsdf_reset_grid. A restored map therefore runs
+ * slower than the map it was saved from: late in a long sequence most
+ * returns land in voxels the map already holds, and each of them now loads
+ * and compares its whole window (the result is the same).
  */
 dbtsdf_status dbtsdf_write_voxels(dbtsdf_grid *g, const uint32_t *mask_in, const uint32_t *packed_in);
 

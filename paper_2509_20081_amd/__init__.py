@@ -413,6 +413,11 @@ class Grid:
         return out
 
     def write_voxels(self, mask, packed) -> None:
+        """Overwrite the whole grid from (Nz, Ny, Nx) uint32 planes (validated by the library)."""
+        shape = (self.dims[2], self.dims[1], self.dims[0])
+        for name, a in (("mask", mask), ("packed", packed)):
+            if np.shape(a) != shape:
+                raise ValueError(f"write_voxels: {name} has shape {np.shape(a)}, the grid needs {shape}")
         m = np.ascontiguousarray(mask, dtype=np.uint32)
         p = np.ascontiguousarray(packed, dtype=np.uint32)
         L.check(L.lib().dbtsdf_write_voxels(self._h, m.ctypes.data_as(C.c_void_p), p.ctypes.data_as(C.c_void_p)),

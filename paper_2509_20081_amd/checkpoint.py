@@ -37,6 +37,14 @@ def load_checkpoint(path: str, kernel_set=None, **grid_kw):
         header = json.loads(str(z["header"]))
         if header.get("format") != FORMAT:
             raise ValueError(f"{path}: not a {FORMAT} checkpoint")
+        dims = header.get("dims")
+        if not (isinstance(dims, list) and len(dims) == 3 and all(isinstance(d, int) and d > 0 for d in dims)):
+            raise ValueError(f"{path}: bad grid dims {dims!r} in the header")
+        shape = (dims[2], dims[1], dims[0])
+        for name in ("mask", "packed"):
+            if z[name].shape != shape or z[name].dtype != np.uint32:
+                raise ValueError(f"{path}: {name} plane is {z[name].dtype} {z[name].shape}, "
+                                 f"the header's grid needs uint32 {shape}")
         ks = KernelSet(**header["kernel"]) if kernel_set is None else kernel_set
         if ks.params != header["kernel"]:
             raise ValueError(f"kernel set {ks.params} differs from the checkpoint's {header['kernel']}")

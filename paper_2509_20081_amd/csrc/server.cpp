@@ -66,7 +66,9 @@ struct dbtsdf_server {
     hipStream_t admin = nullptr;
     std::mutex mu;
     std::condition_variable cv_done;
-    std::vector<MapSlot> maps;
+    // a deque: add_map's push_back never moves a slot, so a reference held
+    // across a wait that releases mu (remove_map) stays valid
+    std::deque<MapSlot> maps;
     std::deque<Request> queue;
     std::vector<Lane> lanes;
     std::deque<dbtsdf_completion> done;
@@ -294,14 +296,20 @@ dbtsdf_status dbtsdf_server_remove_map(dbtsdf_server *s, uint32_t map_id) {
         set_error("unknown map");
         return DBTSDF_ERR_INVALID_ARG;
     }
-    MapSlot &m = s->maps[map_id];
-    m.removing = true;
+    if (s->maps[map_id].removing) {
+        set_error("map is already being removed");
+        return DBTSDF_ERR_INVALID_ARG;
+    }
+    s->maps[map_id].removing = true;
+    // the wait releases mu: other threads may add maps meanwhile, so the slot
+    // is looked up again by index rather than held across it
     s->cv_done.wait(lk, [&] {
-        if (m.busy) return false;
+        if (s->maps[map_id].busy) return false;
         for (const Request &r : s->queue)
             if (r.map == map_id) return false;
         return true;
     });
+    MapSlot &m = s->maps[map_id];
     dbtsdf_destroy_grid(m.grid);
     m.grid = nullptr;
     s->admitted -= m.bytes;

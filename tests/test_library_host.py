@@ -163,3 +163,28 @@ def test_missing_library_fails_loudly(tmp_path):
     ) % (os.path.dirname(os.path.dirname(os.path.abspath(__file__))), str(tmp_path / "libdbtsdf.so"))
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
     assert out.returncode == 0 and out.stdout.strip() == "raised", (out.stdout, out.stderr)
+
+
+def test_checkpoint_refuses_planes_that_do_not_fit_the_header(db, tmp_path):
+    """A checkpoint whose planes do not have the header's (Nz, Ny, Nx) uint32 shape is refused before any
+    grid is made (a short plane would otherwise be read past its end by the library)."""
+    import json
+
+    from paper_2509_20081_amd.checkpoint import FORMAT, load_checkpoint
+    header = dict(format=FORMAT, dims=[8, 6, 4], voxel_size=0.1, origin=[0.0, 0.0, 0.0], hit_threshold=5,
+                  hit_max=65535, dedup=True, kernel=dict(kernel_size=3, binning="cube26", shadow_r2=1))
+    good = np.full((4, 6, 8), 0xFFFFFFFF, np.uint32)
+    cases = {"short": (good[:, :, :7], good), "transposed": (good, good.transpose(2, 1, 0).copy()),
+             "wrong dtype": (good.astype(np.int64), good)}
+    for what, (m, p) in cases.items():
+        path = str(tmp_path / f"{what.replace(' ', '_')}.npz")
+        with open(path, "wb") as f:
+            np.savez(f, header=np.array(json.dumps(header)), mask=m, packed=p)
+        with pytest.raises(ValueError):
+            load_checkpoint(path)
+    bad = dict(header, dims=[8, 6])
+    path = str(tmp_path / "bad_dims.npz")
+    with open(path, "wb") as f:
+        np.savez(f, header=np.array(json.dumps(bad)), mask=good, packed=good)
+    with pytest.raises(ValueError):
+        load_checkpoint(path)
