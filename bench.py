@@ -84,36 +84,39 @@ def no_gc():
         gc.unfreeze()
 
 
-def grid_hash(torch, g):
-    """Two position-weighted sums over both planes (torch-owned planes), for bit-exact comparisons."""
-    out = []
-    for t in (g.mask_tensor, g.packed_tensor):
-        x = t.view(-1)
-        s1 = s2 = 0
-        step = 1 << 26
-        for i in range(0, x.numel(), step):
-            c = x[i: i + step].to(torch.int64) & 0xFFFFFFFF
-            w = torch.arange(i, i + c.numel(), device=c.device, dtype=torch.int64) % 65521 + 1
-            s1 += int(c.sum().item())
-            s2 += int((c * w).sum().item())
-        out += [s1, s2]
-    return tuple(out)
+def planes_equal(torch, a, b):
+    """Both planes of two grids (torch-owned planes) equal word for word, compared on the device."""
+    return bool(torch.equal(a.mask_tensor, b.mask_tensor)) and bool(torch.equal(a.packed_tensor, b.packed_tensor))
+
+
+def far_pose():
+    """A pose that puts every return of a scan outside any grid of these workloads: calls with it run the
+    whole pass sequence (descriptors, front end, select, apply with no survivors) and change nothing. Used
+    to visit every ring slot (and capture its graphs) before a timed region without integrating a scan
+    twice."""
+    p = np.eye(4, dtype=np.float32)
+    p[:3, 3] = 1.0e6
+    return p
+
+
+def warm_ring(g, pts):
+    for _ in range(RING_SLOTS):
+        g.integrate(far_pose(), pts)
+    g.sync()
 
 
 def run_plain(db, torch, gdef, ks, dev, warmup, steps, tuning, profile=True):
     g = db.Grid(gdef["dims"], gdef["voxel_size"], gdef["origin"], ks, planes="torch")
     if tuning:
         g.set_tuning(**{k: v for k, v in tuning.items() if k != "apply_blocks"})
-    n_seq = len(dev)
-    # the warm-up runs as profiled as the timed region: every ring slot's
-    # graphs (16 slots) are captured before the clock starts
-    if warmup < RING_SLOTS:
-        log(f"warm-up of {warmup} calls visits fewer than the {RING_SLOTS} ring slots: "
-            "some graph captures fall into the timed region")
+    # the warm-up runs as profiled as the timed region: every ring slot is
+    # visited (and its graphs captured) by calls that integrate nothing, then
+    # the warm-up scans 0 .. warmup-1 are integrated once each
     if profile:
         g.set_profiling(True, every=PROF_EVERY)
+    warm_ring(g, dev[0][1])
     for k in range(warmup):
-        pose, pts = dev[k % n_seq]
+        pose, pts = dev[k]
         g.integrate(pose, pts)
     g.sync()
     if profile:
@@ -123,7 +126,7 @@ def run_plain(db, torch, gdef, ks, dev, warmup, steps, tuning, profile=True):
         t0 = time.perf_counter()
         stats = []
         for k in range(warmup, warmup + steps):
-            pose, pts = dev[k % n_seq]
+            pose, pts = dev[k]
             stats.append(g.integrate(pose, pts))
         g.sync()
         torch.cuda.synchronize()
@@ -142,12 +145,13 @@ def run_deskew(db, torch, gdef, ks, dev, warmup, steps, tuning, mode="se3"):
     n_seq = len(dev)
     times = {}
     def sweep(k):
-        pose, pts = dev[k % n_seq]
-        end = dev[(k + 1) % n_seq][0] if (k + 1) % n_seq else pose
+        pose, pts = dev[k]
+        end = dev[k + 1][0] if k + 1 < n_seq else pose
         n = int(pts.shape[0])
         if n not in times:
             times[n] = torch.linspace(0.0, 1.0, n, dtype=torch.float32, device="cuda")
         return pose, pts, end, times[n]
+    warm_ring(g, dev[0][1])
     for k in range(warmup):
         pose, pts, end, tt = sweep(k)
         g.integrate(pose, pts, pose_end=end, times=tt, deskew=mode)
@@ -171,7 +175,6 @@ def run_batched(db, torch, gdef, ks, dev, warmup, steps, tuning, per_launch):
     if tuning:
         g.set_tuning(**{k: v for k, v in tuning.items() if k != "apply_blocks"})
     b = db.Batch(use_graph=True)
-    n_seq = len(dev)
     # capture the context's graphs for every ring slot on a scratch grid of the
     # same shape (the graphs do not depend on which grid a launch updates)
     b.set_profiling(True)
@@ -185,7 +188,7 @@ def run_batched(db, torch, gdef, ks, dev, warmup, steps, tuning, per_launch):
     b.set_profiling(False)
 
     def launch(ks_):
-        return b.integrate([(g, dev[k % n_seq][0], dev[k % n_seq][1]) for k in ks_])
+        return b.integrate([(g, dev[k][0], dev[k][1]) for k in ks_])
 
     for s in range(0, warmup, per_launch):
         launch(range(s, min(s + per_launch, warmup)))
@@ -210,10 +213,9 @@ def count_traffic(db, gdef, ks, dev, warmup, steps, tuning):
     g = db.Grid(gdef["dims"], gdef["voxel_size"], gdef["origin"], ks, count_traffic=True)
     if tuning:
         g.set_tuning(**{k: v for k, v in tuning.items() if k != "apply_blocks"})
-    n_seq = len(dev)
     out = []
     for k in range(warmup + steps):
-        pose, pts = dev[k % n_seq]
+        pose, pts = dev[k]
         st = g.integrate(pose, pts)
         if k >= warmup:
             out.append(st)
@@ -230,15 +232,14 @@ def plain_latency(db, torch, gdef, ks, dev, n, tuning):
     if tuning:
         g.set_tuning(**{k: v for k, v in tuning.items() if k != "apply_blocks"})
     lat = []
-    warm = RING_SLOTS + 3  # every ring slot's graph captured before measuring
+    warm_ring(g, dev[0][1])   # every ring slot visited before measuring, nothing integrated
     with no_gc():
-        for k in range(n + warm):
-            pose, pts = dev[k % len(dev)]
+        for k in range(min(n, len(dev))):
+            pose, pts = dev[k]
             t0 = time.perf_counter()
             g.integrate(pose, pts)
             g.sync()
-            if k >= warm:
-                lat.append((time.perf_counter() - t0) * 1e3)
+            lat.append((time.perf_counter() - t0) * 1e3)
     g.close()
     return lat
 
@@ -308,7 +309,21 @@ def cpu_baseline(gdef, scans, kparams, budget_s=15.0):
             break
     return dict(value=upd / t_tot, unit="voxel-updates/s", cores=1, kind="oracle",
                 sample=f"first {n} scans of the same sequence, single-threaded C oracle, {t_tot:.1f}s",
-                scans_per_s=n / t_tot)
+                scans_per_s=n / t_tot, host=host_cpu())
+
+
+def host_cpu():
+    """The host the CPU legs ran on: logical CPUs visible to this process and the CPU model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return dict(nproc=len(os.sched_getaffinity(0)), cpu_model=model)
 
 
 def run_mesh(torch, g, dims, reps=3):
@@ -434,9 +449,10 @@ def run_c4(db, torch, ks, n_maps, n_scans, tuning):
         torch.cuda.synchronize()
         dt_plain = time.perf_counter() - t0
     upd = sum(s.as_dict()["voxel_updates"] for s in st_plain)
-    h_plain = {m: grid_hash(torch, gs[m]) for m in small}
-    for g in gs:
-        g.close()
+    kept = {m: gs[m] for m in small}   # the smaller maps' plain grids stay for the comparison
+    for m, g in enumerate(gs):
+        if m not in kept:
+            g.close()
     del gs
     torch.cuda.empty_cache()
     # batched: one launch per round
@@ -455,7 +471,9 @@ def run_c4(db, torch, ks, n_maps, n_scans, tuning):
         dt_b = time.perf_counter() - t0
     caps, reps = b.graph_stats()
     updb = sum(s.as_dict()["voxel_updates"] for s in st_b)
-    same = all(grid_hash(torch, gs[m]) == h_plain[m] for m in small)
+    same = all(planes_equal(torch, gs[m], kept[m]) for m in small)
+    for g in kept.values():
+        g.close()
     b.close()
     for g in gs:
         g.close()
@@ -475,9 +493,11 @@ def run_c4(db, torch, ks, n_maps, n_scans, tuning):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200, help="timed scans (plain form)")
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3))
+    ap.add_argument("--steps", type=int, default=20, help="timed scans (plain form)")
+    ap.add_argument("--warmup", type=int, default=5, help="scans integrated before the timed ones")
+    ap.add_argument("--config", type=int, default=3, choices=(1, 2, 3),
+                    help="3: 100 scans of 128x2048 into 2048x2048x512 @ 0.02 m (the large grid, default); "
+                         "2: 200 scans of 64x1024 into 1024x1024x256 @ 0.05 m")
     ap.add_argument("--batch-scans", type=int, default=8, help="scans per batched launch")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
@@ -519,7 +539,13 @@ def main():
     cfg = args.config
     gdef = synth.config_grid(cfg)
     n_seq = synth.CONFIGS[cfg]["scans"]
-    scans, dev = load_scans(cfg, min(n_seq, args.warmup + args.steps), torch)
+    if args.warmup + args.steps > n_seq:
+        # a timed region never integrates a scan twice (a repeated scan at the same pose finds every
+        # window already applied and would time less work)
+        print(json.dumps({"error": f"warmup + steps = {args.warmup + args.steps} exceeds the {n_seq} scans of "
+                                   f"config {cfg}; no scan is integrated twice"}))
+        return 2
+    scans, dev = load_scans(cfg, args.warmup + args.steps, torch)
     kparams = dict(kernel_size=11, binning="cube26", shadow_r2=9) if args.kernel == "workload" else \
         dict(kernel_size=21, binning="azel", bins_az=40, bins_el=40, shadow_r2=9)
     ks = db.KernelSet(**kparams)
@@ -546,11 +572,12 @@ def main():
     upd = sum(s["voxel_updates"] for s in sd)
     value = upd / dt
     log(f"plain: {args.steps} scans in {dt * 1e3:.1f} ms -> {value / 1e9:.1f} G voxel-updates/s; profile {prof}")
-    plain_hash = grid_hash(torch, g) if not args.no_batched else None
     mesh = None if args.no_mesh else run_mesh(torch, g, gdef["dims"])
     if mesh:
         log(f"mesh: {mesh}")
-    g.close()
+    plain_grid = g          # kept for the batched form's word-for-word comparison
+    if args.no_batched:
+        g.close()
     torch.cuda.empty_cache()
 
     deskew = None
@@ -585,15 +612,24 @@ def main():
             traffic = tj.get("bytes_per_launch")
     copy_gbs = copy_bandwidth(torch)
     visits = float(np.mean([t["voxel_updates"] for t in sd]))
+    k3 = kparams["kernel_size"] ** 3
+    n_int = float(np.sum([t["n_integrated"] for t in sd]))
+    n_rev = float(np.sum([t["n_revisit"] for t in sd]))
+    applied_frac = 1.0 - n_rev / n_int if n_int else None
+    # operations the apply kernel executes: K^3 cells per applied window plus one counter step per shadow cell
+    executed = float(np.mean([(t["n_integrated"] - t["n_revisit"]) * k3 + t["shadow_updates"] for t in sd]))
     roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
                     traffic=traffic, kernel=kname, avg_launch_us=apply_ms * 1e3,
                     timed_launches=prof["applies"],
                     timing="HIP events around the apply kernel of every %dth call of the timed region" % PROF_EVERY,
                     measured_copy_gbs=copy_gbs, frac_vs_copy=achieved / copy_gbs,
                     secondary=dict(ceiling="LDS/atomic dword ops: 256 CUs x 32 per clock x 2.4 GHz",
-                                   peak_ops_per_s=LDS_ATOMIC_OPS, achieved_ops_per_s=visits / (apply_ms * 1e-3),
-                                   frac=visits / (apply_ms * 1e-3) / LDS_ATOMIC_OPS,
-                                   per_launch="voxel-updates of one scan (K^3 per integrated point)"),
+                                   peak_ops_per_s=LDS_ATOMIC_OPS, achieved_ops_per_s=executed / (apply_ms * 1e-3),
+                                   frac=executed / (apply_ms * 1e-3) / LDS_ATOMIC_OPS,
+                                   per_launch="operations executed in one scan: K^3 per applied window (returns "
+                                              "in voxels an earlier scan integrated skip theirs) + one per "
+                                              "shadow cell"),
+                    windows_applied_frac=applied_frac,
                     algorithmic_bytes_per_launch=apply_bytes,
                     per_launch="4*U_m + 4*C_m + 8*U_s of one scan (unique mask words read, changed words "
                                "written, unique shadow words read+written)",
@@ -611,14 +647,17 @@ def main():
         batched = dict(value=bupd / bdt, unit="voxel-updates/s", scans_per_s=args.steps / bdt,
                        scans_per_launch=args.batch_scans, ms_per_scan=bdt * 1e3 / args.steps,
                        graph_captures=caps, graph_replays=reps, speedup_vs_plain=(bupd / bdt) / value,
-                       bit_exact_vs_plain=grid_hash(torch, bg) == plain_hash)
+                       bit_exact_vs_plain=planes_equal(torch, bg, plain_grid),
+                       comparison="both planes word for word on the device (torch.equal)")
         bg.close()
+        plain_grid.close()
         log(f"batched: {batched}")
         torch.cuda.empty_cache()
 
     lat = plain_latency(db, torch, gdef, ks, dev, args.latency_scans, tuning) if args.latency_scans else []
-    latency = dict(plain_p50_ms=pct(lat, 50), plain_p99_ms=pct(lat, 99),
-                   plain_definition="integrate_scan call to sync return, one scan at a time")
+    latency = dict(plain_p50_ms=pct(lat, 50), plain_p99_ms=pct(lat, 99), plain_scans=len(lat),
+                   plain_definition="integrate_scan call to sync return, one scan at a time, scans 0.. of the "
+                                    "sequence in order on a fresh grid (none repeated)")
     torch.cuda.empty_cache()
 
     served = None
@@ -661,6 +700,8 @@ def main():
                    "tuning": tuning},
         "scans_per_s": args.steps / dt,
         "mean_integrated_per_scan": float(np.mean([s["n_integrated"] for s in sd])),
+        "windows_applied_frac": applied_frac,
+        "timed_scans": [args.warmup, args.warmup + args.steps - 1],
         "batched": batched,
         "mesh_export": mesh,
         "deskew": deskew,

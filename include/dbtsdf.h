@@ -131,6 +131,12 @@ typedef struct {
  * counted; they only occur for K = 37), of those whose value changed, and of
  * distinct words in the union of the shadows. In a batch call they are per grid and reported on the first scan of
  * that grid in the batch (zero on the others).
+ * n_revisit counts the integrated returns whose voxel an earlier call had
+ * already integrated (its mask reads 0): their eq. 4 window cannot lower any
+ * mask, and the per-point and sort strategies skip it (the shadow counters are
+ * still updated). It is a scheduling statistic of the library, not part of
+ * the method: zero for the brick strategy, for kernel sets of more than 32768
+ * bins, and for a grid whose planes dbtsdf_write_voxels wrote, until reset.
  */
 typedef struct {
     uint64_t n_in;
@@ -143,6 +149,7 @@ typedef struct {
     uint64_t u_mask;
     uint64_t c_mask;
     uint64_t u_shadow;
+    uint64_t n_revisit;
 } dbtsdf_scan_stats;
 
 /* How conflicting updates to one voxel are resolved. Results are identical. */

@@ -29,7 +29,7 @@ class GridParams(C.Structure):
 
 
 STAT_FIELDS = ("n_in", "n_invalid", "n_out_of_bounds", "n_duplicate", "n_integrated",
-               "voxel_updates", "shadow_updates", "u_mask", "c_mask", "u_shadow")
+               "voxel_updates", "shadow_updates", "u_mask", "c_mask", "u_shadow", "n_revisit")
 
 
 class ScanStats(C.Structure):

@@ -320,6 +320,7 @@ void Workspace::deliver(RingSlot &s) {
         st.n_integrated = sc[SC_INT];
         st.voxel_updates = sc[SC_INT] * p.k3;
         st.shadow_updates = sc[SC_SHADOW];
+        st.n_revisit = sc[SC_REVISIT];
         if (p.traffic_grid >= 0) {
             const unsigned long long *tc = c + (size_t)scans_cap * SC_N + (size_t)p.traffic_grid * TC_N;
             st.u_mask = tc[TC_UMASK];

@@ -125,7 +125,7 @@ struct DevScan {
 static_assert(sizeof(DevScan) % 16 == 0, "DevScan is read in 16-byte pieces");
 
 // Per-scan counters (u64) and per-grid traffic counters.
-enum { SC_INVALID = 0, SC_OOB, SC_DUP, SC_INT, SC_SHADOW, SC_N };
+enum { SC_INVALID = 0, SC_OOB, SC_DUP, SC_INT, SC_SHADOW, SC_REVISIT, SC_N };
 enum { TC_UMASK = 0, TC_CMASK, TC_USHADOW, TC_N };
 
 struct Ctrl {

@@ -536,7 +536,7 @@ __global__ __launch_bounds__(kPtThreads) void k_stats(PipeArgs a, const CallInfo
         const uint32_t s0 = find_scan(a.scans, info->n_scans, lo);
         const uint32_t s1 = find_scan(a.scans, info->n_scans, hi - 1);
         if (s0 == s1) {
-            uint32_t c[SC_N] = {0u, 0u, 0u, 0u, 0u};
+            uint32_t c[SC_N] = {};
             for (uint32_t i = lo + threadIdx.x; i < hi; i += kPtThreads) {
                 const uint32_t w = a.rec[i].w;
                 const uint32_t st = (w >> 16) & 3u;
@@ -1038,6 +1038,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_atomic(PipeArgs a, const
         c[SC_DUP] = st == kStOk && !surv;
         c[SC_INT] = surv;
         c[SC_SHADOW] = surv ? a.tab.sh_start[(r.w & 0xFFFFu) + 1] - a.tab.sh_start[r.w & 0xFFFFu] : 0u;
+        c[SC_REVISIT] = revisit != 0u;
         // statistics: one atomic per counter per workgroup when all of its
         // points are in one scan, else one per scan per wavefront
         const uint32_t last = min(n, base + blockDim.x) - 1u;
