@@ -291,6 +291,31 @@ dbtsdf_status dbtsdf_integrate_scan(dbtsdf_grid *g, const float pose[16], const 
                                     int points_on_device, dbtsdf_scan_stats *stats);
 
 /*
+ * For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): dbtsdf_integrate_scan
+ * with device points and the per-point strategy, allocating nothing. Every
+ * buffer the call needs beyond the grid and the points (descriptors,
+ * counters, point records, the first-return dedup table, the survivor list)
+ * lives in one static device array of DBTSDF_NOALLOC_SCRATCH_BYTES per GPU,
+ * set up on the first call on a device and held until the process ends.
+ *   points_dev  n x 3 fp32 in device memory, valid until the passes have run.
+ *   n           at most DBTSDF_NOALLOC_MAX_POINTS; more is OUT_OF_RANGE.
+ *   stats       NULL: the call returns once its passes are enqueued on the
+ *               grid's stream. Non-NULL: the call waits for its passes and
+ *               fills *stats (traffic counts, u_mask/c_mask/u_shadow, are
+ *               not taken and stay 0).
+ * The grid's tuning is not used (the per-point kernels always run) and its
+ * result is that of dbtsdf_integrate_scan, bit for bit. Calls on one GPU
+ * share its array: calls that overlap on the device (different streams, or
+ * threads) race and must be ordered by the caller. Calls on the same grid are
+ * stream-ordered as usual. Errors: INVALID_ARG, OUT_OF_RANGE, DEVICE, POISONED.
+ */
+#define DBTSDF_NOALLOC_MAX_POINTS 131072u
+#define DBTSDF_NOALLOC_SCRATCH_BYTES 11011584u
+dbtsdf_status dbtsdf_integrate_scan_noalloc(dbtsdf_grid *g, const float pose[16], const float *points_dev, uint64_t n,
+                                            dbtsdf_scan_stats *stats);
+
+/*
  * dbtsdf_integrate_scan with the sequential downsampling of Sec. IV-B (DS =
  * every): only returns 0, every, 2 every, ... of the n given are taken, in
  * that order (so "first return" is among them), and the statistics count

@@ -77,6 +77,7 @@ SIGNATURES = {
     "dbtsdf_set_tuning": (C.c_int, [P, C.POINTER(Tuning)]),
     "dbtsdf_integrate_scan": (C.c_int, [P, P, P, U64, C.c_int, C.POINTER(ScanStats)]),
     "dbtsdf_sync": (C.c_int, [P]),
+    "dbtsdf_integrate_scan_noalloc": (C.c_int, [P, P, P, U64, C.POINTER(ScanStats)]),
     "dbtsdf_read_voxels": (C.c_int, [P, P, P, P, P]),
     "dbtsdf_read_distance": (C.c_int, [P, P, P, P]),
     "dbtsdf_write_voxels": (C.c_int, [P, P, P]),

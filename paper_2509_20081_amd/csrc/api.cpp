@@ -389,6 +389,59 @@ static uint32_t entry_factor(const Tuning &t, int R) {
 }
 
 // ------------------------------------------------------------ enqueue ---
+DevGrid dev_grid_of(const dbtsdf_grid *g, uint32_t index) {
+    DevGrid d{};
+    d.mask = g->mask;
+    d.packed = g->packed;
+    d.brick_cnt = g->brick_cnt;
+    d.brick_slot = g->brick_slot;
+    d.nx = g->params.dims[0];
+    d.ny = g->params.dims[1];
+    d.nz = g->params.dims[2];
+    d.nbx = g->nb[0];
+    d.nby = g->nb[1];
+    d.nbz = g->nb[2];
+    d.T = g->params.hit_threshold;
+    d.hmax = g->params.hit_max;
+    d.traffic_slot = index;
+    d.revisit_skip = g->revisit_skip ? 1u : 0u;
+    return d;
+}
+
+DevScan dev_scan_of(const ScanIn &s, uint32_t begin, uint32_t grid_index) {
+    const dbtsdf_grid_params &gp = s.grid->params;
+    DevScan d{};
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) d.rot[3 * r + c] = s.pose[4 * r + c];
+        d.trans[r] = s.pose[4 * r + 3];
+        d.origin[r] = gp.origin[r];
+    }
+    d.inv_s = 1.0f / gp.voxel_size;
+    d.pts = s.points;
+    d.begin = begin;
+    d.n = (uint32_t)s.n;
+    d.grid = grid_index;
+    d.dedup = (gp.flags & DBTSDF_DEDUP_FIRST) ? 1u : 0u;
+    d.step = s.step;
+    if (s.times) {
+        d.deskew = 1;
+        d.times = s.times;
+        for (int k = 0; k < 4; ++k) d.dq[k] = s.dq[k];
+        for (int k = 0; k < 3; ++k) d.dt[k] = s.dt[k];
+    }
+    return d;
+}
+
+// The per-point strategy's row kernel covers a call when the kernel set has
+// its tables and every grid has 16-byte aligned rows and window byte offsets
+// within 32 bits.
+bool row_kernel_covers(const dbtsdf_grid *g) {
+    if (g->tables->t.row_image == nullptr) return false;
+    const uint64_t span = (uint64_t)g->tables->t.R *
+                          (1ull + g->params.dims[0] + (uint64_t)g->params.dims[0] * g->params.dims[1]);
+    return g->params.dims[0] % 4u == 0 && 8 * span < (1ull << 32);
+}
+
 
 dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &scans, bool use_graph, bool plain) {
     // drop empty scans (their statistics are all zero)
@@ -439,12 +492,8 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
     if (grids.size() > kMaxAtomicGrids) tun.strategy = DBTSDF_STRATEGY_BRICK;
     // the per-point strategy's row kernel: tables for the kernel set, 16-byte
     // aligned grid rows and window byte offsets within 32 bits in every grid
-    bool row_kernel = g0->tables->t.row_image != nullptr;
-    for (dbtsdf_grid *g : grids) {
-        const uint64_t span = (uint64_t)g->tables->t.R *
-                              (1ull + g->params.dims[0] + (uint64_t)g->params.dims[0] * g->params.dims[1]);
-        if (g->params.dims[0] % 4u || 8 * span >= (1ull << 32)) row_kernel = false;
-    }
+    bool row_kernel = true;
+    for (dbtsdf_grid *g : grids) row_kernel = row_kernel && row_kernel_covers(g);
     if (tun.apply_blocks == 0) tun.apply_blocks = (uint32_t)apply_blocks_default(tun, g0->K, row_kernel, g0->device);
     for (dbtsdf_grid *g : grids) {
         dbtsdf_status s = ensure_bricks(g);
@@ -472,22 +521,7 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
     std::memcpy(h, &ci, sizeof(ci));
     DevGrid *hg = (DevGrid *)(h + sizeof(CallInfo));
     for (size_t i = 0; i < n_gr; ++i) {
-        dbtsdf_grid *g = grids[i];
-        DevGrid d{};
-        d.mask = g->mask;
-        d.packed = g->packed;
-        d.brick_cnt = g->brick_cnt;
-        d.brick_slot = g->brick_slot;
-        d.nx = g->params.dims[0];
-        d.ny = g->params.dims[1];
-        d.nz = g->params.dims[2];
-        d.nbx = g->nb[0];
-        d.nby = g->nb[1];
-        d.nbz = g->nb[2];
-        d.T = g->params.hit_threshold;
-        d.hmax = g->params.hit_max;
-        d.traffic_slot = (uint32_t)i;
-        d.revisit_skip = g->revisit_skip ? 1u : 0u;
+        const DevGrid d = dev_grid_of(grids[i], (uint32_t)i);
         std::memcpy(&hg[i], &d, sizeof(d));
     }
     DevScan *hs = (DevScan *)(h + scans_off);
@@ -498,25 +532,7 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
     for (size_t i = 0; i < n_sc; ++i) {
         const ScanIn &s = live[i];
         const dbtsdf_grid_params &gp = s.grid->params;
-        DevScan d{};
-        for (int r = 0; r < 3; ++r) {
-            for (int c = 0; c < 3; ++c) d.rot[3 * r + c] = s.pose[4 * r + c];
-            d.trans[r] = s.pose[4 * r + 3];
-            d.origin[r] = gp.origin[r];
-        }
-        d.inv_s = 1.0f / gp.voxel_size;
-        d.pts = s.points;
-        d.begin = begin;
-        d.n = (uint32_t)s.n;
-        d.grid = gidx[s.grid];
-        d.dedup = (gp.flags & DBTSDF_DEDUP_FIRST) ? 1u : 0u;
-        d.step = s.step;
-        if (s.times) {
-            d.deskew = 1;
-            d.times = s.times;
-            for (int k = 0; k < 4; ++k) d.dq[k] = s.dq[k];
-            for (int k = 0; k < 3; ++k) d.dt[k] = s.dt[k];
-        }
+        const DevScan d = dev_scan_of(s, begin, gidx[s.grid]);
         std::memcpy(&hs[i], &d, sizeof(d));
         begin += (uint32_t)s.n;
         PendingStat p{s.stats, (uint32_t)i, -1, s.n, k3};
