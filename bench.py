@@ -598,7 +598,9 @@ def main():
     apply_ms = prof["apply_ms"] / max(prof["applies"], 1)
     call_ms = prof["call_ms"] / max(prof["calls"], 1)
     achieved = apply_bytes / (apply_ms * 1e-3) / 1e9
-    if tuning["strategy"] == "brick":
+    if tuning["strategy"] == "tile":
+        kname = "k_apply_tile"
+    elif tuning["strategy"] == "brick":
         kname = f"k_apply_brick<{tuning['brick'][0]},{tuning['brick'][1]},{tuning['brick'][2]},{tuning['block_threads']}>"
     elif kparams["kernel_size"] <= 11 and kparams["binning"] == "cube26" and gdef["dims"][0] % 4 == 0:
         kname = "k_apply_points<true>"   # the row kernel of the plain one-scan call

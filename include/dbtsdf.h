@@ -157,9 +157,15 @@ typedef enum {
     DBTSDF_STRATEGY_AUTO = 0,   /* the default: DBTSDF_STRATEGY_ATOMIC (dbtsdf_autotune measures instead) */
     DBTSDF_STRATEGY_BRICK = 1,  /* returns bucketed by grid brick; one workgroup owns a brick in LDS */
     DBTSDF_STRATEGY_ATOMIC = 2, /* one wavefront per return; 32-bit global atomics */
-    DBTSDF_STRATEGY_SORT = 3    /* every change a return makes to a word becomes a (voxel key, contribution)
+    DBTSDF_STRATEGY_SORT = 3,   /* every change a return makes to a word becomes a (voxel key, contribution)
                                    pair; the pairs are radix-sorted by key and a wavefront segmented reduction
                                    applies eq. 4 and eqs. 5-6 once per voxel, with no atomics on the planes */
+    DBTSDF_STRATEGY_TILE = 4    /* returns listed by the 32x16x8 grid tiles their window reaches (a return in
+                                   a voxel an earlier call integrated: the tiles its shadow reaches); one
+                                   workgroup per tile takes the minimum eq. 3 distance and the shadow hit
+                                   count of every word in LDS, then reads, updates and writes each touched
+                                   word once with plain loads and stores (no atomics on the planes).
+                                   Kernel sets with K <= 11, at most 31 bins and r_s^2 <= 9 */
 } dbtsdf_strategy;
 
 /*
@@ -178,6 +184,9 @@ typedef enum {
  * return once the pairs are sorted, and it never replays graphs), holds up to
  * 2^28 pairs of 12 bytes twice over in device memory (allocated on first use,
  * grown as calls need) and takes larger calls in several rounds of returns.
+ * DBTSDF_STRATEGY_TILE takes brick 32x16x8 (0x0x0 or that shape) and 256
+ * threads, ignores chunk, and needs a kernel set with K <= 11, at most 31
+ * bins and r_s^2 <= 9 (INVALID_ARG otherwise).
  * Any valid tuning gives bit-identical grids. A new grid
  * starts with DBTSDF_STRATEGY_ATOMIC, brick 32x8x8, 256 threads, chunk 64.
  * A call that counts traffic (DBTSDF_COUNT_TRAFFIC) or spans more than 65536

@@ -29,7 +29,7 @@ _BINNING = {"azel": L.BIN_AZEL, "cube26": L.BIN_CUBE26}
 _METRIC = {"l2": L.DIST_L2, "l1": L.DIST_L1}
 _SHADOW = {"hemisphere": 0, "cone": 1}
 _STRATEGY = {"auto": L.STRATEGY_AUTO, "brick": L.STRATEGY_BRICK, "atomic": L.STRATEGY_ATOMIC,
-             "sort": L.STRATEGY_SORT}
+             "sort": L.STRATEGY_SORT, "tile": L.STRATEGY_TILE}
 _STRATEGY_NAME = {v: k for k, v in _STRATEGY.items()}
 
 

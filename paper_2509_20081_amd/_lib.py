@@ -14,7 +14,7 @@ STATUS_NAMES = {0: "OK", 1: "ERR_INVALID_ARG", 2: "ERR_OUT_OF_MEMORY", 3: "ERR_D
 BIN_AZEL, BIN_CUBE26 = 0, 1
 DIST_L2, DIST_L1 = 0, 1
 DEDUP_FIRST, COUNT_TRAFFIC = 0x1, 0x2
-STRATEGY_AUTO, STRATEGY_BRICK, STRATEGY_ATOMIC, STRATEGY_SORT = 0, 1, 2, 3
+STRATEGY_AUTO, STRATEGY_BRICK, STRATEGY_ATOMIC, STRATEGY_SORT, STRATEGY_TILE = 0, 1, 2, 3, 4
 
 
 class KernelParams(C.Structure):

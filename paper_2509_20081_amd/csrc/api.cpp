@@ -370,9 +370,13 @@ dbtsdf_status ensure_bricks(dbtsdf_grid *g) {
         nbr *= g->nb[k];
         g->brick_dims[k] = bd[k];
     }
-    e = hipMalloc((void **)&g->brick_cnt, nbr * 4);
-    if (e == hipSuccess) e = hipMalloc((void **)&g->brick_slot, nbr * 4);
-    if (e == hipSuccess) e = launch_fill_u32(g->brick_cnt, 0u, nbr, g->stream);
+    // a power of two of counters: the tile strategy indexes them through a
+    // multiplicative bijection on that range
+    uint64_t cap = 1;
+    while (cap < nbr) cap <<= 1;
+    e = hipMalloc((void **)&g->brick_cnt, cap * 4);
+    if (e == hipSuccess) e = hipMalloc((void **)&g->brick_slot, cap * 4);
+    if (e == hipSuccess) e = launch_fill_u32(g->brick_cnt, 0u, cap, g->stream);
     if (e != hipSuccess) {
         g->brick_cnt = nullptr;
         return check_hip(e, "allocating brick counters", g);
@@ -435,6 +439,8 @@ DevScan dev_scan_of(const ScanIn &s, uint32_t begin, uint32_t grid_index) {
 // The per-point strategy's row kernel covers a call when the kernel set has
 // its tables and every grid has 16-byte aligned rows and window byte offsets
 // within 32 bits.
+bool row_kernel_tables(const dbtsdf_grid *g) { return g->tables->t.row_image != nullptr; }
+
 bool row_kernel_covers(const dbtsdf_grid *g) {
     if (g->tables->t.row_image == nullptr) return false;
     const uint64_t span = (uint64_t)g->tables->t.R *
@@ -577,13 +583,16 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
         const uint32_t bd[3] = {tun.bx, tun.by, tun.bz};
         for (int k = 0; k < 3; ++k) a.span[k] = 1u + (2u * (uint32_t)R + bd[k] - 1u) / bd[k];
     }
-    // exact unique-word counts need every brick merged by one work unit
-    a.chunk = traffic ? 0u : tun.chunk;
+    // exact unique-word counts need every brick merged by one work unit; the
+    // tile strategy never splits a tile
+    a.chunk = traffic || tun.strategy == DBTSDF_STRATEGY_TILE ? 0u : tun.chunk;
     // the plain one-scan call has a kernel of its own (no per-point scan lookup)
     // (its front pass reads the scan descriptor from the host in 16-byte pieces)
     a.single_scan = plain && live.size() == 1 && scans_off % 16 == 0 ? 1u : 0u;
     a.row_kernel = row_kernel ? 1u : 0u;
     a.revisit_ok = g0->tables->t.n_bins <= 32768u ? 1u : 0u;
+    a.tile_mode = tun.strategy == DBTSDF_STRATEGY_TILE ? 1u : 0u;
+    if (a.tile_mode && !row_kernel_tables(g0)) return invalid("the tile strategy needs K <= 11, at most 31 bins and r_s^2 <= 9");
 
     // batches that ask for it, and plain brick-strategy calls (nine passes),
     // replay captured graphs (one host call instead of one per pass); plain
@@ -593,7 +602,7 @@ dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &
     // (the sort strategy reads counts back in the middle of its apply and
     // launches directly)
     const bool sort = tun.strategy == DBTSDF_STRATEGY_SORT;
-    const bool graphs = !sort && (use_graph || (plain && tun.strategy != DBTSDF_STRATEGY_ATOMIC));
+    const bool graphs = !sort && (use_graph || (plain && tun.strategy == DBTSDF_STRATEGY_BRICK));
     SortPlan plan{};
     if (sort) {
         uint64_t max_vox = 0;
@@ -842,6 +851,15 @@ dbtsdf_status dbtsdf_set_tuning(dbtsdf_grid *g, const dbtsdf_tuning *t) {
     n.chunk = t->chunk == 0 ? Tuning{}.chunk : (t->chunk == 0xFFFFFFFFu ? 0u : t->chunk);
     // the sort strategy's chunk: most survivors per round (0: as many as the pair buffers allow)
     if (n.strategy == DBTSDF_STRATEGY_SORT) n.chunk = t->chunk == 0xFFFFFFFFu ? 0u : t->chunk;
+    if (n.strategy == DBTSDF_STRATEGY_TILE) {
+        if (!row_kernel_tables(g)) return invalid("the tile strategy needs K <= 11, at most 31 bins and r_s^2 <= 9");
+        if (n.bx == 0 && n.by == 0 && n.bz == 0) {
+            n.bx = kTileX;
+            n.by = kTileY;
+            n.bz = kTileZ;
+        }
+        if (n.threads == 0) n.threads = 256;
+    }
     if (n.strategy == DBTSDF_STRATEGY_ATOMIC || n.strategy == DBTSDF_STRATEGY_SORT) {
         if (n.bx == 0) {
             n.bx = g->tuning.bx;

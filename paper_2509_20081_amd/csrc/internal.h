@@ -31,6 +31,14 @@ constexpr uint32_t kRecSurvivor = 1u << 30;
 // 32768 bins, PipeArgs::revisit_ok), grid index in bits 16-31
 constexpr uint32_t kRecRevisit = 1u << 15;
 constexpr uint32_t kRowBinMask = kRecRevisit - 1u;
+// point record word, tile strategy: the front pass found the return's voxel
+// integrated by an earlier call (its window is skipped)
+constexpr uint32_t kRecTileRevisit = 1u << 29;
+// tile strategy: list entries of returns that lost the first-return test
+constexpr uint32_t kTileHole = 0xFFFFFFFFu;
+// The tile strategy's grid tiles (x fastest): 128-byte rows of words, 4096
+// words a tile.
+constexpr uint32_t kTileX = 32, kTileY = 16, kTileZ = 8;
 
 // ------------------------------------------------------- host kernel set ---
 struct KernelSet {
@@ -134,7 +142,8 @@ struct Ctrl {
     uint32_t n_survivors;    // integrated points (atomic strategy)
     uint32_t n_work;         // apply work units (bricks, heavy ones split)
     uint32_t select_done;    // workgroups of the select pass that have finished (atomic strategy)
-    uint32_t pad[3];
+    uint32_t work_next;      // tile strategy: work items claimed by the apply's workgroups
+    uint32_t pad[2];
 };
 
 // Sizes of the current call, read by the kernels from device memory so that a
@@ -173,6 +182,8 @@ struct PipeArgs {
                              // tables and every grid has Nx % 4 == 0 (16-byte aligned rows) and window
                              // byte offsets that fit 32 bits (8 R (1 + Nx + Nx Ny) < 2^32)
     uint32_t single_scan;    // the call holds exactly one scan (one grid)
+    uint32_t tile_mode;      // the tile strategy: per-grid counters indexed through tile_ctr, list offsets
+                             // beside them
     uint32_t revisit_ok;     // the kernel set has at most 32768 bins: bit 15 of a survivor's record
                              // word is free for the revisit flag (else the bin uses bits 0-15)
     // the call's descriptors are read from, and its counters written to, the
@@ -226,7 +237,8 @@ enum { kPartAll = 0, kPartPre = 1, kPartApply = 2, kPartPost = 3 };
 inline bool per_point_front(const Tuning &t) {
     return t.strategy == DBTSDF_STRATEGY_ATOMIC || t.strategy == DBTSDF_STRATEGY_SORT;
 }
-inline bool pipeline_has_post(const Tuning &t) { return !per_point_front(t); }
+// Only the brick strategy has passes after the apply (k_download).
+inline bool pipeline_has_post(const Tuning &t) { return t.strategy == DBTSDF_STRATEGY_BRICK; }
 hipError_t launch_pipeline(const PipeArgs &a, const Tuning &t, uint32_t points_cap, hipStream_t st, int part);
 hipError_t launch_read_distance(const uint32_t *mask, const uint32_t *packed, int8_t *out, uint64_t n,
                                 hipStream_t st);

@@ -83,12 +83,36 @@ typedef __attribute__((address_space(1))) uint32_t gu32;
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) const u32x4 gu32x4;
 __device__ __forceinline__ gu32 *glob(uint32_t *p) { return (gu32 *)p; }
+__device__ __forceinline__ uint4 gload4(const uint4 *p, size_t i) {
+    const u32x4 v = ((gu32x4 *)p)[i];
+    return make_uint4(v[0], v[1], v[2], v[3]);
+}
+// A 16-byte store to global memory. Pointers read from memory (the grid
+// descriptors) are generic to the compiler; a generic (flat) access also
+// counts against the LDS wait counter, so every later LDS wait would wait for
+// it too.
+__device__ __forceinline__ void gstore4(uint32_t *p, uint32_t a0, uint32_t a1, uint32_t a2, uint32_t a3) {
+    typedef __attribute__((address_space(1))) u32x4 gu32x4w;
+    u32x4 v;
+    v[0] = a0;
+    v[1] = a1;
+    v[2] = a2;
+    v[3] = a3;
+    *reinterpret_cast<gu32x4w *>(glob(p)) = v;
+}
 __device__ __forceinline__ void g_and(gu32 *p, uint32_t v) {
     (void)__hip_atomic_fetch_and(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ uint32_t g_add(gu32 *p, uint32_t v) {
     return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ uint32_t g_cas(gu32 *p, uint32_t expected, uint32_t desired) {
+    (void)__hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+    return expected;   // the value found (equal to the one expected when the exchange took place)
+}
+typedef __attribute__((address_space(1))) const float gf32;
+__device__ __forceinline__ gf32 *globf(const float *p) { return (gf32 *)p; }
 __device__ __forceinline__ void g_sub(gu32 *p, uint32_t v) {
     (void)__hip_atomic_fetch_sub(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -287,13 +311,14 @@ constexpr int kSelThreads = 256;    // one claim atomic per block of points
 constexpr uint32_t kCtrlWords = sizeof(Ctrl) / 4;
 
 // Clears the call's counters: threads [first, first + stride) of the launch.
+// keep_active: leave Ctrl::n_active (word 0) alone.
 __device__ __forceinline__ void reset_counters(const PipeArgs &a, uint32_t n_scans, uint32_t n_grids, uint32_t first,
-                                               uint32_t stride) {
+                                               uint32_t stride, bool keep_active = false) {
     const uint32_t n_sc = n_scans * SC_N, n_tc = n_grids * TC_N;
     for (uint32_t i = first; i < n_sc + n_tc + kCtrlWords; i += stride) {
         if (i < n_sc) a.scan_ctr[i] = 0ull;
         else if (i < n_sc + n_tc) a.traffic_ctr[i - n_sc] = 0ull;
-        else ((uint32_t *)a.ctrl)[i - n_sc - n_tc] = 0u;
+        else if (!keep_active || i != n_sc + n_tc) ((uint32_t *)a.ctrl)[i - n_sc - n_tc] = 0u;
     }
 }
 
@@ -316,6 +341,9 @@ __global__ __launch_bounds__(256) void k_upload(PipeArgs a) {
 // host buffer.
 __global__ __launch_bounds__(256) void k_download(PipeArgs a, const CallInfo *info) {
     const uint32_t n_s = info->n_scans * SC_N, n_t = info->n_grids * TC_N;
+    // the tile strategy's one-scan front pass counts on a cleared work-item
+    // counter (the brick passes that read it are done)
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.ctrl->n_active = 0u;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_s + n_t; i += gridDim.x * blockDim.x) {
         if (i < n_s) a.host_ctr[i] = a.scan_ctr[i];
         else a.host_ctr[(size_t)a.scans_cap * SC_N + (i - n_s)] = a.traffic_ctr[i - n_s];
@@ -323,85 +351,220 @@ __global__ __launch_bounds__(256) void k_download(PipeArgs a, const CallInfo *in
     __threadfence_system();
 }
 
+// A workgroup barrier that orders LDS only: it waits for this wave's LDS
+// operations, not for its global loads (__syncthreads' fence waits for every
+// outstanding vector memory operation, which would drain loads issued ahead
+// to overlap later work).
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// Exclusive prefix of v over the block; *total receives the block sum.
+// LDS_ONLY: the barriers order LDS only (see lds_barrier).
+template <int THREADS, bool LDS_ONLY = false>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_tmp, uint32_t &total) {
+    const uint32_t w = threadIdx.x >> 6;
+    const uint32_t incl = wave_incl_scan_u32(v);
+    if (lane() == 63u) s_tmp[w] = incl;
+    if constexpr (LDS_ONLY) lds_barrier(); else __syncthreads();
+    uint32_t before = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < THREADS / 64; ++k) {
+        const uint32_t x = s_tmp[k];
+        before += (uint32_t)k < w ? x : 0u;
+        tot += x;
+    }
+    if constexpr (LDS_ONLY) lds_barrier(); else __syncthreads();
+    total = tot;
+    return before + incl - v;
+}
+
+// atomics issued together per return (list ranks)
+constexpr int kSelUnroll = 6;
+constexpr int kFrontUnroll = 12;   // the tile strategy: every list of a K = 11 window at once
+
 // Transform, voxelise, bin and dedup-insert every point of the call. In a
 // one-scan call (ONE) the passes that copy the descriptors in and clear the
 // counters are folded in: every workgroup reads what it needs of the call's
-// descriptors (the sizes, the grid's dimensions, the scan) straight from the
-// ring slot's pinned host buffer into LDS, in eleven 16-byte reads issued
-// together, and workgroup 0 also writes the whole device copy that the later
-// passes read and clears the counters (no pass before this one touches
-// either).
+// descriptors (the sizes, the grid, the scan) straight from the ring slot's
+// pinned host buffer into LDS, in 16-byte reads issued together, and
+// workgroup 0 also writes the whole device copy that the later passes read
+// and clears the counters (no pass before this one touches either).
+// TILE (the tile strategy): every valid return is also listed, before the
+// survivor test, in each grid tile (kTileX x kTileY x kTileZ) its eq. 4 window
+// reaches, or, for a return whose voxel an earlier call integrated (its
+// window is skipped), each tile its shadow ball reaches: the atomicAdd on the
+// tile's counter gives the return's rank in that tile's list, and the return
+// that opens a tile claims its work item (one global atomic per workgroup).
 constexpr uint32_t kInfoWords = sizeof(CallInfo) / 8, kGridWords = sizeof(DevGrid) / 8,
                    kScanWords = sizeof(DevScan) / 8;
 constexpr uint32_t kOneDescWords = kInfoWords + kGridWords + kScanWords;
 static_assert(kOneDescWords <= 64 && kCtrlWords + SC_N + TC_N <= (uint32_t)kPtThreads - 128, "one pass of workgroup 0");
 constexpr uint32_t kScanPieces = sizeof(DevScan) / 16;
-static_assert(sizeof(CallInfo) == 16 && offsetof(DevGrid, nx) == 32 && sizeof(DevScan) % 16 == 0 &&
-                  2 + kScanPieces <= 64,
+constexpr uint32_t kGridPieces = (sizeof(DevGrid) + 15) / 16;
+static_assert(sizeof(CallInfo) == 16 && sizeof(DevScan) % 16 == 0 && 1 + kGridPieces + kScanPieces <= 64,
               "the one-scan front pass reads the descriptors in these 16-byte pieces");
 
-template <bool ONE>
+// Shadow ball radius in voxels (the largest r with r^2 <= r_s^2), clipped to
+// the kernel radius; -1 without a shadow.
+__device__ __forceinline__ int shadow_extent(const DevTables &t) {
+    if (t.shadow_r2 < 0) return -1;
+    int rs = 0;
+    while (rs < t.R && (rs + 1) * (rs + 1) <= t.shadow_r2) ++rs;
+    return rs;
+}
+
+// The tiles a return's list entries go to: those its window (extent R) or,
+// for a revisit, its shadow ball reaches, as a box of tile coordinates.
+struct TileSpan {
+    uint32_t x0, y0, z0, nx, ny, nz;   // first tile and tiles per axis (nx = 0: none)
+};
+__device__ __forceinline__ TileSpan tile_span(uint32_t vx, uint32_t vy, uint32_t vz, int ext) {
+    TileSpan sp{0u, 0u, 0u, 0u, 0u, 0u};
+    if (ext < 0) return sp;
+    const uint32_t e = (uint32_t)ext;   // vx, vy, vz >= R >= ext (the bounds rule)
+    sp.x0 = (vx - e) / kTileX;
+    sp.y0 = (vy - e) / kTileY;
+    sp.z0 = (vz - e) / kTileZ;
+    sp.nx = (vx + e) / kTileX - sp.x0 + 1u;
+    sp.ny = (vy + e) / kTileY - sp.y0 + 1u;
+    sp.nz = (vz + e) / kTileZ - sp.z0 + 1u;
+    return sp;
+}
+// The tile strategy's counter of tile id: the per-grid counter arrays hold a
+// power of two of entries, indexed by id times an odd constant modulo that
+// size (a bijection), so that the counters of neighbouring tiles, which the
+// returns of one neighbourhood update together, lie on different cache lines.
+__device__ __forceinline__ uint32_t tile_ctr(const DevGrid &g, uint32_t id) {
+    const unsigned long long n = (unsigned long long)g.nbx * g.nby * g.nbz;
+    const unsigned long long cap = n <= 1ull ? 1ull : 1ull << (64 - __clzll(n - 1ull));
+    return (uint32_t)((id * 0x9E3779B1u) & (uint32_t)(cap - 1ull));
+}
+__device__ __forceinline__ uint32_t span_tile(const TileSpan &sp, uint32_t j, const DevGrid &g) {
+    const uint32_t jx = j % sp.nx, jy = (j / sp.nx) % sp.ny, jz = j / (sp.nx * sp.ny);
+    return (sp.x0 + jx) + g.nbx * ((sp.y0 + jy) + g.nby * (sp.z0 + jz));
+}
+
+template <bool ONE, bool TILE>
 __global__ __launch_bounds__(kPtThreads) void k_front(PipeArgs a, const CallInfo *info_dev) {
-    __shared__ uint4 s_desc[ONE ? 2 + kScanPieces : 1];
+    __shared__ uint4 s_desc[ONE ? 1 + kGridPieces + kScanPieces : 1];
+    __shared__ uint32_t s_tmp[kPtThreads / 64];
+    __shared__ uint32_t s_base;
     const CallInfo *info = info_dev;
     const DevScan *scans = a.scans;
     const DevGrid *grids = a.grids;
-    DevGrid g_one{};
     if constexpr (ONE) {
         const uint32_t t = threadIdx.x;
-        // host layout: CallInfo, DevGrid[grids_cap] and, at desc_scans_off
-        // (a multiple of 16), DevScan[n_scans]; piece 1 is the grid's
-        // nx, ny, nz (and nbx), pieces 2 on the scan
+        // host layout: CallInfo, DevGrid[grids_cap] (16-byte pieces 1 on) and,
+        // at desc_scans_off (a multiple of 16), DevScan[n_scans]
         const uint4 *h16 = reinterpret_cast<const uint4 *>(a.host_desc);
-        if (t < 2u + kScanPieces) s_desc[t] = h16[t == 0u ? 0u : t == 1u ? 3u : a.desc_scans_off / 16u + (t - 2u)];
+        if (t < 1u + kGridPieces + kScanPieces)
+            s_desc[t] = h16[t <= kGridPieces ? t : a.desc_scans_off / 16u + (t - 1u - kGridPieces)];
         if (blockIdx.x == 0) {
             if (t >= 64u && t < 64u + kOneDescWords) {
                 const uint32_t w = t - 64u;
                 const uint32_t src = w < kInfoWords + kGridWords ? w : a.desc_scans_off / 8u + (w - kInfoWords - kGridWords);
                 reinterpret_cast<uint2 *>(a.ctrl + 1)[src] = a.host_desc[src];
             } else if (t >= 128u) {
-                reset_counters(a, 1u, 1u, t - 128u, kPtThreads - 128u);
+                // the tile strategy's work-item counter is in use by this pass:
+                // the select pass of the previous call cleared it
+                reset_counters(a, 1u, 1u, t - 128u, kPtThreads - 128u, TILE);
             }
         }
         __syncthreads();
         info = reinterpret_cast<const CallInfo *>(s_desc);
-        g_one.nx = s_desc[1].x;
-        g_one.ny = s_desc[1].y;
-        g_one.nz = s_desc[1].z;
-        scans = reinterpret_cast<const DevScan *>(s_desc + 2);
+        grids = reinterpret_cast<const DevGrid *>(s_desc + 1);
+        scans = reinterpret_cast<const DevScan *>(s_desc + 1 + kGridPieces);
     }
     const uint32_t n = info->n_points, n_scans = info->n_scans;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const uint32_t s = ONE ? 0u : find_scan(scans, n_scans, i);
-        const DevScan &sc = scans[s];
-        const DevGrid &g = ONE ? g_one : grids[sc.grid];
-        const uint32_t j = i - sc.begin;
-        const float *pp = sc.pts + 3 * (size_t)j * sc.step;
-        const float px = pp[0];
-        const float py = pp[1];
-        const float pz = pp[2];
-        const bool deskew = sc.deskew != 0u;
-        const float tau = deskew ? sc.times[(size_t)j * sc.step] : 0.0f;
-        int vx = 0, vy = 0, vz = 0, bin = 0;
-        const uint32_t st = front_end(sc, g, a.tab, px, py, pz, deskew, tau, vx, vy, vz, bin);
-        uint32_t slot = kNoSlot;
-        if (st == kStOk && sc.dedup) {
+    const int R = a.tab.R;
+    const int rs = TILE ? shadow_extent(a.tab) : 0;
+    const uint32_t F = a.span[0] * a.span[1] * a.span[2];
+    // block-uniform rounds (the tile claims synchronise the workgroup)
+    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+        const uint32_t i = base + threadIdx.x;
+        uint32_t n_open = 0, gi = 0;
+        unsigned long long opened = 0;   // list j of the return opened its tile
+        TileSpan sp{0u, 0u, 0u, 0u, 0u, 0u};
+        if (i < n) {
+            const uint32_t s = ONE ? 0u : find_scan(scans, n_scans, i);
+            const DevScan &sc = scans[s];
+            gi = ONE ? 0u : sc.grid;
+            const DevGrid &g = grids[gi];
+            const uint32_t j = i - sc.begin;
+            const gf32 *pp = globf(sc.pts) + 3 * (size_t)j * sc.step;
+            const float px = pp[0];
+            const float py = pp[1];
+            const float pz = pp[2];
+            const bool deskew = sc.deskew != 0u;
+            const float tau = deskew ? globf(sc.times)[(size_t)j * sc.step] : 0.0f;
+            int vx = 0, vy = 0, vz = 0, bin = 0;
+            const uint32_t st = front_end(sc, g, a.tab, px, py, pz, deskew, tau, vx, vy, vz, bin);
+            uint32_t slot = kNoSlot;
             const unsigned long long lin = (unsigned long long)vx +
                 (unsigned long long)g.nx * ((unsigned long long)vy + (unsigned long long)g.ny * (unsigned long long)vz);
-            const unsigned long long key = ((unsigned long long)s << kVoxelKeyBits) | lin;
-            uint32_t h = hash_of(key) & a.hash_mask;
-            for (;;) {  // the table holds >= 2x the call's points, so an empty slot exists
-                const unsigned long long prev = atomicCAS(&a.hkeys[h], kHashEmpty, key);
-                if (prev == kHashEmpty || prev == key) {
-                    atomicMin(&a.hvals[h], i);
-                    break;
+            if (st == kStOk && sc.dedup) {
+                const unsigned long long key = ((unsigned long long)s << kVoxelKeyBits) | lin;
+                uint32_t h = hash_of(key) & a.hash_mask;
+                for (;;) {  // the table holds >= 2x the call's points, so an empty slot exists
+                    const unsigned long long prev = atomicCAS(&a.hkeys[h], kHashEmpty, key);
+                    if (prev == kHashEmpty || prev == key) {
+                        atomicMin(&a.hvals[h], i);
+                        break;
+                    }
+                    h = (h + 1) & a.hash_mask;
                 }
-                h = (h + 1) & a.hash_mask;
+                slot = h;
             }
-            slot = h;
+            uint32_t w = (st << 16) | (uint32_t)bin;
+            if constexpr (TILE) {
+                if (st == kStOk) {
+                    // a return in a voxel an earlier call integrated (mask 0)
+                    // skips its window: its lists are those of its shadow
+                    const bool rv = a.revisit_ok && g.revisit_skip && glob(g.mask)[lin] == 0u;
+                    if (rv) w |= kRecTileRevisit;
+                    sp = tile_span((uint32_t)vx, (uint32_t)vy, (uint32_t)vz, rv ? rs : R);
+                    const uint32_t np = sp.nx * sp.ny * sp.nz;
+                    for (uint32_t j0 = 0; j0 < np; j0 += kFrontUnroll) {
+                        uint32_t rk[kFrontUnroll];
+#pragma unroll
+                        for (int u = 0; u < kFrontUnroll; ++u)
+                            rk[u] = j0 + u < np ? g_add(glob(g.brick_cnt) + tile_ctr(g, span_tile(sp, j0 + u, g)), 1u) : 1u;
+#pragma unroll
+                        for (int u = 0; u < kFrontUnroll; ++u) {
+                            if (j0 + u >= np) continue;
+                            a.rank[(size_t)i * F + j0 + u] = rk[u];
+                            if (rk[u] == 0u) {
+                                ++n_open;
+                                opened |= 1ull << (j0 + u);
+                            }
+                        }
+                    }
+                }
+            }
+            a.rec[i] = make_uint4((uint32_t)vx, (uint32_t)vy, (uint32_t)vz, w);
+            a.pslot[i] = slot;
         }
-        a.rec[i] = make_uint4((uint32_t)vx, (uint32_t)vy, (uint32_t)vz, (st << 16) | (uint32_t)bin);
-        a.pslot[i] = slot;
+        if constexpr (TILE) {
+            uint32_t total;
+            const uint32_t pos = block_excl_scan<kPtThreads>(n_open, s_tmp, total);
+            if (total) {
+                if (threadIdx.x == 0) s_base = atomicAdd(&a.ctrl->n_active, total);
+                __syncthreads();
+                if (n_open) {
+                    const DevGrid &g = grids[gi];
+                    uint32_t k = 0;
+                    for (uint32_t j = 0; j < 64u && opened; ++j) {
+                        if (!((opened >> j) & 1ull)) continue;
+                        opened &= ~(1ull << j);
+                        const uint32_t id = span_tile(sp, j, g);
+                        const uint32_t slot = s_base + pos + k++;
+                        a.items[slot] = ((unsigned long long)gi << 32) | id;
+                    }
+                }
+                __syncthreads();  // s_base is reused by the next round
+            }
+        }
     }
 }
 
@@ -429,25 +592,6 @@ __device__ __forceinline__ SelectOut select_point(const PipeArgs &a, const CallI
     return o;
 }
 
-// Exclusive prefix of v over the block; *total receives the block sum.
-template <int THREADS>
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_tmp, uint32_t &total) {
-    const uint32_t w = threadIdx.x >> 6;
-    const uint32_t incl = wave_incl_scan_u32(v);
-    if (lane() == 63u) s_tmp[w] = incl;
-    __syncthreads();
-    uint32_t before = 0, tot = 0;
-#pragma unroll
-    for (int k = 0; k < THREADS / 64; ++k) {
-        const uint32_t x = s_tmp[k];
-        before += (uint32_t)k < w ? x : 0u;
-        tot += x;
-    }
-    __syncthreads();
-    total = tot;
-    return before + incl - v;
-}
-
 // brick j of the (at most span[0] x span[1] x span[2]) bricks a K^3 cube touches
 __device__ __forceinline__ bool pair_brick(const PipeArgs &a, const uint4 &r, uint32_t j, const DevGrid &g,
                                            uint32_t &id) {
@@ -469,7 +613,6 @@ __device__ __forceinline__ bool pair_brick(const PipeArgs &a, const uint4 &r, ui
 // that they are in flight together); the returned old count is the pair's
 // rank in the brick's list. Pairs that open a brick take work-item slots,
 // one global atomic per block.
-constexpr int kSelUnroll = 6;
 
 __global__ __launch_bounds__(kSelThreads) void k_select_pairs(PipeArgs a, const CallInfo *info) {
     __shared__ uint32_t s_tmp[kSelThreads / 64];
@@ -493,7 +636,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_pairs(PipeArgs a, const 
                 for (int u = 0; u < kSelUnroll; ++u) {
                     uint32_t id = 0;
                     v[u] = j0 + u < F && pair_brick(a, o.r, j0 + u, g, id);
-                    rk[u] = v[u] ? atomicAdd(&g.brick_cnt[id], 1u) : 1u;
+                    rk[u] = v[u] ? g_add(glob(g.brick_cnt) + id, 1u) : 1u;
                 }
 #pragma unroll
                 for (int u = 0; u < kSelUnroll; ++u) {
@@ -518,7 +661,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_pairs(PipeArgs a, const 
                 if (!op || !pair_brick(a, o.r, j, g, id)) continue;
                 const uint32_t slot = s_base + pos + k++;
                 a.items[slot] = ((unsigned long long)gi << 32) | id;
-                g.brick_slot[id] = slot;
+                glob(g.brick_slot)[id] = slot;
             }
             __syncthreads();
         }
@@ -590,7 +733,8 @@ __global__ __launch_bounds__(kPtThreads) void k_offsets(PipeArgs a) {
         uint32_t cnt = 0;
         if (t < n) {
             const unsigned long long it = a.items[t];
-            uint32_t *bc = a.grids[it >> 32].brick_cnt + (uint32_t)it;
+            const DevGrid &g = a.grids[it >> 32];
+            gu32 *bc = glob(g.brick_cnt) + (a.tile_mode ? tile_ctr(g, (uint32_t)it) : (uint32_t)it);
             cnt = *bc;
             *bc = 0u;
         }
@@ -608,6 +752,11 @@ __global__ __launch_bounds__(kPtThreads) void k_offsets(PipeArgs a) {
             const uint32_t first = wbase + incl - cnt;
             a.item_off[t] = first;
             a.item_cnt[t] = cnt;
+            // the tile strategy's fill finds the list's first entry beside the counter
+            if (a.tile_mode) {
+                const DevGrid &g = a.grids[it >> 32];
+                glob(g.brick_slot)[tile_ctr(g, (uint32_t)it)] = first;
+            }
             const uint32_t split = nsub > 1u ? 0x80000000u : 0u;
             for (uint32_t k = 0; k < nsub; ++k) {
                 const uint32_t s0 = a.chunk ? k * a.chunk : 0u;
@@ -639,7 +788,7 @@ __global__ __launch_bounds__(kPtThreads) void k_fill_pairs(PipeArgs a, const Cal
             for (int u = 0; u < kSelUnroll; ++u) {  // independent loads, all in flight
                 uint32_t id = 0;
                 v[u] = j0 + u < F && pair_brick(a, r, j0 + u, g, id);
-                item[u] = v[u] ? g.brick_slot[id] : 0u;
+                item[u] = v[u] ? glob(g.brick_slot)[id] : 0u;
                 rk[u] = v[u] ? a.rank[(size_t)i * F + j0 + u] : 0u;
             }
 #pragma unroll
@@ -741,7 +890,7 @@ __global__ __launch_bounds__(THREADS) void k_apply_brick(PipeArgs a) {
                            gz = (uint32_t)(z0 + v / (BX * BY));
             linq[k] = (size_t)gx + (size_t)g.nx * ((size_t)gy + (size_t)g.ny * gz);
             fastq[k] = !split && vec_x && gx + 3u < g.nx && gy < g.ny && gz < g.nz;
-            if (fastq[k]) pm[k] = *reinterpret_cast<const uint4 *>(g.mask + linq[k]);
+            if (fastq[k]) pm[k] = gload4(reinterpret_cast<const uint4 *>(g.mask + linq[k]), 0);
         }
 
         for (int q = threadIdx.x; q < TILE / 4; q += THREADS) {
@@ -873,7 +1022,7 @@ __global__ __launch_bounds__(THREADS) void k_apply_brick(PipeArgs a) {
                 lin[k] = linq[k0 + k];
                 fast[k] = fastq[k0 + k];
                 om[k] = pm[k0 + k];
-                if (fast[k] && any_c) op[k] = *reinterpret_cast<const uint4 *>(g.packed + lin[k]);
+                if (fast[k] && any_c) op[k] = gload4(reinterpret_cast<const uint4 *>(g.packed + lin[k]), 0);
             }
 #pragma unroll
             for (int k = 0; k < NB; ++k) {
@@ -890,7 +1039,7 @@ __global__ __launch_bounds__(THREADS) void k_apply_brick(PipeArgs a) {
                             cm += nw[j] != o[j];
                             ch |= nw[j] != o[j];
                         }
-                        if (ch) *reinterpret_cast<uint4 *>(g.mask + lin[k]) = make_uint4(nw[0], nw[1], nw[2], nw[3]);
+                        if (ch) gstore4(g.mask + lin[k], nw[0], nw[1], nw[2], nw[3]);
                     }
                     if (need_c[k]) {
                         const uint32_t o[4] = {op[k].x, op[k].y, op[k].z, op[k].w};
@@ -905,7 +1054,7 @@ __global__ __launch_bounds__(THREADS) void k_apply_brick(PipeArgs a) {
                             us += sc[k][j] != 0u;
                             ch |= nw[j] != o[j];
                         }
-                        if (ch) *reinterpret_cast<uint4 *>(g.packed + lin[k]) = make_uint4(nw[0], nw[1], nw[2], nw[3]);
+                        if (ch) gstore4(g.packed + lin[k], nw[0], nw[1], nw[2], nw[3]);
                     }
                     continue;
                 }
@@ -919,21 +1068,21 @@ __global__ __launch_bounds__(THREADS) void k_apply_brick(PipeArgs a) {
                     if (!split) {
                         // grid edge or Nx not a multiple of 4: element by element
                         if (sm[k][j] != 0xFFFFFFFFu) {
-                            const uint32_t old = g.mask[li];
+                            const uint32_t old = glob(g.mask)[li];
                             const uint32_t nw = old & sm[k][j];
                             if (nw != old) {
-                                g.mask[li] = nw;
+                                glob(g.mask)[li] = nw;
                                 ++cm;
                             }
                             ++um;
                         }
                         if (sc[k][j]) {
-                            const uint32_t old = g.packed[li];
+                            const uint32_t old = glob(g.packed)[li];
                             const uint32_t h0 = old & 0xFFFFu;
                             const uint32_t h1 = min(h0 + sc[k][j], g.hmax);
                             const uint32_t sign = (h0 < g.T && h1 >= g.T) ? 0u : (old & 0x80000000u);
                             const uint32_t nw = sign | h1;
-                            if (nw != old) g.packed[li] = nw;
+                            if (nw != old) glob(g.packed)[li] = nw;
                             ++us;
                         }
                     } else {
@@ -942,18 +1091,18 @@ __global__ __launch_bounds__(THREADS) void k_apply_brick(PipeArgs a) {
                         // (c steps of eq. 5 then d steps equal c + d steps, and eq. 6
                         // fires once on the crossing, so the merge order does not matter)
                         if (sm[k][j] != 0xFFFFFFFFu) {
-                            const uint32_t old = g.mask[li];
-                            if ((old & sm[k][j]) != old) atomicAnd(&g.mask[li], sm[k][j]);
+                            const uint32_t old = glob(g.mask)[li];
+                            if ((old & sm[k][j]) != old) g_and(glob(g.mask) + li, sm[k][j]);
                         }
                         if (sc[k][j]) {
-                            uint32_t old = g.packed[li];
+                            uint32_t old = glob(g.packed)[li];
                             for (;;) {
                                 const uint32_t h0 = old & 0xFFFFu;
                                 const uint32_t h1 = min(h0 + sc[k][j], g.hmax);
                                 const uint32_t sign = (h0 < g.T && h1 >= g.T) ? 0u : (old & 0x80000000u);
                                 const uint32_t nw = sign | h1;
                                 if (nw == old) break;
-                                const uint32_t prev = atomicCAS(&g.packed[li], old, nw);
+                                const uint32_t prev = g_cas(glob(g.packed) + li, old, nw);
                                 if (prev == old) break;
                                 old = prev;
                             }
@@ -1029,7 +1178,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_atomic(PipeArgs a, const
             const DevGrid &g = a.grids[a.scans[s].grid];
             if (g.revisit_skip) {
                 const size_t v = (size_t)r.x + (size_t)g.nx * ((size_t)r.y + (size_t)g.ny * (size_t)r.z);
-                revisit = g.mask[v] == 0u ? kRecRevisit : 0u;
+                revisit = glob(g.mask)[v] == 0u ? kRecRevisit : 0u;
             }
         }
         uint32_t c[SC_N];
@@ -1418,6 +1567,486 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const C
             }
         }
     }
+}
+
+// ======================================================== tile strategy ===
+// Returns are listed by grid tile (kTileX x kTileY x kTileZ words) in the
+// front pass; k_offsets lays the lists out; k_select_fill takes the survivor
+// test and writes each return into its lists (a return that lost the
+// first-return test leaves a hole); k_apply_tile gives each tile to one
+// workgroup, which takes in LDS, per word of the tile, the smallest eq. 3
+// metric value q over the windows of the tile's listed returns (ds_min; the
+// mask of the smallest q is the AND of all their masks, eq. 3 being
+// monotone in q) and the number of shadow hits, then reads, updates and
+// writes each touched word of both planes once with plain 16-byte loads and
+// stores. Every word has one owner tile, so no atomic touches the planes.
+
+// Survivor test, statistics and list fill of the tile strategy (one thread
+// per return). Only the slot's winner releases a dedup slot (as in
+// k_select_atomic). The last workgroup writes the statistics into the ring
+// slot; workgroup 0 clears the work-item counter the next call's front pass
+// counts on (every reader of it, the offsets pass, is done).
+__global__ __launch_bounds__(kSelThreads) void k_select_fill(PipeArgs a, const CallInfo *info) {
+    __shared__ uint32_t s_red[SC_N][kSelThreads / 64];
+    const uint32_t n = info->n_points;
+    const int R = a.tab.R;
+    const int rs = shadow_extent(a.tab);
+    const uint32_t F = a.span[0] * a.span[1] * a.span[2];
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.ctrl->n_active = 0u;
+    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+        const uint32_t i = base + threadIdx.x;
+        const bool live = i < n;
+        uint4 r = make_uint4(0u, 0u, 0u, 0u);
+        uint32_t s = 0, st = 3u;
+        bool surv = false, rv = false;
+        if (live) {
+            r = a.rec[i];
+            st = (r.w >> 16) & 3u;
+            s = find_scan(a.scans, info->n_scans, i);
+            if (st == kStOk) {
+                if (a.scans[s].dedup) {
+                    const uint32_t slot = a.pslot[i];
+                    surv = a.hvals[slot] == i;
+                    if (surv) {
+                        a.hkeys[slot] = kHashEmpty;
+                        a.hvals[slot] = 0xFFFFFFFFu;
+                    }
+                } else {
+                    surv = true;
+                }
+                rv = (r.w & kRecTileRevisit) != 0u;
+                const DevGrid &g = a.grids[a.scans[s].grid];
+                const TileSpan sp = tile_span(r.x, r.y, r.z, rv ? rs : R);
+                const uint32_t np = sp.nx * sp.ny * sp.nz;
+                const uint4 e = surv ? make_uint4(r.x, r.y, r.z, (r.w & 0xFFFFu) | (rv ? kRecRevisit : 0u))
+                                     : make_uint4(kTileHole, kTileHole, kTileHole, kTileHole);
+                for (uint32_t j0 = 0; j0 < np; j0 += kSelUnroll) {
+                    uint32_t slot[kSelUnroll], rk[kSelUnroll];
+#pragma unroll
+                    for (int u = 0; u < kSelUnroll; ++u) {  // independent loads, all in flight
+                        const bool v = j0 + u < np;
+                        slot[u] = v ? glob(g.brick_slot)[tile_ctr(g, span_tile(sp, j0 + u, g))] : 0u;
+                        rk[u] = v ? a.rank[(size_t)i * F + j0 + u] : 0u;
+                    }
+#pragma unroll
+                    for (int u = 0; u < kSelUnroll; ++u)
+                        if (j0 + u < np) a.entries[slot[u] + rk[u]] = e;
+                }
+            }
+        }
+        uint32_t c[SC_N];
+        c[SC_INVALID] = st == kStInvalid;
+        c[SC_OOB] = st == kStOob;
+        c[SC_DUP] = st == kStOk && !surv;
+        c[SC_INT] = surv;
+        c[SC_SHADOW] = surv ? a.tab.sh_start[(r.w & 0xFFFFu) + 1] - a.tab.sh_start[r.w & 0xFFFFu] : 0u;
+        c[SC_REVISIT] = surv && rv;
+        const uint32_t last = min(n, base + blockDim.x) - 1u;
+        const uint32_t s_lo = find_scan(a.scans, info->n_scans, base);
+        const bool one_scan = s_lo == find_scan(a.scans, info->n_scans, last);
+        if (one_scan) {
+#pragma unroll
+            for (int f = 0; f < SC_N; ++f) {
+                const uint32_t v = wave_sum_u32(c[f]);
+                if (lane() == 0) s_red[f][threadIdx.x >> 6] = v;
+            }
+            __syncthreads();
+            if (threadIdx.x < SC_N) {
+                unsigned long long sum = 0;
+                for (int k = 0; k < kSelThreads / 64; ++k) sum += s_red[threadIdx.x][k];
+                if (sum) atomicAdd(&a.scan_ctr[(size_t)s_lo * SC_N + threadIdx.x], sum);
+            }
+            __syncthreads();
+        } else {
+#pragma unroll
+            for (int f = 0; f < SC_N; ++f) wave_add(a.scan_ctr, s, (uint32_t)f, c[f]);
+        }
+    }
+    // the statistics out, by the last workgroup to finish (as k_select_atomic)
+    __shared__ uint32_t s_last;
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0)
+        s_last = __hip_atomic_fetch_add(&a.ctrl->select_done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                         gridDim.x - 1u
+                     ? 1u
+                     : 0u;
+    __syncthreads();
+    if (s_last) {
+        const uint32_t n_s = info->n_scans * SC_N, n_t = info->n_grids * TC_N;
+        for (uint32_t i = threadIdx.x; i < n_s + n_t; i += blockDim.x) {
+            unsigned long long *src = i < n_s ? &a.scan_ctr[i] : &a.traffic_ctr[i - n_s];
+            a.host_ctr[i < n_s ? (size_t)i : (size_t)a.scans_cap * SC_N + (i - n_s)] =
+                __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");  // system scope: the host reads them
+    }
+}
+
+// One workgroup per tile work item (persistent: items dealt round-robin over
+// the workgroups of one XCD, each XCD taking a contiguous eighth of the list).
+// LDS holds, per word of the tile, the eq. 3 stamp as a 16-bit mask
+// (2^n - 1; 0xFFFF where no window reaches, the identity of the AND) and the
+// shadow hit count as a byte; rows of 32 words are padded to 36 so that
+// neighbouring rows fall in different banks. The tile's list is taken in
+// rounds of at most 255 entries (a count byte cannot overflow: an entry adds
+// at most one hit to a word):
+//   1. stamps and counts cleared, the round's entries staged in LDS;
+//   2. one thread per entry: the rows it walks, clipped to the tile (the
+//      window's (y, z) rows for a return that applies its window, the shadow
+//      ball's for one whose voxel an earlier call integrated), and the row
+//      counts' prefix over the round, with a bitmap of the rows where an
+//      entry starts;
+//   3. the rows of all entries are dealt to the lanes, 64 consecutive rows a
+//      wavefront: a lane finds its entry by counting the starts below its row
+//      in the bitmap, ANDs its window row's masks in with one ds_and_b64 per
+//      4-word quad (the masks of the row kernel's table for the window's
+//      alignment phase), and, where the row lies in the shadow ball, adds the
+//      row's hits (bits of the bin's shadow row) with one ds_add_u32 of four
+//      count bytes per word quad;
+//   4. the round is merged, four 16-byte quads per thread, every load issued
+//      before any store: mask &= the stamp (stored when changed); h = min(h +
+//      c, H_max) with the sign cleared on the crossing h < T <= h + c (eqs.
+//      5-6 for c unit steps). A tile of several rounds merges each in turn
+//      (AND is idempotent and c then d steps are c + d steps).
+// Needs the row kernel's tables (K <= 11, at most 31 bins, r_s^2 <= 9).
+constexpr int kTileThreads = 256;
+constexpr uint32_t kTileRound = 255;                    // entries per round
+constexpr uint32_t kTileRows = kTileY * kTileZ;         // (y, z) rows of a tile
+constexpr uint32_t kTileQx = kTileX / 4;                // quads per row
+constexpr uint32_t kTilePq = kTileQx + 1;               // LDS row pitch in quads (odd: rows spread over banks)
+constexpr uint32_t kTileLayer = kTilePq * kTileY + 1;   // LDS z-layer pitch in quads (layers spread over banks)
+constexpr uint32_t kTileSlots = kTileLayer * kTileZ;
+// the hit counts: a byte per word, rows of 8 count words padded to 10 (8-byte
+// pairs at an odd pitch), z layers to 162 words
+constexpr uint32_t kCntPitch = 10, kCntLayer = kCntPitch * kTileY + 2, kCntSlots = kCntLayer * kTileZ;
+constexpr uint32_t kTileQuadsPerThread = kTileRows * kTileQx / kTileThreads;
+constexpr uint32_t kShadowRows = 49;                    // (dy, dz) in [-3, 3]^2
+constexpr uint32_t kRowsMax = kTileRound * 11u * kTileZ;   // rows of a round (windows of 11 rows, clipped z)
+constexpr uint32_t kRowBlocks = (kRowsMax + 63) / 64;
+constexpr uint32_t kMtRows = 11u * 11u;                 // window rows of K <= 11
+static_assert(kTileRows * kTileQx % kTileThreads == 0, "whole quads per thread");
+static_assert(kTileRound < kTileThreads, "one entry per thread in the set-up");
+
+__device__ __forceinline__ uint32_t spread4(uint32_t b4) {   // bit j -> byte j
+    return (b4 * 0x00204081u) & 0x01010101u;
+}
+
+__global__ __launch_bounds__(kTileThreads, 3) void k_apply_tile(PipeArgs a) {
+    __shared__ __align__(16) uint2 stamp[kTileSlots];      // 4 x 16-bit masks per quad
+    __shared__ __align__(16) uint32_t cnt[kCntSlots];      // 4 x 8-bit hit counts per word of counts
+    __shared__ __align__(16) uint2 mt[4][kMtRows][4];               // masks by (phase, window row, quad)
+    __shared__ uint8_t smask[kRowBins * kShadowRows];               // shadow x bits (dx + 3) per (bin, dy, dz)
+    // per entry with rows, in round order: box and point (tile-local), row
+    // magic and bin, first row
+    __shared__ uint4 info[kTileRound];
+    __shared__ unsigned long long starts[kRowBlocks];  // bit: an entry's first row
+    __shared__ uint16_t block_base[kRowBlocks];        // entries with rows starting before the block
+    __shared__ uint32_t s_scan[kTileThreads / 64 + 1];
+    __shared__ uint32_t s_magic[kTileY + 1];
+    const DevTables &t = a.tab;
+    if (threadIdx.x <= kTileY) s_magic[threadIdx.x] = threadIdx.x ? (65536u + threadIdx.x - 1u) / threadIdx.x : 0u;
+    const int R = t.R, K = t.K;
+    const int rs = shadow_extent(t);
+    {
+        // the row kernel's table mtab[sel][row] (sel = 4 qd + 3 - phase) laid
+        // out by (phase, row) so that a row's four quads are contiguous
+        const uint2 *mtab = reinterpret_cast<const uint2 *>(t.row_image) + kImgMtab / 2;
+        for (uint32_t i = threadIdx.x; i < 4u * kMtRows * 4u; i += kTileThreads) {
+            const uint32_t ph = i / (kMtRows * 4u), row = (i / 4u) % kMtRows, qd = i % 4u;
+            mt[ph][row][qd] = (int)row < K * K ? mtab[(4u * qd + 3u - ph) * kRowPad + row] : make_uint2(~0u, ~0u);
+        }
+        // each bin's shadow set as 7-bit x rows, from its 343-bit set (bits
+        // (dx + 3) + 7 (dy + 3) + 49 (dz + 3))
+        const uint32_t *bits = reinterpret_cast<const uint32_t *>(t.row_image) + kImgShBits;
+        for (uint32_t i = threadIdx.x; i < t.n_bins * kShadowRows; i += kTileThreads) {
+            const uint32_t b = i / kShadowRows, p = 7u * (i % kShadowRows);
+            const uint32_t w = p >> 5, o = p & 31u;
+            uint32_t v = bits[b * kShadowSetWords + w] >> o;
+            if (o > 25u) v |= bits[b * kShadowSetWords + w + 1] << (32u - o);
+            smask[i] = (uint8_t)(v & 0x7Fu);
+        }
+    }
+    const uint32_t l = lane();
+    const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    constexpr uint32_t kWaves = kTileThreads / 64;
+    const uint32_t n_work = a.ctrl->n_work;
+    // Work items are dealt round-robin. The next item's descriptor and first
+    // round of entries (a thread holds at most one of them) are loaded one
+    // item ahead, the descriptor of the item after it two ahead; each is taken
+    // into registers before the plane loads of a round are issued, so that
+    // no wait for them also waits for those (vector loads complete in order),
+    // and every barrier here orders LDS only.
+    const uint32_t G = gridDim.x;
+    // Loads of a work item's descriptor (uniform, but loaded per lane so that
+    // it is waited for with the vector loads) and of one entry per lane; zero
+    // where the condition fails. Both go to global memory directly.
+    auto vload = [&](const uint4 *p, uint32_t i, bool c) {
+        uint32_t v = i;
+        asm volatile("" : "+v"(v));
+        uint4 r = make_uint4(0u, 0u, 0u, 0u);
+        if (c) r = gload4(p, v);
+        return r;
+    };
+    auto eload = [&](uint32_t i, bool c) {
+        uint4 r = make_uint4(0u, 0u, 0u, 0u);
+        if (c) r = gload4(a.entries, i);
+        return r;
+    };
+    uint32_t wi = blockIdx.x;
+    uint4 wk = vload(a.work, wi, wi < n_work);
+    uint4 ent_cur = eload(wk.z + threadIdx.x, wi < n_work && threadIdx.x < min(wk.w & 0x7FFFFFFFu, kTileRound));
+    uint4 wk_next = vload(a.work, wi + G, wi + G < n_work);
+    for (uint32_t c = threadIdx.x; c < kRowBlocks; c += kTileThreads) starts[c] = 0ull;
+    // the grid of the last item (loaded again only when it changes)
+    uint32_t cur_gi = 0u;
+    DevGrid g = uniform_grid(a.grids[0]);
+    // The merge of a round is split: right after its rows, each thread takes
+    // the stamps and counts of its quads into registers and issues the loads
+    // of the words they touch (issue); the stores follow after the next
+    // round's set-up and rows (finish), so that the loads' latency is spent
+    // on that work.
+    uint2 sq[kTileQuadsPerThread];
+    uint32_t cq[kTileQuadsPerThread];
+    u32x4 om[kTileQuadsPerThread], op[kTileQuadsPerThread];
+    bool pend = false;
+    int pX0 = 0, pY0 = 0, pZ0 = 0;
+    DevGrid pg = g;
+    auto quad_of = [&](uint32_t k, uint32_t &gx, uint32_t &gy, uint32_t &gz) {
+        const uint32_t qi = threadIdx.x + k * kTileThreads;
+        const uint32_t row = qi / kTileQx;
+        gx = (uint32_t)pX0 + 4u * (qi % kTileQx);
+        gy = (uint32_t)pY0 + row % kTileY;
+        gz = (uint32_t)pZ0 + row / kTileY;
+    };
+    auto fast_quad = [&](uint32_t gx, uint32_t gy, uint32_t gz) {
+        return (pg.nx & 3u) == 0u && gx + 3u < pg.nx && gy < pg.ny && gz < pg.nz;
+    };
+    auto issue = [&](int X0, int Y0, int Z0, const DevGrid &gi) {
+        pX0 = X0;
+        pY0 = Y0;
+        pZ0 = Z0;
+        pg = gi;
+#pragma unroll
+        for (uint32_t k = 0; k < kTileQuadsPerThread; ++k) {
+            const uint32_t qi = threadIdx.x + k * kTileThreads;
+            const uint32_t row = qi / kTileQx, qxm = qi % kTileQx;
+            sq[k] = stamp[qxm + kTilePq * (row % kTileY) + kTileLayer * (row / kTileY)];
+            cq[k] = cnt[qxm + kCntPitch * (row % kTileY) + kCntLayer * (row / kTileY)];
+            uint32_t gx, gy, gz;
+            quad_of(k, gx, gy, gz);
+            const size_t lin = (size_t)gx + (size_t)pg.nx * ((size_t)gy + (size_t)pg.ny * (size_t)gz);
+            if (fast_quad(gx, gy, gz)) {
+                if ((sq[k].x & sq[k].y) != ~0u) om[k] = *reinterpret_cast<const gu32x4 *>(glob(pg.mask) + lin);
+                if (cq[k] != 0u) op[k] = *reinterpret_cast<const gu32x4 *>(glob(pg.packed) + lin);
+            }
+        }
+        pend = true;
+    };
+    auto finish = [&]() {
+        pend = false;
+#pragma unroll
+        for (uint32_t k = 0; k < kTileQuadsPerThread; ++k) {
+            const bool nm = (sq[k].x & sq[k].y) != ~0u, nh = cq[k] != 0u;
+            if (!nm && !nh) continue;
+            uint32_t mm[4] = {sq[k].x & 0xFFFFu, sq[k].x >> 16, sq[k].y & 0xFFFFu, sq[k].y >> 16};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) mm[j] = mm[j] == 0xFFFFu ? ~0u : mm[j];
+            uint32_t gx, gy, gz;
+            quad_of(k, gx, gy, gz);
+            const size_t lin = (size_t)gx + (size_t)pg.nx * ((size_t)gy + (size_t)pg.ny * (size_t)gz);
+            if (fast_quad(gx, gy, gz)) {
+                if (nm) {
+                    const uint32_t o[4] = {om[k][0], om[k][1], om[k][2], om[k][3]};
+                    uint32_t nw[4];
+                    bool ch = false;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        nw[j] = o[j] & mm[j];
+                        ch |= nw[j] != o[j];
+                    }
+                    if (ch) gstore4(pg.mask + lin, nw[0], nw[1], nw[2], nw[3]);
+                }
+                if (nh) {
+                    const uint32_t o[4] = {op[k][0], op[k][1], op[k][2], op[k][3]};
+                    uint32_t nw[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const uint32_t c = (cq[k] >> (8 * j)) & 0xFFu;
+                        const uint32_t h0 = o[j] & 0xFFFFu;
+                        const uint32_t h1 = min(h0 + c, pg.hmax);
+                        const uint32_t sign = (h0 < pg.T && h1 >= pg.T) ? 0u : (o[j] & 0x80000000u);
+                        nw[j] = c ? (sign | h1) : o[j];
+                    }
+                    gstore4(pg.packed + lin, nw[0], nw[1], nw[2], nw[3]);
+                }
+                continue;
+            }
+            // a quad at the grid's x edge, or rows not 16-byte aligned: word by word
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (gx + (uint32_t)j >= pg.nx || gy >= pg.ny || gz >= pg.nz) continue;
+                const size_t li = lin + (size_t)j;
+                if (mm[j] != ~0u) {
+                    gu32 *pm = glob(pg.mask) + li;
+                    const uint32_t old = *pm;
+                    const uint32_t nw = old & mm[j];
+                    if (nw != old) *pm = nw;
+                }
+                const uint32_t c = (cq[k] >> (8 * j)) & 0xFFu;
+                if (c) {
+                    gu32 *pp = glob(pg.packed) + li;
+                    const uint32_t old = *pp;
+                    const uint32_t h0 = old & 0xFFFFu;
+                    const uint32_t h1 = min(h0 + c, pg.hmax);
+                    const uint32_t sign = (h0 < pg.T && h1 >= pg.T) ? 0u : (old & 0x80000000u);
+                    *pp = sign | h1;
+                }
+            }
+        }
+    };
+    while (wi < n_work) {
+        if (wk.y != cur_gi) {
+            cur_gi = wk.y;
+            g = uniform_grid(a.grids[cur_gi]);
+        }
+        const uint32_t brick = wk.x;
+        const uint32_t tx = brick % g.nbx, ty = (brick / g.nbx) % g.nby, tz = brick / (g.nbx * g.nby);
+        const int X0 = (int)(tx * kTileX), Y0 = (int)(ty * kTileY), Z0 = (int)(tz * kTileZ);
+        const uint32_t first = wk.z, total = wk.w & 0x7FFFFFFFu;
+        // the next item's first round of entries, where this item's last
+        // round is its first
+        const uint32_t next_first = wk_next.z;
+        const uint32_t next_nb = wi + G < n_work ? min(wk_next.w & 0x7FFFFFFFu, kTileRound) : 0u;
+        uint4 wk_nn = vload(a.work, wi + 2u * G, wi + 2u * G < n_work);   // the descriptor of the item after next
+        if (total == 0u) ent_cur = eload(next_first + threadIdx.x, threadIdx.x < next_nb);
+        for (uint32_t b0 = 0; b0 < total; b0 += kTileRound) {
+            const uint32_t nb = min(total - b0, kTileRound);
+            lds_barrier();   // the previous round's (or item's) merge is done with the arrays
+            for (uint32_t q = threadIdx.x; q < kTileSlots; q += kTileThreads) stamp[q] = make_uint2(~0u, ~0u);
+            for (uint32_t q = threadIdx.x; q < kCntSlots; q += kTileThreads) cnt[q] = 0u;
+            const uint4 r = ent_cur;
+            // the next round's entries: this item's next round, else the next item's first
+            const bool more = b0 + kTileRound < total;
+            const uint32_t pidx = more ? first + b0 + kTileRound : next_first;
+            const uint32_t pcnt = more ? min(total - b0 - kTileRound, kTileRound) : next_nb;
+            uint4 pe = eload(pidx + threadIdx.x, threadIdx.x < pcnt);
+            // per entry (thread e): the rows it walks, clipped to the tile
+            uint32_t rows = 0;
+            uint4 inf = make_uint4(0u, 0u, 0u, 0u);
+            if (threadIdx.x < nb && r.x != kTileHole) {
+                const int lx = (int)r.x - X0, ly = (int)r.y - Y0, lz = (int)r.z - Z0;
+                const bool rv = a.revisit_ok && (r.w & kRecRevisit);
+                const uint32_t bin = r.w & (a.revisit_ok ? kRowBinMask : 0xFFFFu);
+                const int ext = rv ? rs : R;
+                if (ext >= 0) {
+                    const int ya = max(ly - ext, 0), yb = min(ly + ext, (int)kTileY - 1);
+                    const int za = max(lz - ext, 0), zb = min(lz + ext, (int)kTileZ - 1);
+                    const int wy = yb - ya + 1, wz = zb - za + 1;
+                    if (wy > 0 && wz > 0 && lx + ext >= 0 && lx - ext < (int)kTileX) {
+                        rows = (uint32_t)(wy * wz);
+                        const uint32_t magic = s_magic[wy];   // r / wy = (r * magic) >> 16 for r < 256
+                        inf = make_uint4((uint32_t)ya | ((uint32_t)za << 4) | ((uint32_t)wy << 8) |
+                                             ((uint32_t)(lx + 16) << 12) | ((uint32_t)(ly + 16) << 18) |
+                                             ((uint32_t)(lz + 16) << 24) | (rv ? 1u << 30 : 0u),
+                                         magic | (bin << 17), 0u, 0u);   // magic: up to 2^16, 17 bits
+                    }
+                }
+            }
+            // one scan over the round: the rows before the entry (high bits)
+            // and the entries with rows before it (low 9 bits)
+            uint32_t tot;
+            const uint32_t ex = block_excl_scan<kTileThreads, true>((rows << 9) | (rows ? 1u : 0u), s_scan, tot);
+            const uint32_t n_rows = tot >> 9;
+            const uint32_t n_blocks = (n_rows + 63u) / 64u;
+            if (rows) {
+                const uint32_t k_e = ex & 511u, r0 = ex >> 9;
+                inf.z = r0;
+                info[k_e] = inf;
+                atomicOr(&starts[r0 >> 6], 1ull << (r0 & 63u));
+                // blocks whose first row lies after this entry's first row and
+                // at or before the next one's: this entry's index + 1 entries
+                // start before them
+                for (uint32_t c = (r0 >> 6) + 1u; c <= min((r0 + rows) >> 6, n_blocks - 1u); ++c)
+                    block_base[c] = (uint16_t)(k_e + 1u);
+            }
+            if (threadIdx.x == 0) block_base[0] = 0;
+            lds_barrier();
+            // the rows, 64 to a wavefront
+            for (uint32_t c = w; c < n_blocks; c += kWaves) {
+                const uint32_t rho = 64u * c + l;
+                if (rho >= n_rows) continue;
+                const unsigned long long seg = starts[c];
+                const uint32_t k = block_base[c] + (uint32_t)__popcll(seg & ((2ull << l) - 1ull)) - 1u;
+                const uint4 in = info[k];
+                const uint32_t rr = rho - in.z;
+                const int ya = (int)(in.x & 15u), za = (int)((in.x >> 4) & 15u), wy = (int)((in.x >> 8) & 15u);
+                const int lx = (int)((in.x >> 12) & 63u) - 16, ly = (int)((in.x >> 18) & 63u) - 16,
+                          lz = (int)((in.x >> 24) & 63u) - 16;
+                const bool rv = (in.x >> 30) & 1u;
+                const int rz = (int)((rr * (in.y & 0x1FFFFu)) >> 16);
+                const int yy = ya + ((int)rr - rz * wy), zz = za + rz;
+                const int dy = yy - ly, dz = zz - lz;
+                const uint32_t rowq = kTilePq * (uint32_t)yy + kTileLayer * (uint32_t)zz;
+                const uint32_t crow = kCntPitch * (uint32_t)yy + kCntLayer * (uint32_t)zz;
+                if (!rv) {
+                    // the window row: cells lx - R .. lx + R in the quads from x0 = (lx - R) rounded down
+                    const int xs = lx - R;
+                    const int q0 = xs >> 2;
+                    const uint32_t tr = (uint32_t)(dy + R) + (uint32_t)K * (uint32_t)(dz + R);
+                    const uint4 m01 = *reinterpret_cast<const uint4 *>(&mt[xs & 3][tr][0]);
+                    const uint4 m23 = *reinterpret_cast<const uint4 *>(&mt[xs & 3][tr][2]);
+                    const unsigned long long mq[4] = {(unsigned long long)m01.x | ((unsigned long long)m01.y << 32),
+                                                      (unsigned long long)m01.z | ((unsigned long long)m01.w << 32),
+                                                      (unsigned long long)m23.x | ((unsigned long long)m23.y << 32),
+                                                      (unsigned long long)m23.z | ((unsigned long long)m23.w << 32)};
+#pragma unroll
+                    for (int qd = 0; qd < 4; ++qd) {
+                        const int qx = q0 + qd;
+                        if (qx >= 0 && qx < (int)kTileQx && 4 * qx <= lx + R)
+                            atomicAnd(reinterpret_cast<unsigned long long *>(&stamp[rowq + (uint32_t)qx]), mq[qd]);
+                    }
+                }
+                if (rs >= 0 && dy >= -rs && dy <= rs && dz >= -rs && dz <= rs) {
+                    // the shadow row: cells lx - 3 .. lx + 3, in 8-cell count
+                    // pairs (two words, one 64-bit add; a byte cannot carry:
+                    // at most 255 hits a round) from (lx - 3) rounded down to 8
+                    const uint32_t bin = in.y >> 17;
+                    const uint32_t m7 = smask[bin * kShadowRows + (uint32_t)(dy + 3) + 7u * (uint32_t)(dz + 3)];
+                    const int xs = lx - 3;
+                    const uint32_t bits = m7 << (xs & 7);
+                    const int p0 = xs >> 3;
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) {
+                        const uint32_t oct = (bits >> (8 * i)) & 0xFFu;
+                        const int pq = p0 + i;   // 8-cell pair of words
+                        if (oct && pq >= 0 && pq < (int)(kTileQx / 2)) {
+                            const unsigned long long v = (unsigned long long)spread4(oct & 0xFu) |
+                                                         ((unsigned long long)spread4(oct >> 4) << 32);
+                            atomicAdd(reinterpret_cast<unsigned long long *>(&cnt[crow + 2u * (uint32_t)pq]), v);
+                        }
+                    }
+                }
+            }
+            lds_barrier();
+            for (uint32_t c = threadIdx.x; c < n_blocks; c += kTileThreads) starts[c] = 0ull;   // for the next round
+            // the prefetched values taken into registers now, before the
+            // plane loads below are issued
+            ent_cur = pe;
+            asm volatile("" : "+v"(ent_cur.x), "+v"(ent_cur.y), "+v"(ent_cur.z), "+v"(ent_cur.w), "+v"(wk_nn.x),
+                              "+v"(wk_nn.y), "+v"(wk_nn.z), "+v"(wk_nn.w));
+            // the previous round's merge: its plane loads have had this
+            // round's set-up and rows to land. A thread merges the same quads
+            // of a tile in every round, so the next round of the same tile
+            // loads what this thread stored (program order).
+            if (pend) finish();
+            issue(X0, Y0, Z0, g);
+        }
+        wi += G;
+        wk = wk_next;
+        wk_next = wk_nn;
+    }
+    if (pend) finish();
 }
 
 // ========================================================== mesh export ===
@@ -1813,6 +2442,8 @@ static apply_fn find_apply(const Tuning &t, int R) {
 }
 
 bool tuning_supported(const Tuning &t, int K) {
+    if (t.strategy == DBTSDF_STRATEGY_TILE)   // (the kernel set must have the row kernel's tables too)
+        return t.threads == (uint32_t)kTileThreads && t.bx == kTileX && t.by == kTileY && t.bz == kTileZ && K <= 11;
     if (per_point_front(t)) return t.threads >= 64 && t.threads <= 1024 && (t.threads % 64) == 0;
     if (t.strategy != DBTSDF_STRATEGY_BRICK) return false;
     return find_apply(t, (K - 1) / 2) != nullptr;
@@ -1858,6 +2489,13 @@ static int apply_blocks_query(const Tuning &t, int K, bool row_kernel, int devic
             per_cu = 1;
         return cus * per_cu;
     }
+    if (t.strategy == DBTSDF_STRATEGY_TILE) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(k_apply_tile),
+                                                         kTileThreads, 0) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        return cus * per_cu;
+    }
     apply_fn f = find_apply(t, (K - 1) / 2);
     if (!f || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(f),
                                                            (int)t.threads, 0) != hipSuccess || per_cu < 1)
@@ -1873,6 +2511,27 @@ hipError_t launch_pipeline(const PipeArgs &a, const Tuning &t, uint32_t points_c
     while ((uint64_t)stat_chunk * 512 < points_cap) stat_chunk *= 2;
     const bool all = part == kPartAll;
     const bool pre = all || part == kPartPre, apply = all || part == kPartApply, post = all || part == kPartPost;
+    if (t.strategy == DBTSDF_STRATEGY_TILE) {
+        // front (lists counted), offsets (lists laid out), select and fill,
+        // apply; the select pass writes the statistics out
+        if (pre) {
+            if (a.single_scan) {
+                k_front<true, true><<<pb, kPtThreads, 0, st>>>(a, info);
+            } else {
+                k_upload<<<kCopyBlocks, 256, 0, st>>>(a);
+                k_reset<<<8, 256, 0, st>>>(a, info);
+                k_front<false, true><<<pb, kPtThreads, 0, st>>>(a, info);
+            }
+            k_offsets<<<blocks_for(points_cap, kPtThreads, 256), kPtThreads, 0, st>>>(a);
+            k_select_fill<<<sb, kSelThreads, 0, st>>>(a, info);
+        }
+        if (apply) {
+            if (!a.tab.row_image) return hipErrorInvalidValue;
+            k_apply_tile<<<t.apply_blocks, kTileThreads, 0, st>>>(a);
+        }
+        (void)post;
+        return hipGetLastError();
+    }
     if (per_point_front(t)) {
         // three passes: front (one-scan calls copy their descriptors in and
         // clear the counters there), select (writes the statistics out), apply
@@ -1880,11 +2539,11 @@ hipError_t launch_pipeline(const PipeArgs &a, const Tuning &t, uint32_t points_c
         if (apply && t.strategy == DBTSDF_STRATEGY_SORT) return hipErrorInvalidValue;
         if (pre) {
             if (a.single_scan) {
-                k_front<true><<<pb, kPtThreads, 0, st>>>(a, info);
+                k_front<true, false><<<pb, kPtThreads, 0, st>>>(a, info);
             } else {
                 k_upload<<<kCopyBlocks, 256, 0, st>>>(a);
                 k_reset<<<8, 256, 0, st>>>(a, info);
-                k_front<false><<<pb, kPtThreads, 0, st>>>(a, info);
+                k_front<false, false><<<pb, kPtThreads, 0, st>>>(a, info);
             }
             k_select_atomic<<<sb, kSelThreads, 0, st>>>(a, info);
         }
@@ -1909,7 +2568,7 @@ hipError_t launch_pipeline(const PipeArgs &a, const Tuning &t, uint32_t points_c
     if (pre) {
         k_upload<<<kCopyBlocks, 256, 0, st>>>(a);
         k_reset<<<8, 256, 0, st>>>(a, info);
-        k_front<false><<<pb, kPtThreads, 0, st>>>(a, info);
+        k_front<false, false><<<pb, kPtThreads, 0, st>>>(a, info);
         k_select_pairs<<<sb, kSelThreads, 0, st>>>(a, info);
         k_stats<<<blocks_for(points_cap, stat_chunk, 512), kPtThreads, 0, st>>>(a, info, stat_chunk);
         k_offsets<<<blocks_for(points_cap, kPtThreads, 256), kPtThreads, 0, st>>>(a);

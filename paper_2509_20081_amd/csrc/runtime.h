@@ -199,6 +199,7 @@ bool sweep_constants(const float p0[16], const float p1[16], int mode, float out
 DevGrid dev_grid_of(const dbtsdf_grid *g, uint32_t index);
 DevScan dev_scan_of(const ScanIn &s, uint32_t begin, uint32_t grid_index);
 bool row_kernel_covers(const dbtsdf_grid *g);
+bool row_kernel_tables(const dbtsdf_grid *g);
 
 // Validates and enqueues one call (plain or batched) on stream st using ws.
 dbtsdf_status enqueue_scans(Workspace &ws, hipStream_t st, std::vector<ScanIn> &scans, bool use_graph, bool plain);

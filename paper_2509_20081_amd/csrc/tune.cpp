@@ -38,6 +38,13 @@ std::vector<Tuning> candidates(int K) {
     a.strategy = DBTSDF_STRATEGY_ATOMIC;
     a.threads = 256;
     out.push_back(a);
+    Tuning tl;
+    tl.strategy = DBTSDF_STRATEGY_TILE;
+    tl.bx = kTileX;
+    tl.by = kTileY;
+    tl.bz = kTileZ;
+    tl.threads = 256;
+    if (tuning_supported(tl, K)) out.push_back(tl);
     Tuning srt;
     srt.strategy = DBTSDF_STRATEGY_SORT;
     srt.threads = 256;

@@ -70,6 +70,7 @@ TUNINGS = [
     dict(strategy="atomic", block_threads=256),
     dict(strategy="sort"),
     dict(strategy="sort", chunk=7),                                              # rounds of 7 returns
+    dict(strategy="tile"),
 ]
 
 
@@ -85,7 +86,12 @@ def test_tiny_grids_match_oracle(db, case, tuning):
     try:
         g.set_tuning(**tuning)
     except db.DbtsdfError:
-        # documented: the largest brick shapes cannot hold the tiles for K = 37
+        # documented: the largest brick shapes cannot hold the tiles for K = 37,
+        # and the tile strategy takes K <= 17
+        if tuning["strategy"] == "tile":
+            n_bins = 26 if case["binning"] == "cube26" else case.get("bins_az", 40) * case.get("bins_el", 40)
+            assert K > 11 or n_bins > 31 or case.get("shadow_r2", 9) > 9
+            pytest.skip("the tile strategy takes K <= 11, at most 31 bins, r_s^2 <= 9")
         assert K == 37 and tuning["brick"] == (32, 16, 16)
         pytest.skip("brick shape too small in LDS for this kernel radius")
     m, p = o.new_grid()
@@ -215,7 +221,7 @@ def test_paper_kernel_set_config1(db, tuning):
     assert ref["n_integrated"] > 3000
 
 
-@pytest.mark.parametrize("strategy", ["atomic", "brick", "sort"])
+@pytest.mark.parametrize("strategy", ["atomic", "brick", "sort", "tile"])
 def test_plain_calls_over_the_ring(db, strategy):
     """20 plain calls into one grid (more than the 16 ring slots, so every slot's descriptors, and with the
     brick strategy its captured graph, are used again), eager work between calls: statistics and grid
@@ -240,7 +246,7 @@ def test_plain_calls_over_the_ring(db, strategy):
 
 @pytest.mark.parametrize("hit", [(2, 3), (1, 1), (5, 65535)])
 @pytest.mark.parametrize("dedup", [True, False])
-@pytest.mark.parametrize("strategy", ["atomic", "sort"])
+@pytest.mark.parametrize("strategy", ["atomic", "sort", "tile"])
 def test_dense_neighbouring_returns_saturate_exactly(db, hit, dedup, strategy):
     """Returns one voxel apart in input order (neighbours share most of their shadows, so the per-point
     kernel adds shared shadow cells once with their count) on a small hit cap: counters, signs and masks
@@ -271,7 +277,7 @@ def test_dense_neighbouring_returns_saturate_exactly(db, hit, dedup, strategy):
     assert ref["n_integrated"] > 200
 
 
-@pytest.mark.parametrize("strategy", ["atomic", "brick", "sort"])
+@pytest.mark.parametrize("strategy", ["atomic", "brick", "sort", "tile"])
 def test_profiling_period_mixes_call_forms(db, strategy):
     """Profiling every 3rd call: timed calls (split launch) and untimed calls (one graph) interleave
     over the ring; the totals count the timed calls only and every call matches the oracle."""
@@ -465,7 +471,7 @@ def test_autotune_keeps_result_identical(db):
     (o, g, _), gdef = _config_grid_pair(db, 1)
     scans = [(pose, P.to_device(pts)) for pose, pts in synth.config_scans(1, 0, [0])]
     tun = g.autotune(scans, True)
-    assert tun["strategy"] in ("brick", "atomic", "sort")
+    assert tun["strategy"] in ("brick", "atomic", "sort", "tile")
     m, p = o.new_grid()
     for pose, pts in synth.config_scans(1, 0, [0]):
         o.integrate(m, p, pose, pts)
@@ -548,7 +554,7 @@ def test_readout_and_restore(db):
 
 
 @pytest.mark.parametrize("kernel", ["row", "generic"])
-@pytest.mark.parametrize("strategy", ["atomic", "sort"])
+@pytest.mark.parametrize("strategy", ["atomic", "sort", "tile"])
 def test_written_planes_integrate_every_window(db, strategy, kernel):
     """Planes written with zero masks at voxels whose windows were never stamped (not a state integration
     makes): returns landing there still get their whole eq. 4 window, as in the oracle; after a reset the
@@ -557,6 +563,8 @@ def test_written_planes_integrate_every_window(db, strategy, kernel):
     kw = dict(synth.KERNEL_DEFAULTS)
     if kernel == "generic":
         kw.update(kernel_size=13)   # past the row kernel's tables: the generic per-point kernel
+    if strategy == "tile" and kernel == "generic":
+        pytest.skip("the tile strategy takes K <= 11")
     o, g, _ = P.make_pair(dims, 1.0, (0.0, 0.0, 0.0), **kw)
     g.set_tuning(strategy=strategy)
     rng = np.random.default_rng(17)
@@ -667,7 +675,7 @@ def _sweep_times(rng, n):
 
 
 @pytest.mark.parametrize("mode", ["se3", "yaw"])
-@pytest.mark.parametrize("strategy", ["atomic", "brick", "sort"])
+@pytest.mark.parametrize("strategy", ["atomic", "brick", "sort", "tile"])
 def test_deskewed_sweeps_match_oracle(db, mode, strategy):
     """Motion-compensated sweeps (start and end poses, a time fraction per return) on a small grid: device
     and host points, DS = 1 and 2, invalid time fractions; statistics and whole grid equal the oracle's
