@@ -1684,31 +1684,33 @@ __global__ __launch_bounds__(kSelThreads) void k_select_fill(PipeArgs a, const C
 }
 
 // One workgroup per tile work item (persistent: items dealt round-robin over
-// the workgroups of one XCD, each XCD taking a contiguous eighth of the list).
-// LDS holds, per word of the tile, the eq. 3 stamp as a 16-bit mask
-// (2^n - 1; 0xFFFF where no window reaches, the identity of the AND) and the
-// shadow hit count as a byte; rows of 32 words are padded to 36 so that
-// neighbouring rows fall in different banks. The tile's list is taken in
-// rounds of at most 255 entries (a count byte cannot overflow: an entry adds
-// at most one hit to a word):
-//   1. stamps and counts cleared, the round's entries staged in LDS;
-//   2. one thread per entry: the rows it walks, clipped to the tile (the
-//      window's (y, z) rows for a return that applies its window, the shadow
-//      ball's for one whose voxel an earlier call integrated), and the row
-//      counts' prefix over the round, with a bitmap of the rows where an
-//      entry starts;
-//   3. the rows of all entries are dealt to the lanes, 64 consecutive rows a
+// the workgroups). LDS holds, per word of the tile, the eq. 3 stamp as a
+// 16-bit mask (2^n - 1; 0xFFFF where no window reaches, the identity of the
+// AND), four words to a 64-bit quad, rows of 8 quads padded to 9 and z layers
+// to 145 quads so that lanes on neighbouring rows fall in different banks;
+// and the shadow hit count as a byte, four to a 32-bit word (rows of 8 count
+// words padded to 10, layers to 162). The tile's list is taken in rounds of
+// at most 255 entries (a count byte cannot overflow: an entry adds at most one
+// hit to a word):
+//   1. stamps and counts cleared; one thread per entry: the rows it walks,
+//      clipped to the tile (the window's (y, z) rows for a return that
+//      applies its window, the shadow ball's for one whose voxel an earlier
+//      call integrated), and one scan of the row counts over the round, with
+//      a bitmap of the rows where an entry starts;
+//   2. the rows of all entries are dealt to the lanes, 64 consecutive rows a
 //      wavefront: a lane finds its entry by counting the starts below its row
 //      in the bitmap, ANDs its window row's masks in with one ds_and_b64 per
-//      4-word quad (the masks of the row kernel's table for the window's
-//      alignment phase), and, where the row lies in the shadow ball, adds the
-//      row's hits (bits of the bin's shadow row) with one ds_add_u32 of four
-//      count bytes per word quad;
-//   4. the round is merged, four 16-byte quads per thread, every load issued
-//      before any store: mask &= the stamp (stored when changed); h = min(h +
-//      c, H_max) with the sign cleared on the crossing h < T <= h + c (eqs.
-//      5-6 for c unit steps). A tile of several rounds merges each in turn
-//      (AND is idempotent and c then d steps are c + d steps).
+//      quad (the masks of the row kernel's table for the window's alignment
+//      phase), and, where the row lies in the shadow ball, adds the row's
+//      hits (bits of the bin's shadow row) with one 64-bit add per 8-word
+//      pair of count words;
+//   3. the round is merged, four 16-byte quads per thread: right after the
+//      rows, the stamps and counts go to registers and the loads of the words
+//      they touch are issued; the stores follow after the next round's rows
+//      (or the next item's): mask &= the stamp (stored when changed); h =
+//      min(h + c, H_max) with the sign cleared on the crossing h < T <= h + c
+//      (eqs. 5-6 for c unit steps). A tile of several rounds merges each in
+//      turn (AND is idempotent and c then d steps are c + d steps).
 // Needs the row kernel's tables (K <= 11, at most 31 bins, r_s^2 <= 9).
 constexpr int kTileThreads = 256;
 constexpr uint32_t kTileRound = 255;                    // entries per round
@@ -1735,7 +1737,9 @@ __device__ __forceinline__ uint32_t spread4(uint32_t b4) {   // bit j -> byte j
 __global__ __launch_bounds__(kTileThreads, 3) void k_apply_tile(PipeArgs a) {
     __shared__ __align__(16) uint2 stamp[kTileSlots];      // 4 x 16-bit masks per quad
     __shared__ __align__(16) uint32_t cnt[kCntSlots];      // 4 x 8-bit hit counts per word of counts
-    __shared__ __align__(16) uint2 mt[4][kMtRows][4];               // masks by (phase, window row, quad)
+    // masks by (phase, window row, quad); rows padded to 5 quads (40 bytes:
+    // lanes on consecutive window rows fall in different banks)
+    __shared__ __align__(16) unsigned long long mt[4][kMtRows][5];
     __shared__ uint8_t smask[kRowBins * kShadowRows];               // shadow x bits (dx + 3) per (bin, dy, dz)
     // per entry with rows, in round order: box and point (tile-local), row
     // magic and bin, first row
@@ -1754,7 +1758,8 @@ __global__ __launch_bounds__(kTileThreads, 3) void k_apply_tile(PipeArgs a) {
         const uint2 *mtab = reinterpret_cast<const uint2 *>(t.row_image) + kImgMtab / 2;
         for (uint32_t i = threadIdx.x; i < 4u * kMtRows * 4u; i += kTileThreads) {
             const uint32_t ph = i / (kMtRows * 4u), row = (i / 4u) % kMtRows, qd = i % 4u;
-            mt[ph][row][qd] = (int)row < K * K ? mtab[(4u * qd + 3u - ph) * kRowPad + row] : make_uint2(~0u, ~0u);
+            const uint2 m = (int)row < K * K ? mtab[(4u * qd + 3u - ph) * kRowPad + row] : make_uint2(~0u, ~0u);
+            mt[ph][row][qd] = (unsigned long long)m.x | ((unsigned long long)m.y << 32);
         }
         // each bin's shadow set as 7-bit x rows, from its 343-bit set (bits
         // (dx + 3) + 7 (dy + 3) + 49 (dz + 3))
@@ -1810,41 +1815,48 @@ __global__ __launch_bounds__(kTileThreads, 3) void k_apply_tile(PipeArgs a) {
     uint32_t cq[kTileQuadsPerThread];
     u32x4 om[kTileQuadsPerThread], op[kTileQuadsPerThread];
     bool pend = false;
-    int pX0 = 0, pY0 = 0, pZ0 = 0;
+    // A thread's quads: x 4 (tid mod 8), y (tid / 8) mod 16 and z tid / 128
+    // + kQz k for its k-th; the same in every tile.
+    constexpr uint32_t kQz = kTileThreads / (kTileQx * kTileY);
+    static_assert(kTileThreads % (kTileQx * kTileY) == 0 && kQz * kTileQuadsPerThread == kTileZ, "quads per thread");
+    const uint32_t q_x = 4u * (threadIdx.x % kTileQx), q_y = (threadIdx.x / kTileQx) % kTileY,
+                   q_z = threadIdx.x / (kTileQx * kTileY);
+    const uint32_t s_off = q_x / 4u + kTilePq * q_y + kTileLayer * q_z;   // stamp slot of quad 0 (+ kTileLayer kQz k)
+    const uint32_t c_off = q_x / 4u + kCntPitch * q_y + kCntLayer * q_z;  // count slot of quad 0 (+ kCntLayer kQz k)
+    // the pending merge: grid, first word, word step between quads, the
+    // quad's cells and which quads lie inside the grid with 16-byte aligned rows
     DevGrid pg = g;
-    auto quad_of = [&](uint32_t k, uint32_t &gx, uint32_t &gy, uint32_t &gz) {
-        const uint32_t qi = threadIdx.x + k * kTileThreads;
-        const uint32_t row = qi / kTileQx;
-        gx = (uint32_t)pX0 + 4u * (qi % kTileQx);
-        gy = (uint32_t)pY0 + row % kTileY;
-        gz = (uint32_t)pZ0 + row / kTileY;
-    };
-    auto fast_quad = [&](uint32_t gx, uint32_t gy, uint32_t gz) {
-        return (pg.nx & 3u) == 0u && gx + 3u < pg.nx && gy < pg.ny && gz < pg.nz;
-    };
+    size_t plin = 0, pstep = 0;
+    uint32_t pgx = 0, pgy = 0, pgz = 0;
+    bool pxy = false;
     auto issue = [&](int X0, int Y0, int Z0, const DevGrid &gi) {
-        pX0 = X0;
-        pY0 = Y0;
-        pZ0 = Z0;
         pg = gi;
+        pgx = (uint32_t)X0 + q_x;
+        pgy = (uint32_t)Y0 + q_y;
+        pgz = (uint32_t)Z0 + q_z;
+        plin = (size_t)pgx + (size_t)gi.nx * ((size_t)pgy + (size_t)gi.ny * (size_t)pgz);
+        pstep = (size_t)kQz * (size_t)gi.nx * (size_t)gi.ny;
+        pxy = (gi.nx & 3u) == 0u && pgx + 3u < gi.nx && pgy < gi.ny;
 #pragma unroll
         for (uint32_t k = 0; k < kTileQuadsPerThread; ++k) {
-            const uint32_t qi = threadIdx.x + k * kTileThreads;
-            const uint32_t row = qi / kTileQx, qxm = qi % kTileQx;
-            sq[k] = stamp[qxm + kTilePq * (row % kTileY) + kTileLayer * (row / kTileY)];
-            cq[k] = cnt[qxm + kCntPitch * (row % kTileY) + kCntLayer * (row / kTileY)];
-            uint32_t gx, gy, gz;
-            quad_of(k, gx, gy, gz);
-            const size_t lin = (size_t)gx + (size_t)pg.nx * ((size_t)gy + (size_t)pg.ny * (size_t)gz);
-            if (fast_quad(gx, gy, gz)) {
-                if ((sq[k].x & sq[k].y) != ~0u) om[k] = *reinterpret_cast<const gu32x4 *>(glob(pg.mask) + lin);
-                if (cq[k] != 0u) op[k] = *reinterpret_cast<const gu32x4 *>(glob(pg.packed) + lin);
+            sq[k] = stamp[s_off + kTileLayer * kQz * k];
+            cq[k] = cnt[c_off + kCntLayer * kQz * k];
+            if (pxy && pgz + kQz * k < gi.nz) {
+                const size_t lin = plin + (size_t)k * pstep;
+                if ((sq[k].x & sq[k].y) != ~0u) om[k] = *reinterpret_cast<const gu32x4 *>(glob(gi.mask) + lin);
+                if (cq[k] != 0u) op[k] = *reinterpret_cast<const gu32x4 *>(glob(gi.packed) + lin);
             }
         }
         pend = true;
     };
     auto finish = [&]() {
         pend = false;
+        // All the loaded words taken into registers first: one wait for the
+        // loads, issued a round ago. (Vector stores count against the same
+        // counter, so a wait between this thread's stores would also wait
+        // for the stores before it.)
+#pragma unroll
+        for (uint32_t k = 0; k < kTileQuadsPerThread; ++k) asm volatile("" : "+v"(om[k]), "+v"(op[k]));
 #pragma unroll
         for (uint32_t k = 0; k < kTileQuadsPerThread; ++k) {
             const bool nm = (sq[k].x & sq[k].y) != ~0u, nh = cq[k] != 0u;
@@ -1852,10 +1864,9 @@ __global__ __launch_bounds__(kTileThreads, 3) void k_apply_tile(PipeArgs a) {
             uint32_t mm[4] = {sq[k].x & 0xFFFFu, sq[k].x >> 16, sq[k].y & 0xFFFFu, sq[k].y >> 16};
 #pragma unroll
             for (int j = 0; j < 4; ++j) mm[j] = mm[j] == 0xFFFFu ? ~0u : mm[j];
-            uint32_t gx, gy, gz;
-            quad_of(k, gx, gy, gz);
-            const size_t lin = (size_t)gx + (size_t)pg.nx * ((size_t)gy + (size_t)pg.ny * (size_t)gz);
-            if (fast_quad(gx, gy, gz)) {
+            const uint32_t gz = pgz + kQz * k;
+            const size_t lin = plin + (size_t)k * pstep;
+            if (pxy && gz < pg.nz) {
                 if (nm) {
                     const uint32_t o[4] = {om[k][0], om[k][1], om[k][2], om[k][3]};
                     uint32_t nw[4];
@@ -1882,10 +1893,10 @@ __global__ __launch_bounds__(kTileThreads, 3) void k_apply_tile(PipeArgs a) {
                 }
                 continue;
             }
-            // a quad at the grid's x edge, or rows not 16-byte aligned: word by word
+            // a quad at the grid's edge, or rows not 16-byte aligned: word by word
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                if (gx + (uint32_t)j >= pg.nx || gy >= pg.ny || gz >= pg.nz) continue;
+                if (pgx + (uint32_t)j >= pg.nx || pgy >= pg.ny || gz >= pg.nz) continue;
                 const size_t li = lin + (size_t)j;
                 if (mm[j] != ~0u) {
                     gu32 *pm = glob(pg.mask) + li;
@@ -1972,13 +1983,32 @@ __global__ __launch_bounds__(kTileThreads, 3) void k_apply_tile(PipeArgs a) {
             }
             if (threadIdx.x == 0) block_base[0] = 0;
             lds_barrier();
-            // the rows, 64 to a wavefront
-            for (uint32_t c = w; c < n_blocks; c += kWaves) {
+            // The rows, 64 to a wavefront. A lane's entry is the last one
+            // starting at or before its row: block c's entries before it plus
+            // the start bits up to the lane (block 0 starts with entry 0; a
+            // later block has a nonzero base). The look-ups run ahead of the
+            // rows: the start bits and base two blocks ahead, the entry one.
+            auto entry_of = [&](unsigned long long seg, uint32_t bb) {
+                return bb + (uint32_t)__popcll(seg & ((2ull << l) - 1ull)) - 1u;
+            };
+            uint32_t c = w;
+            uint4 in_next = make_uint4(0u, 0u, 0u, 0u);
+            unsigned long long seg2 = 0ull;
+            uint32_t bb2 = 0u;
+            if (c < n_blocks) in_next = info[entry_of(starts[c], block_base[c])];
+            if (c + kWaves < n_blocks) {
+                seg2 = starts[c + kWaves];
+                bb2 = block_base[c + kWaves];
+            }
+            for (; c < n_blocks; c += kWaves) {
+                const uint4 in = in_next;
+                if (c + kWaves < n_blocks) in_next = info[entry_of(seg2, bb2)];
+                if (c + 2u * kWaves < n_blocks) {
+                    seg2 = starts[c + 2u * kWaves];
+                    bb2 = block_base[c + 2u * kWaves];
+                }
                 const uint32_t rho = 64u * c + l;
                 if (rho >= n_rows) continue;
-                const unsigned long long seg = starts[c];
-                const uint32_t k = block_base[c] + (uint32_t)__popcll(seg & ((2ull << l) - 1ull)) - 1u;
-                const uint4 in = info[k];
                 const uint32_t rr = rho - in.z;
                 const int ya = (int)(in.x & 15u), za = (int)((in.x >> 4) & 15u), wy = (int)((in.x >> 8) & 15u);
                 const int lx = (int)((in.x >> 12) & 63u) - 16, ly = (int)((in.x >> 18) & 63u) - 16,
@@ -1994,12 +2024,8 @@ __global__ __launch_bounds__(kTileThreads, 3) void k_apply_tile(PipeArgs a) {
                     const int xs = lx - R;
                     const int q0 = xs >> 2;
                     const uint32_t tr = (uint32_t)(dy + R) + (uint32_t)K * (uint32_t)(dz + R);
-                    const uint4 m01 = *reinterpret_cast<const uint4 *>(&mt[xs & 3][tr][0]);
-                    const uint4 m23 = *reinterpret_cast<const uint4 *>(&mt[xs & 3][tr][2]);
-                    const unsigned long long mq[4] = {(unsigned long long)m01.x | ((unsigned long long)m01.y << 32),
-                                                      (unsigned long long)m01.z | ((unsigned long long)m01.w << 32),
-                                                      (unsigned long long)m23.x | ((unsigned long long)m23.y << 32),
-                                                      (unsigned long long)m23.z | ((unsigned long long)m23.w << 32)};
+                    const unsigned long long *mrow = mt[xs & 3][tr];
+                    const unsigned long long mq[4] = {mrow[0], mrow[1], mrow[2], mrow[3]};
 #pragma unroll
                     for (int qd = 0; qd < 4; ++qd) {
                         const int qx = q0 + qd;
