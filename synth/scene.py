@@ -311,3 +311,31 @@ def random_pose(rng: np.random.Generator, t_lo, t_hi, max_angle: float = math.pi
     ang = rng.uniform(-max_angle, max_angle, size=3)
     t = rng.uniform(t_lo, t_hi)
     return pose_from_xyz_rpy(t[0], t[1], t[2], ang[0], ang[1] * 0.5, ang[2]).astype(np.float32)
+
+
+def config_ground_truth(cfg: int, map_id: int = 0, scan_ids=None, n_scans: int | None = None,
+                        cell: float = 0.02) -> np.ndarray:
+    """Reference surface points for the accuracy metrics: the exact (noise-free)
+    first hits of the same rays as ``config_scans`` on the analytic scene, in
+    the map frame (fp64 ray casting, then fp32), within the sensor's range,
+    thinned to the first point (in scan, then ray order) of each cube of side
+    ``cell`` so that the density does not follow the sensor's range falloff."""
+    poses = config_poses(cfg, map_id, n_scans)
+    room_w, room_h, _ = _room_and_sensor(cfg, map_id, 0)
+    scene = make_scene(_rng(cfg, map_id, _S_SCENE), room_w=room_w, room_h=room_h,
+                       path_xy=poses[:, :2, 3])
+    if scan_ids is None:
+        scan_ids = range(len(poses))
+    chunks = []
+    for k in scan_ids:
+        _, _, sensor = _room_and_sensor(cfg, map_id, k)
+        pose = poses[k]
+        dirs_w = sensor_directions(sensor) @ pose[:3, :3].T
+        t = cast_rays(scene, pose[:3, 3], dirs_w)
+        keep = np.isfinite(t) & (t <= sensor.max_range)
+        chunks.append(pose[:3, 3][None, :] + dirs_w[keep] * t[keep, None])
+    pts = np.concatenate(chunks) if chunks else np.zeros((0, 3))
+    k = np.floor(pts / cell).astype(np.int64) + (1 << 20)   # cells within +-2^20 of the origin
+    key = k[:, 0] | (k[:, 1] << 21) | (k[:, 2] << 42)
+    _, first = np.unique(key, return_index=True)
+    return np.ascontiguousarray(pts[np.sort(first)].astype(np.float32))
