@@ -434,6 +434,53 @@ dbtsdf_status dbtsdf_extract_points(dbtsdf_grid *g, const uint32_t lo[3], const 
                                     uint64_t max_points, uint64_t *n_points);
 
 /*
+ * Reconstruction-accuracy metrics (Sec. IV-A): nearest-neighbour distances
+ * between a predicted point set (points on the zero level of the map, e.g.
+ * the vertices of the exported mesh) and a ground-truth set.
+ * Squared distances are ((qx - rx)^2 + (qy - ry)^2) + (qz - rz)^2 in IEEE
+ * fp64 from the fp32 coordinates, one operation at a time in that order; a
+ * nearest squared distance is the minimum of that over the whole set (exact:
+ * it does not depend on the search order). "Within the tolerance t" is
+ * d^2 < t * t (strict).
+ *   accuracy      mean over predicted points of the distance to the nearest
+ *                 ground-truth point (metres)
+ *   completeness  mean over ground-truth points of the distance to the
+ *                 nearest predicted point (metres)
+ *   chamfer_l1    (accuracy + completeness) / 2
+ *   precision     share of predicted points within t of the ground truth
+ *   recall        share of ground-truth points within t of the prediction
+ *   fscore        2 precision recall / (precision + recall), 0 when both are 0
+ */
+typedef struct dbtsdf_metrics {
+    double accuracy, completeness, chamfer_l1;
+    double precision, recall, fscore;
+    uint64_t n_pred, n_gt, n_pred_within, n_gt_within;
+} dbtsdf_metrics;
+
+/*
+ * Nearest squared distance of every query point to the reference set.
+ * query_dev: n_query x 3 fp32 (x, y, z per point), ref_dev: n_ref x 3 fp32,
+ * d2_dev: n_query fp64 written; all device memory of GPU `device`, owned by
+ * the caller. Runs on that device's null stream and synchronises it;
+ * allocates scratch (a cell grid of the reference points) for the call.
+ * Errors: INVALID_ARG (NULL pointer with a nonzero count, n_ref 0 with
+ * queries, a non-finite coordinate), OUT_OF_RANGE (n_ref >= 2^32 - 16),
+ * OUT_OF_MEMORY, DEVICE.
+ */
+dbtsdf_status dbtsdf_nearest_sq(int device, const float *query_dev, uint64_t n_query, const float *ref_dev,
+                                uint64_t n_ref, double *d2_dev);
+
+/*
+ * The metrics above of pred_dev (n_pred x 3 fp32) against gt_dev (n_gt x 3
+ * fp32), device memory of GPU `device`, at tolerance t (metres, finite,
+ * >= 0), into *out (host). Sums are taken in a fixed order (repeatable bit
+ * for bit). Errors as dbtsdf_nearest_sq; either set empty, NULL out or a bad
+ * tolerance is INVALID_ARG.
+ */
+dbtsdf_status dbtsdf_surface_metrics(int device, const float *pred_dev, uint64_t n_pred, const float *gt_dev,
+                                     uint64_t n_gt, double tolerance, dbtsdf_metrics *out);
+
+/*
  * Overwrite the whole grid from host planes (Nx*Ny*Nz uint32 each, x fastest),
  * e.g. a checkpoint written from dbtsdf_read_voxels. Rejects (INVALID_ARG)
  * planes that break the representation: a mask not of the form 2^n - 1, bits

@@ -23,7 +23,8 @@ import numpy as np
 from . import _lib as L
 from ._lib import DbtsdfError  # noqa: F401
 
-__all__ = ["KernelSet", "Grid", "Batch", "Server", "DbtsdfError", "now_ns", "library_path"]
+__all__ = ["KernelSet", "Grid", "Batch", "Server", "DbtsdfError", "now_ns", "library_path", "nearest_sq",
+           "surface_metrics", "mesh_vertices"]
 
 _BINNING = {"azel": L.BIN_AZEL, "cube26": L.BIN_CUBE26}
 _METRIC = {"l2": L.DIST_L2, "l1": L.DIST_L1}
@@ -107,6 +108,49 @@ def deskew_constants(pose_start, pose_end, mode="se3"):
     L.check(L.lib().dbtsdf_deskew_constants(p0.ctypes.data_as(C.c_void_p), p1.ctypes.data_as(C.c_void_p),
                                             DESKEW[mode], out.ctypes.data_as(C.c_void_p)), "deskew_constants")
     return out
+
+
+def _cloud_arg(pts, name):
+    import torch
+    if not isinstance(pts, torch.Tensor) or not pts.is_cuda or pts.dtype != torch.float32 or pts.dim() != 2 \
+            or pts.shape[1] != 3 or not pts.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous (n, 3) float32 CUDA tensor")
+    return C.c_void_p(pts.data_ptr() if pts.shape[0] else 0), int(pts.shape[0])
+
+
+def nearest_sq(query, ref):
+    """Per query point, the smallest squared distance (fp64, exact) to the reference points: a float64
+    CUDA tensor of shape (n_query,)."""
+    import torch
+    q, nq = _cloud_arg(query, "query")
+    r, nr = _cloud_arg(ref, "ref")
+    out = torch.empty(nq, dtype=torch.float64, device=query.device)
+    torch.cuda.synchronize(query.device)   # the library runs on the device's null stream
+    L.check(L.lib().dbtsdf_nearest_sq(query.device.index or 0, q, nq, r, nr,
+                                      C.c_void_p(out.data_ptr() if nq else 0)), "nearest_sq")
+    return out
+
+
+def surface_metrics(pred, gt, tolerance: float) -> dict:
+    """Accuracy, completeness, Chamfer-L1 (metres), precision, recall and F-score at `tolerance` of the
+    predicted points `pred` against the ground truth `gt` (both (n, 3) float32 CUDA tensors)."""
+    import torch
+    p, n_p = _cloud_arg(pred, "pred")
+    g, n_g = _cloud_arg(gt, "gt")
+    m = L.Metrics()
+    torch.cuda.synchronize(pred.device)
+    L.check(L.lib().dbtsdf_surface_metrics(pred.device.index or 0, p, n_p, g, n_g, float(tolerance), C.byref(m)),
+            "surface_metrics")
+    return {"accuracy": m.accuracy, "completeness": m.completeness, "chamfer_l1": m.chamfer_l1,
+            "precision": m.precision, "recall": m.recall, "fscore": m.fscore, "n_pred": int(m.n_pred),
+            "n_gt": int(m.n_gt), "n_pred_within": int(m.n_pred_within), "n_gt_within": int(m.n_gt_within),
+            "tolerance": float(tolerance)}
+
+
+def mesh_vertices(tris):
+    """The predicted point set of the accuracy metrics: the three vertices of every triangle of a mesh
+    from Grid.extract_mesh (a (n, 9) float32 CUDA tensor), as an (3 n, 3) view."""
+    return tris.reshape(-1, 3)
 
 
 def integrate_batch(items) -> list:

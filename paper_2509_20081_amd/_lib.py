@@ -55,6 +55,13 @@ class Completion(C.Structure):
                 ("batch_scans", C.c_uint32), ("stats", ScanStats)]
 
 
+class Metrics(C.Structure):
+    _fields_ = [("accuracy", C.c_double), ("completeness", C.c_double), ("chamfer_l1", C.c_double),
+                ("precision", C.c_double), ("recall", C.c_double), ("fscore", C.c_double),
+                ("n_pred", C.c_uint64), ("n_gt", C.c_uint64), ("n_pred_within", C.c_uint64),
+                ("n_gt_within", C.c_uint64)]
+
+
 P = C.c_void_p
 U32, U64, I32 = C.c_uint32, C.c_uint64, C.c_int32
 PP = C.POINTER(C.c_void_p)
@@ -84,6 +91,8 @@ SIGNATURES = {
     "dbtsdf_integrate_scan_every": (C.c_int, [P, P, P, U64, U32, C.c_int, P]),
     "dbtsdf_extract_mesh": (C.c_int, [P, P, P, P, U64, C.POINTER(U64)]),
     "dbtsdf_extract_points": (C.c_int, [P, P, P, P, U64, C.POINTER(U64)]),
+    "dbtsdf_nearest_sq": (C.c_int, [C.c_int, P, U64, P, U64, P]),
+    "dbtsdf_surface_metrics": (C.c_int, [C.c_int, P, U64, P, U64, C.c_double, C.POINTER(Metrics)]),
     "dbtsdf_deskew_constants": (C.c_int, [P, P, C.c_int, P]),
     "dbtsdf_integrate_scan_deskew": (C.c_int, [P, P, P, P, P, U64, U32, C.c_int, C.c_int, P]),
     "dbtsdf_batch_integrate_deskew": (C.c_int, [P, U32, P, P, P, C.c_int, P, P, P, C.c_int, P]),

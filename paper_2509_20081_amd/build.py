@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdbtsdf.so")
-SOURCES = ["api.cpp", "kernel_set.cpp", "mesh.cpp", "server.cpp", "tune.cpp", "kernels.hip", "sort_reduce.hip", "deskew.cpp", "noalloc.cpp"]
+SOURCES = ["api.cpp", "kernel_set.cpp", "mesh.cpp", "server.cpp", "tune.cpp", "kernels.hip", "sort_reduce.hip", "deskew.cpp", "noalloc.cpp", "metrics.hip"]
 ARCH = os.environ.get("DBTSDF_OFFLOAD_ARCH", "gfx950")
 
 
