@@ -1,7 +1,9 @@
 """Compile the plain C oracle into ``oracle/liboracle.so`` (test infrastructure only).
 
 Built with gcc, ``-O2 -ffp-contract=off`` so every fp32 operation of the front
-end is one IEEE operation (no fused multiply-add), single-threaded.
+end is one IEEE operation (no fused multiply-add). Every entry point is
+single-threaded except ``orc_integrate_omp``, the all-core timing leg
+(OpenMP), whose planes equal the single-threaded ones bit for bit.
 """
 from __future__ import annotations
 
@@ -17,7 +19,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-std=c11", "-D_DEFAULT_SOURCE", "-O2", "-ffp-contract=off", "-fno-fast-math",
            "-fPIC", "-shared", "-Wall", "-Wextra", "-Wno-unused-parameter",
-           "-o", LIB + ".tmp", SRC, "-lm"]
+           "-fopenmp", "-o", LIB + ".tmp", SRC, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

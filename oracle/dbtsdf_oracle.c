@@ -67,6 +67,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_BIN_AZEL 0
 #define ORC_BIN_CUBE26 1
@@ -729,6 +732,123 @@ int orc_integrate_deskew(orc_ctx *c, uint32_t *mask, uint32_t *packed, const flo
                          orc_stats *st, int count_traffic)
 {
     return integrate(c, mask, packed, pose_start, pose_end, mode, times, pts, n, st, count_traffic);
+}
+
+/* ---- the same scan on every host core (OpenMP) --------------------------
+
+   For timing the CPU on the headline workload only. The front end runs in
+   parallel (it reads the tables and writes one slot per return), the
+   first-return test stays sequential (the lowest index of each voxel wins, as
+   above), and the windows are applied in parallel with an atomic fetch-and
+   per mask word and a compare-and-swap loop per counter word. Both updates
+   commute (eq. 4 is an AND; c unit steps of eqs. 5-6 in any order end in the
+   same word), so the planes equal those of orc_integrate bit for bit.
+   Statistics as orc_integrate without the traffic counts. Returns 1 on a
+   non-finite pose, 2 when the library was built without OpenMP, 3 when out
+   of memory. *threads receives the threads used. */
+int orc_integrate_omp(orc_ctx *c, uint32_t *mask, uint32_t *packed, const float pose[16], const float *pts,
+                      uint64_t n, orc_stats *st, int *threads)
+{
+#ifndef _OPENMP
+    (void)c; (void)mask; (void)packed; (void)pose; (void)pts; (void)n; (void)st;
+    if (threads)
+        *threads = 0;
+    return 2;
+#else
+    const int K = c->K, R = c->R;
+    const uint64_t nx = c->p.dims[0], ny = c->p.dims[1];
+    const uint32_t T = c->p.hit_threshold, HMAX = c->p.hit_max;
+    orc_stats s;
+    int k;
+    int64_t i;
+    for (k = 0; k < 16; k++)
+        if (!isfinite(pose[k]))
+            return 1;
+    memset(&s, 0, sizeof(s));
+    s.n_in = n;
+    if (threads)
+        *threads = omp_get_max_threads();
+    if (n == 0) {
+        if (st)
+            *st = s;
+        return 0;
+    }
+    int *vox = (int *)malloc(sizeof(int) * 3 * n);
+    int *bins = (int *)malloc(sizeof(int) * n);
+    int8_t *res = (int8_t *)malloc(n);
+    if (!vox || !bins || !res) {
+        free(vox);
+        free(bins);
+        free(res);
+        return 3;
+    }
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < (int64_t)n; i++)
+        res[i] = (int8_t)front_end(c, pose, pts + 3 * i, vox + 3 * i, bins + i);
+    seen_reset(c, n);
+    for (i = 0; i < (int64_t)n; i++) {
+        if (res[i] == ST_INVALID) {
+            s.n_invalid++;
+            continue;
+        }
+        if (res[i] == ST_OOB) {
+            s.n_out_of_bounds++;
+            continue;
+        }
+        const int *v = vox + 3 * i;
+        const uint64_t key = (uint64_t)v[0] + nx * ((uint64_t)v[1] + ny * (uint64_t)v[2]);
+        if (c->p.dedup && seen_test_and_insert(c, key)) {
+            s.n_duplicate++;
+            res[i] = -1;   /* lost the first-return test */
+            continue;
+        }
+        s.n_integrated++;
+    }
+    uint64_t vu = 0, su = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : vu, su)
+    for (i = 0; i < (int64_t)n; i++) {
+        int dx, dy, dz;
+        if (res[i] != ST_OK)
+            continue;
+        const int *v = vox + 3 * i;
+        const uint8_t *sh = c->shadow_k + (size_t)bins[i] * K * K * K;
+        for (dz = -R; dz <= R; dz++)
+            for (dy = -R; dy <= R; dy++)
+                for (dx = -R; dx <= R; dx++) {
+                    const int cell = ((dz + R) * K + (dy + R)) * K + (dx + R);
+                    const uint64_t u = (uint64_t)(v[0] + dx) + nx * ((uint64_t)(v[1] + dy) + ny * (uint64_t)(v[2] + dz));
+                    const uint32_t mk = c->mask_k[cell];
+                    vu++;
+                    /* words only lose bits: one already inside mk stays inside it */
+                    if (mk != 0xFFFFFFFFu) {
+                        const uint32_t g = __atomic_load_n(&mask[u], __ATOMIC_RELAXED);
+                        if ((g & mk) != g)
+                            __atomic_fetch_and(&mask[u], mk, __ATOMIC_RELAXED);
+                    }
+                    if (sh[cell]) {
+                        uint32_t word = __atomic_load_n(&packed[u], __ATOMIC_RELAXED), nw;
+                        do {
+                            const uint32_t h0 = word & 0xFFFFu;
+                            const uint32_t h1 = h0 + 1 < HMAX ? h0 + 1 : HMAX;
+                            uint32_t sign = word & 0x80000000u;
+                            if (h0 < T && h1 >= T)
+                                sign = 0;
+                            nw = sign | h1;
+                        } while (!__atomic_compare_exchange_n(&packed[u], &word, nw, 0, __ATOMIC_RELAXED,
+                                                              __ATOMIC_RELAXED));
+                        su++;
+                    }
+                }
+    }
+    s.voxel_updates = vu;
+    s.shadow_updates = su;
+    free(vox);
+    free(bins);
+    free(res);
+    if (st)
+        *st = s;
+    return 0;
+#endif
 }
 
 /* signed distance readout: (sign ? +1 : -1) * popcount(mask) */

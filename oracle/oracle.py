@@ -58,6 +58,9 @@ def _load():
         lib.orc_grid_init.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         lib.orc_front_end.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64,
                                       C.c_void_p, C.c_void_p, C.c_void_p]
+        lib.orc_integrate_omp.restype = C.c_int
+        lib.orc_integrate_omp.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.c_uint64, C.c_void_p, C.c_void_p]
         lib.orc_integrate.restype = C.c_int
         lib.orc_integrate.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_void_p, C.c_uint64, C.POINTER(_Stats), C.c_int]
@@ -161,6 +164,24 @@ class Oracle:
         if rc != 0:
             raise ValueError("oracle: non-finite pose")
         return {n: int(getattr(st, n)) for n, _ in _Stats._fields_}
+
+    def integrate_parallel(self, mask, packed, pose, pts):
+        """``integrate`` on every host core (OpenMP; the all-core CPU timing leg): the same planes bit for
+        bit, statistics without the traffic counts. Returns (statistics, threads used)."""
+        assert mask.dtype == np.uint32 and packed.dtype == np.uint32
+        assert mask.flags.c_contiguous and packed.flags.c_contiguous
+        assert mask.size == packed.size == self.dims[0] * self.dims[1] * self.dims[2]
+        pose = np.ascontiguousarray(pose, dtype=np.float32).reshape(16)
+        pts = np.ascontiguousarray(pts, dtype=np.float32).reshape(-1, 3)
+        st = _Stats()
+        thr = C.c_int(0)
+        rc = _lib.orc_integrate_omp(self._ctx, _ptr(mask), _ptr(packed), _ptr(pose), _ptr(pts), pts.shape[0],
+                                    C.byref(st), C.byref(thr))
+        if rc == 1:
+            raise ValueError("oracle: non-finite pose")
+        if rc != 0:
+            raise RuntimeError(f"oracle: parallel integration unavailable (code {rc})")
+        return {n: int(getattr(st, n)) for n, _ in _Stats._fields_}, int(thr.value)
 
     def integrate_deskew(self, mask, packed, pose_start, pose_end, pts, times, mode="se3",
                          count_traffic=False) -> dict:

@@ -566,3 +566,32 @@ def test_cones_nest_and_bad_angles_are_rejected():
     for deg in (0.0, -3.0, 90.5):
         with pytest.raises(ValueError):
             Oracle(dims=(16, 16, 16), voxel_size=1.0, kernel_size=5, shadow_model="cone", cone_deg=deg)
+
+
+def test_parallel_oracle_equals_serial():
+    """The all-core timing leg of the oracle (OpenMP, atomic AND and counter CAS) leaves the planes of the
+    single-threaded oracle bit for bit, with the same statistics, over scans that collide, repeat voxels
+    and saturate counters."""
+    import numpy as np
+    from oracle.oracle import Oracle
+    from synth import scene as synth
+    rng = np.random.default_rng(31)
+    for kw in (dict(kernel_size=11, binning="cube26", shadow_r2=9, hit_threshold=2, hit_max=3),
+               dict(kernel_size=7, binning="azel", bins_az=8, bins_el=5, shadow_r2=6, dedup=False)):
+        dims = (48, 40, 36)
+        a = Oracle(dims=dims, voxel_size=0.1, origin=(0.0, 0.0, 0.0), **kw)
+        ma, pa = a.new_grid()
+        mb, pb = a.new_grid()
+        c = np.array(dims) * 0.05
+        for _ in range(4):
+            pose = synth.random_pose(rng, c - 0.5, c + 0.5)
+            pts = synth.random_cloud(rng, 3000, -c * 0.9, c * 0.9)
+            pts = np.concatenate([pts, pts[:500]])          # repeated voxels
+            pts[rng.random(len(pts)) < 0.02] = np.nan
+            s1 = a.integrate(ma, pa, pose, pts)
+            s2, thr = a.integrate_parallel(mb, pb, pose, pts)
+            assert thr >= 1
+            for k in ("n_in", "n_invalid", "n_out_of_bounds", "n_duplicate", "n_integrated", "voxel_updates",
+                      "shadow_updates"):
+                assert s1[k] == s2[k], (k, s1[k], s2[k])
+        assert np.array_equal(ma, mb) and np.array_equal(pa, pb)
