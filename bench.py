@@ -291,7 +291,9 @@ def run_serve(db, torch, seconds, warm_s, rate_hz, n_robots, scans_per_robot, se
 
 
 def cpu_baseline(gdef, scans, kparams, budget_s=15.0):
-    """The CPU oracle, single-threaded, on the first scans of the same sequence."""
+    """The CPU oracle on the first scans of the same sequence: single-threaded (as it stands) until the
+    budget is spent, then the same scans on every host core (its OpenMP leg, the same planes bit for
+    bit) on a fresh grid."""
     from oracle.oracle import Oracle
     from synth import scene as synth
     kw = dict(synth.KERNEL_DEFAULTS)
@@ -307,9 +309,24 @@ def cpu_baseline(gdef, scans, kparams, budget_s=15.0):
         n += 1
         if t_tot > budget_s:
             break
+    del m, p
+    gc.collect()
+    m, p = o.new_grid()
+    upd_p, t_par, threads = 0, 0.0, 0
+    for pose, pts in scans[:n]:
+        t0 = time.perf_counter()
+        st, threads = o.integrate_parallel(m, p, pose, pts)
+        t_par += time.perf_counter() - t0
+        upd_p += st["voxel_updates"]
+    del m, p
+    gc.collect()
     return dict(value=upd / t_tot, unit="voxel-updates/s", cores=1, kind="oracle",
                 sample=f"first {n} scans of the same sequence, single-threaded C oracle, {t_tot:.1f}s",
-                scans_per_s=n / t_tot, host=host_cpu())
+                scans_per_s=n / t_tot, host=host_cpu(),
+                all_cores=dict(value=upd_p / t_par, unit="voxel-updates/s", cores=threads,
+                               kind="oracle, OpenMP leg (atomic AND and counter compare-and-swap)",
+                               sample=f"the same {n} scans on a fresh grid, {t_par:.1f}s", scans_per_s=n / t_par,
+                               speedup_vs_1core=(upd_p / t_par) / (upd / t_tot)))
 
 
 def host_cpu():
@@ -350,6 +367,71 @@ def run_mesh(torch, g, dims, reps=3):
                               per_launch="8 B per voxel (both planes read once) + 36 B per triangle written"),
                 timing="HIP events around one extraction call (best of %d), whole grid" % reps,
                 points=run_points(torch, g, dims, reps))
+
+
+def run_accuracy(db, torch, synth, g, gdef, cfg, n_scans, tolerance=0.1):
+    """Accuracy metrics (Sec. IV-A) of the map after the plain leg's scans against the exact hits of the
+    same rays (one per voxel-sized cube, inside the grid): for the mesh vertices and for the point export,
+    each scored on the GPU (nearest squared distances in fp64, both directions)."""
+    t0 = time.perf_counter()
+    gt = synth.config_ground_truth(cfg, scan_ids=range(n_scans), cell=gdef["voxel_size"])
+    lo = np.array(gdef["origin"], np.float64)
+    hi = lo + np.array(gdef["dims"], np.float64) * gdef["voxel_size"]
+    gt = gt[np.all((gt >= lo) & (gt < hi), axis=1)]
+    t_gt = time.perf_counter() - t0
+    gt_dev = torch.from_numpy(np.ascontiguousarray(gt)).cuda()
+    out = dict(tolerance_m=tolerance, reference=f"exact hits of the rays of scans 0-{n_scans - 1}, first per "
+               f"{gdef['voxel_size']:.3f} m cube", n_reference=int(gt.shape[0]), reference_s=t_gt)
+    sets = {"mesh_vertices": lambda: db.mesh_vertices(g.extract_mesh()), "point_export": g.extract_points}
+    for name, get in sets.items():
+        pred = get()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        m = db.surface_metrics(pred, gt_dev, tolerance)
+        m["gpu_s"] = time.perf_counter() - t1
+        out[name] = m
+        del pred
+        torch.cuda.empty_cache()
+    return out
+
+
+MRES_SIZES = (0.3, 0.2, 0.1, 0.05)
+
+
+def run_mres(db, torch, synth, ks, tuning, n_scans=10, reps=3):
+    """Per-scan cost against voxel size (Sec. IV-B, eq. 7: constant per scan): scans 0 .. n_scans-1 of the
+    second workload integrated into a fresh grid of the same room at each voxel size (the same K^3 kernel,
+    so the same work per return), timed from the first call to the final sync; best of `reps` fresh grids."""
+    scans = list(synth.config_scans(2, 0, range(n_scans)))
+    dev = [(pose, torch.from_numpy(pts).cuda()) for pose, pts in scans]
+    out = []
+    for s in MRES_SIZES:
+        gd = synth.resolution_grid(s)
+        best = None
+        for _ in range(reps):
+            g = db.Grid(gd["dims"], gd["voxel_size"], gd["origin"], ks)
+            if tuning:
+                g.set_tuning(**{k: v for k, v in tuning.items() if k != "apply_blocks"})
+            warm_ring(g, dev[0][1])
+            g.sync()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = [g.integrate(pose, pts) for pose, pts in dev]
+            g.sync()
+            dt = time.perf_counter() - t0
+            g.close()
+            torch.cuda.empty_cache()
+            if best is None or dt < best[0]:
+                best = (dt, st)
+        dt, st = best
+        out.append(dict(voxel_size_m=s, grid=list(gd["dims"]), ms_per_scan=dt * 1e3 / n_scans,
+                        integrated_per_scan=float(np.mean([x.as_dict()["n_integrated"] for x in st])),
+                        revisit_frac=float(np.sum([x.as_dict()["n_revisit"] for x in st]) /
+                                           max(1, np.sum([x.as_dict()["n_integrated"] for x in st])))))
+    t = [r["ms_per_scan"] for r in out]
+    return dict(scans=f"second workload, scans 0-{n_scans - 1} (64 x 1024 returns each)", by_voxel_size=out,
+                max_over_min_ms=max(t) / min(t),
+                timing="wall clock from the first integrate call to the final sync, best of %d fresh grids" % reps)
 
 
 def run_points(torch, g, dims, reps=3):
@@ -504,6 +586,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mesh", action="store_true", help="skip the mesh export leg")
     ap.add_argument("--no-deskew", action="store_true", help="skip the motion-compensated sweep leg")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the accuracy-metrics leg")
+    ap.add_argument("--no-mres", action="store_true", help="skip the per-scan cost against voxel size leg")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--latency-scans", type=int, default=50)
     ap.add_argument("--serve-seconds", type=float, default=5.0)
@@ -575,6 +659,10 @@ def main():
     mesh = None if args.no_mesh else run_mesh(torch, g, gdef["dims"])
     if mesh:
         log(f"mesh: {mesh}")
+    accuracy = None
+    if not args.no_accuracy:
+        accuracy = run_accuracy(db, torch, synth, g, gdef, cfg, args.warmup + args.steps)
+        log(f"accuracy: {accuracy}")
     plain_grid = g          # kept for the batched form's word-for-word comparison
     if args.no_batched:
         g.close()
@@ -656,6 +744,12 @@ def main():
         log(f"batched: {batched}")
         torch.cuda.empty_cache()
 
+    mres = None
+    if not args.no_mres:
+        mres = run_mres(db, torch, synth, ks, tuning)
+        log(f"mres: {mres}")
+        torch.cuda.empty_cache()
+
     lat = plain_latency(db, torch, gdef, ks, dev, args.latency_scans, tuning) if args.latency_scans else []
     latency = dict(plain_p50_ms=pct(lat, 50), plain_p99_ms=pct(lat, 99), plain_scans=len(lat),
                    plain_definition="integrate_scan call to sync return, one scan at a time, scans 0.. of the "
@@ -706,6 +800,8 @@ def main():
         "timed_scans": [args.warmup, args.warmup + args.steps - 1],
         "batched": batched,
         "mesh_export": mesh,
+        "accuracy": accuracy,
+        "mres": mres,
         "deskew": deskew,
         "latency_ms": latency,
         "served": served,

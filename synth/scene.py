@@ -339,3 +339,14 @@ def config_ground_truth(cfg: int, map_id: int = 0, scan_ids=None, n_scans: int |
     key = k[:, 0] | (k[:, 1] << 21) | (k[:, 2] << 42)
     _, first = np.unique(key, return_index=True)
     return np.ascontiguousarray(pts[np.sort(first)].astype(np.float32))
+
+
+def resolution_grid(s: float) -> dict:
+    """The second configuration's room (1024 x 1024 x 256 voxels at 0.05 m: 51.2 x 51.2 x 12.8 m, same
+    centre) at voxel size ``s``, for the per-scan cost against resolution sweep."""
+    base = config_grid(2)
+    ext = np.array(base["dims"], np.float64) * base["voxel_size"]
+    dims = tuple(int(round(e / s)) for e in ext)
+    centre = np.array(base["origin"], np.float64) + ext / 2.0
+    origin = (centre - np.array(dims, np.float64) * np.float32(s) / 2.0).astype(np.float32)
+    return dict(dims=dims, voxel_size=float(np.float32(s)), origin=tuple(float(v) for v in origin))

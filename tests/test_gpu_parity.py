@@ -1040,3 +1040,141 @@ def test_context_free_batch_matches_oracle(db):
             P.assert_stats_equal(stats[k].as_dict(), ref, what=f"round {rnd} scan {k}")
         for gi in range(2):
             P.assert_grids_equal(*P.gpu_planes(pairs[gi][1]), *refs[gi], what=f"round {rnd} grid {gi}")
+
+
+# ---------------------------------------------------------------------------
+# whole grids at full size, on the paths the benchmark times
+# ---------------------------------------------------------------------------
+_C2_ORACLE = {}
+
+
+def _c2_oracle(n_scans):
+    """Oracle planes after scans 0 .. n_scans-1 of the 1024x1024x256 @ 0.05 m sequence (computed once)."""
+    if n_scans not in _C2_ORACLE:
+        gdef = synth.config_grid(2)
+        from oracle.oracle import Oracle
+        kk, gk = P.split_kw(synth.KERNEL_DEFAULTS)
+        o = Oracle(dims=gdef["dims"], voxel_size=gdef["voxel_size"], origin=gdef["origin"], **kk, **gk)
+        m, p = o.new_grid()
+        stats = [o.integrate(m, p, pose, pts) for pose, pts in synth.config_scans(2, 0, range(n_scans))]
+        _C2_ORACLE.clear()
+        _C2_ORACLE[n_scans] = (m, p, stats)
+    return _C2_ORACLE[n_scans]
+
+
+@pytest.mark.parametrize("strategy", ["tile", "atomic"])
+def test_config2_default_paths_whole_grid(db, strategy):
+    """The plain one-scan calls the benchmark times (device points, no traffic counting, so the per-point
+    strategies run with their revisit skips) over 24 scans of 1024x1024x256 @ 0.05 m: every word of
+    both planes and every scan's statistics against the oracle."""
+    m, p, stats = _c2_oracle(24)
+    gdef = synth.config_grid(2)
+    ks = db.KernelSet(kernel_size=11, binning="cube26", shadow_r2=9)
+    g = db.Grid(gdef["dims"], gdef["voxel_size"], gdef["origin"], ks, planes="torch")
+    g.set_tuning(strategy=strategy)
+    revisits = 0
+    for k, (pose, pts) in enumerate(synth.config_scans(2, 0, range(24))):
+        st = g.integrate(pose, P.to_device(pts))
+        g.sync()   # a plain call's statistics arrive with the sync
+        st = st.as_dict()
+        P.assert_stats_equal(st, stats[k], what=f"c2 scan {k}")
+        revisits += st["n_revisit"]
+    assert revisits > 0, "the sequence must exercise the revisit skip"
+    gm, gp = P.gpu_planes(g)
+    P.assert_grids_equal(gm, gp, m, p, what=f"c2 24 scans, {strategy}")
+    g.close()
+
+
+@pytest.mark.parametrize("strategy", ["atomic", "sort"])
+def test_paper_kernel_set_config2_whole_grid(db, strategy):
+    """The paper's kernel set (K = 21, 40 x 40 direction bins) on three scans of 1024x1024x256 @ 0.05 m:
+    whole grid and statistics against the oracle."""
+    gdef = synth.config_grid(2)
+    kw = dict(synth.KERNEL_DEFAULTS)
+    kw.update(PAPER_KERNEL)
+    o, g, _ = P.make_pair(gdef["dims"], gdef["voxel_size"], gdef["origin"], **kw)
+    g.set_tuning(strategy=strategy)
+    m, p = o.new_grid()
+    for k, (pose, pts) in enumerate(synth.config_scans(2, 0, range(3))):
+        ref = o.integrate(m, p, pose, pts)
+        st = g.integrate(pose, P.to_device(pts))
+        g.sync()
+        P.assert_stats_equal(st.as_dict(), ref, what=f"paper kernel c2 scan {k}")
+    gm, gp = P.gpu_planes(g)
+    P.assert_grids_equal(gm, gp, m, p, what=f"paper kernel c2, {strategy}")
+    g.close()
+
+
+def test_config3_whole_grid(db):
+    """2048x2048x512 @ 0.02 m (2^31 voxels): three scans on the default tuning, every word of both planes
+    against the oracle (17 GB per side), compared a slab of 64 z layers at a time."""
+    import torch
+    gdef = synth.config_grid(3)
+    kk, gk = P.split_kw(synth.KERNEL_DEFAULTS)
+    from oracle.oracle import Oracle
+    o = Oracle(dims=gdef["dims"], voxel_size=gdef["voxel_size"], origin=gdef["origin"], **kk, **gk)
+    m, p = o.new_grid()
+    ks = db.KernelSet(**kk)
+    g = db.Grid(gdef["dims"], gdef["voxel_size"], gdef["origin"], ks, planes="torch", **gk)
+    for k, (pose, pts) in enumerate(synth.config_scans(3, 0, range(3))):
+        ref = o.integrate(m, p, pose, pts)
+        st = g.integrate(pose, P.to_device(pts))
+        g.sync()
+        P.assert_stats_equal(st.as_dict(), ref, what=f"c3 scan {k}")
+    torch.cuda.synchronize()
+    nz = gdef["dims"][2]
+    for z0 in range(0, nz, 64):
+        gm = g.mask_tensor[z0:z0 + 64].cpu().numpy().view(np.uint32)
+        gp = g.packed_tensor[z0:z0 + 64].cpu().numpy().view(np.uint32)
+        P.assert_grids_equal(gm, gp, m[z0:z0 + 64], p[z0:z0 + 64], what=f"c3 z {z0}-{z0 + 63}")
+    g.close()
+    del g
+    torch.cuda.empty_cache()
+
+
+def test_served_mix_512_cubes_match_oracle(db):
+    """Eight robots' maps of 512^3 @ 0.05 m served concurrently (continuous batching over two streams),
+    four scans each: every map word for word against the oracle run of that robot's scans alone."""
+    from paper_2509_20081_amd.serve import Server
+    from oracle.oracle import Oracle
+    kk, gk = P.split_kw(synth.KERNEL_DEFAULTS)
+    ks = db.KernelSet(**kk)
+    dims = synth.CONFIGS[5]["dims"]
+    robots = []
+    for rid in range(8):
+        gd = synth.config_grid(5, rid)
+        robots.append((gd, list(synth.config_scans(5, rid, range(4)))))
+    srv = Server(n_streams=2, max_batch_scans=8)
+    ids = [srv.add_map(dims, gd["voxel_size"], gd["origin"], ks) for gd, _ in robots]
+    for k in range(4):
+        for rid, (_, scans) in enumerate(robots):
+            srv.submit(ids[rid], scans[k][0], scans[k][1])
+    srv.drain()
+    done = srv.poll(100)
+    assert len(done) == 32 and all(c["status"] == 0 for c in done)
+    for rid, (gd, scans) in enumerate(robots):
+        o = Oracle(dims=dims, voxel_size=gd["voxel_size"], origin=gd["origin"], **kk, **gk)
+        m, p = o.new_grid()
+        for pose, pts in scans:
+            o.integrate(m, p, pose, pts)
+        s = srv.map_grid(ids[rid], dims, ks).read_voxels()
+        P.assert_grids_equal(s[0], s[1], m, p, what=f"served robot {rid}")
+    srv.close()
+
+
+@pytest.mark.parametrize("s", [0.3, 0.2, 0.1, 0.05])
+def test_resolution_sweep_scan0_whole_grid(db, s):
+    """Scan 0 of the 64x1024 sequence into the same 51.2 x 51.2 x 12.8 m room at voxel size s (the
+    per-scan cost against resolution leg): whole grid and statistics against the oracle."""
+    gd = synth.resolution_grid(s)
+    o, g, _ = P.make_pair(gd["dims"], gd["voxel_size"], gd["origin"], **synth.KERNEL_DEFAULTS)
+    m, p = o.new_grid()
+    for pose, pts in synth.config_scans(2, 0, [0]):
+        ref = o.integrate(m, p, pose, pts)
+        st = g.integrate(pose, P.to_device(pts))
+        g.sync()
+        P.assert_stats_equal(st.as_dict(), ref, what=f"scan 0 at {s} m")
+    gm, gp = P.gpu_planes(g)
+    P.assert_grids_equal(gm, gp, m, p, what=f"scan 0 at {s} m")
+    assert ref["n_integrated"] > 1000
+    g.close()
