@@ -244,28 +244,36 @@ def plain_latency(db, torch, gdef, ks, dev, n, tuning):
     return lat
 
 
-def run_serve(db, torch, seconds, warm_s, rate_hz, n_robots, scans_per_robot, seed=5):
-    """Served form: n_robots maps of 512^3 @ 0.05 m, Poisson arrivals totalling rate_hz."""
+def run_serve(db, torch, seconds, warm_s, rate_hz, n_robots, seed=5, check_robot=0):
+    """Served form: n_robots maps of 512^3 @ 0.05 m, Poisson arrivals totalling rate_hz for warm_s + seconds;
+    every arrival brings the robot's next scan along its own trajectory (no scan repeats). At the end one
+    map is compared word for word with the oracle (all-core leg) fed that robot's scans in order."""
     from paper_2509_20081_amd.serve import Server, poisson_arrivals, run_open_loop
     from synth import scene as synth
     ks = db.KernelSet(kernel_size=11, binning="cube26", shadow_r2=9)
+    rng = np.random.default_rng([20081, 5, seed])
+    arr = poisson_arrivals(rng, rate_hz, warm_s + seconds)
+    robots = rng.integers(0, n_robots, size=len(arr))
+    per_robot = np.bincount(robots, minlength=n_robots)
     t = time.time()
-    robot_scans = [list(synth.config_scans(5, r, range(scans_per_robot))) for r in range(n_robots)]
-    log(f"generated {n_robots}x{scans_per_robot} served scans in {time.time() - t:.1f}s")
+    streams = []
+    for r in range(n_robots):
+        sc = synth.served_scans(r, int(per_robot[r]), torch)
+        streams.append([(pose, pts.cpu().numpy()) for pose, pts in sc])
+        del sc
+    torch.cuda.empty_cache()
+    n_pts = sum(int(p.shape[0]) for st in streams for _, p in st)
+    log(f"generated {len(arr)} distinct served scans ({n_pts} points) in {time.time() - t:.1f}s")
     srv = Server(n_streams=2, max_batch_scans=64, use_graph=True)
     ids = []
     for r in range(n_robots):
         gdef = synth.config_grid(5, r)
         ids.append(srv.add_map(gdef["dims"], gdef["voxel_size"], gdef["origin"], ks))
-    rng = np.random.default_rng([20081, 5, seed])
-    arr = poisson_arrivals(rng, rate_hz, warm_s + seconds)
-    robots = rng.integers(0, n_robots, size=len(arr))
     counters = [0] * n_robots
     schedule = []
     for toff, r in zip(arr, robots):
-        k = counters[r] % scans_per_robot
+        pose, pts = streams[r][counters[r]]
         counters[r] += 1
-        pose, pts = robot_scans[r][k]
         schedule.append((float(toff), ids[r], pose, pts))
     log(f"serving {len(schedule)} scans over {warm_s + seconds:.1f}s")
     with no_gc():
@@ -280,12 +288,25 @@ def run_serve(db, torch, seconds, warm_s, rate_hz, n_robots, scans_per_robot, se
     else:
         span = float("nan")
     upd = sum(c["stats"]["voxel_updates"] for c in meas)
+    # one map against the oracle
+    t = time.time()
+    from oracle.oracle import Oracle
+    gd = synth.config_grid(5, check_robot)
+    kw = dict(synth.KERNEL_DEFAULTS)
+    o = Oracle(dims=gd["dims"], voxel_size=gd["voxel_size"], origin=gd["origin"], **kw)
+    m, p = o.new_grid()
+    for pose, pts in streams[check_robot]:
+        o.integrate_parallel(m, p, pose, pts)
+    sm, sp = srv.map_grid(ids[check_robot], gd["dims"], ks).read_voxels()
+    check = dict(robot=check_robot, scans=int(per_robot[check_robot]),
+                 equal=bool(np.array_equal(sm, m) and np.array_equal(sp, p)), s=time.time() - t)
+    del m, p, sm, sp
     out = dict(workload="c5_32robots_512cube_poisson", robots=n_robots, offered_scans_per_s=rate_hz,
-               measured_s=seconds, scans=len(meas), failed=len(bad),
+               warmup_s=warm_s, measured_s=seconds, scans=len(meas), failed=len(bad),
                value=upd / span if span else None, unit="voxel-updates/s",
                scans_per_s=len(meas) / span if span else None,
                p50_ms=pct(lat, 50), p99_ms=pct(lat, 99), mean_batch_scans=float(np.mean([c["batch_scans"] for c in meas]))
-               if meas else None, scans_per_robot_replayed=scans_per_robot)
+               if meas else None, distinct_scans=True, points=n_pts, oracle_check=check)
     srv.close()
     return out
 
@@ -371,7 +392,8 @@ def run_mesh(torch, g, dims, reps=3):
 
 def run_accuracy(db, torch, synth, g, gdef, cfg, n_scans, tolerance=0.1):
     """Accuracy metrics (Sec. IV-A) of the map after the plain leg's scans against the exact hits of the
-    same rays (one per voxel-sized cube, inside the grid): for the mesh vertices and for the point export,
+    same rays (one per voxel-sized cube, inside the grid): for the mesh (one point per triangle, its
+    centroid) and for the point export,
     each scored on the GPU (nearest squared distances in fp64, both directions)."""
     t0 = time.perf_counter()
     gt = synth.config_ground_truth(cfg, scan_ids=range(n_scans), cell=gdef["voxel_size"])
@@ -382,7 +404,7 @@ def run_accuracy(db, torch, synth, g, gdef, cfg, n_scans, tolerance=0.1):
     gt_dev = torch.from_numpy(np.ascontiguousarray(gt)).cuda()
     out = dict(tolerance_m=tolerance, reference=f"exact hits of the rays of scans 0-{n_scans - 1}, first per "
                f"{gdef['voxel_size']:.3f} m cube", n_reference=int(gt.shape[0]), reference_s=t_gt)
-    sets = {"mesh_vertices": lambda: db.mesh_vertices(g.extract_mesh()), "point_export": g.extract_points}
+    sets = {"mesh_centroids": lambda: db.mesh_centroids(g.extract_mesh()), "point_export": g.extract_points}
     for name, get in sets.items():
         pred = get()
         torch.cuda.synchronize()
@@ -502,7 +524,8 @@ def run_c4(db, torch, ks, n_maps, n_scans, tuning):
         maps.append((gdef, sc))
     n_pts = sum(int(x.shape[0]) for _, sc in maps for _, x in sc)
     log(f"c4: generated {n_maps} maps x {n_scans} scans ({n_pts} points) in {time.time() - t:.1f}s")
-    small = [m for m, (gd, _) in enumerate(maps) if max(gd["dims"]) <= 384]
+    # up to 16 maps every map is compared; beyond, those of side <= 384 (their plain grids stay resident)
+    small = list(range(n_maps)) if n_maps <= 16 else [m for m, (gd, _) in enumerate(maps) if max(gd["dims"]) <= 384]
 
     def make_grids():
         gs = []
@@ -562,14 +585,15 @@ def run_c4(db, torch, ks, n_maps, n_scans, tuning):
     del gs
     torch.cuda.empty_cache()
     grid_gb = sum(2 * 4 * gd["dims"][0] * gd["dims"][1] * gd["dims"][2] for gd, _ in maps) / 1e9
-    return dict(workload="c4_64maps_x20scans", maps=n_maps, scans_per_map=n_scans, points=n_pts,
+    return dict(workload=f"c4_{n_maps}maps_x{n_scans}scans", maps=n_maps, scans_per_map=n_scans, points=n_pts,
                 resident_grid_gb=grid_gb,
                 timed_rounds=n_scans - 1,
                 plain=dict(value=upd / dt_plain, unit="voxel-updates/s", scans_per_s=n_maps * (n_scans - 1) / dt_plain),
                 batched=dict(value=updb / dt_b, unit="voxel-updates/s", scans_per_s=n_maps * (n_scans - 1) / dt_b,
                              scans_per_launch=n_maps, graph_captures=caps, graph_replays=reps),
                 speedup=(updb / dt_b) / (upd / dt_plain), updates_equal=upd == updb,
-                bit_exact_maps_checked=len(small), bit_exact=same)
+                bit_exact_maps_checked=len(small), bit_exact=same,
+                comparison="both planes of each checked map word for word on the device (torch.equal)")
 
 
 def main():
@@ -590,13 +614,14 @@ def main():
     ap.add_argument("--no-mres", action="store_true", help="skip the per-scan cost against voxel size leg")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--latency-scans", type=int, default=50)
-    ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-warmup", type=float, default=1.0)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-robots", type=int, default=32)
-    ap.add_argument("--serve-scans-per-robot", type=int, default=6)
     ap.add_argument("--copy-calibration", action="store_true")
-    ap.add_argument("--c4", action="store_true", help="also run the 64-map batching workload (about 160 GB of grids)")
+    ap.add_argument("--c4-maps", type=int, default=16,
+                    help="maps of the batching workload (plain against batched, every map compared when <= 16; "
+                         "64 is the full workload, about 160 GB of grids; 0 skips it)")
     ap.add_argument("--kernel", choices=("workload", "paper"), default="workload",
                     help="kernel set: the workload's (K = 11, 26 cube bins) or the paper's (K = 21, 40 x 40 bins)")
     ap.add_argument("--tuning", type=str, default="", help="JSON tuning to use instead of autotuning")
@@ -758,17 +783,15 @@ def main():
 
     served = None
     if not args.no_serve:
-        served = run_serve(db, torch, args.serve_seconds, args.serve_warmup, args.serve_rate, args.serve_robots,
-                           args.serve_scans_per_robot)
+        served = run_serve(db, torch, args.serve_seconds, args.serve_warmup, args.serve_rate, args.serve_robots)
         latency.update(served_p50_ms=served["p50_ms"], served_p99_ms=served["p99_ms"],
                        served_definition="scheduled arrival to observed completion, Poisson arrivals")
         log(f"served: {served}")
 
     c4 = None
-    if args.c4:
-        del dev
+    if args.c4_maps:
         torch.cuda.empty_cache()
-        c4 = run_c4(db, torch, ks, synth.CONFIGS[4]["maps"], synth.CONFIGS[4]["scans"], tuning)
+        c4 = run_c4(db, torch, ks, args.c4_maps, synth.CONFIGS[4]["scans"], tuning)
         log(f"c4: {c4}")
 
     cpu = None if args.no_cpu else cpu_baseline(gdef, scans[: min(len(scans), 80)], kparams)

@@ -24,7 +24,7 @@ from . import _lib as L
 from ._lib import DbtsdfError  # noqa: F401
 
 __all__ = ["KernelSet", "Grid", "Batch", "Server", "DbtsdfError", "now_ns", "library_path", "nearest_sq",
-           "surface_metrics", "mesh_vertices"]
+           "surface_metrics", "mesh_vertices", "mesh_centroids"]
 
 _BINNING = {"azel": L.BIN_AZEL, "cube26": L.BIN_CUBE26}
 _METRIC = {"l2": L.DIST_L2, "l1": L.DIST_L1}
@@ -145,6 +145,16 @@ def surface_metrics(pred, gt, tolerance: float) -> dict:
             "precision": m.precision, "recall": m.recall, "fscore": m.fscore, "n_pred": int(m.n_pred),
             "n_gt": int(m.n_gt), "n_pred_within": int(m.n_pred_within), "n_gt_within": int(m.n_gt_within),
             "tolerance": float(tolerance)}
+
+
+def mesh_centroids(tris):
+    """The predicted point set the benchmark scores: one point per triangle of a mesh from
+    Grid.extract_mesh, its centroid: the three fp32 vertices summed in fp64 (exact for coordinates of
+    like magnitude, so the vertex order does not matter), divided by 3 and rounded to fp32 (a (n, 3)
+    float32 CUDA tensor)."""
+    import torch
+    t = tris.reshape(-1, 3, 3).to(torch.float64)
+    return ((t[:, 0] + t[:, 1] + t[:, 2]) / 3.0).to(torch.float32).contiguous()
 
 
 def mesh_vertices(tris):

@@ -6,16 +6,19 @@
 // grid of cubic cells of side h over the bounding box of both sets (count,
 // prefix, fill). A query walks the cells around its own in shells of growing
 // Chebyshev radius r; once shell r is done, every point not yet visited lies
-// at least r h away (its cell index differs from the query's by more than r
-// on some axis), so the search ends when the best squared distance is at most
-// ((r - 1e-6) h)^2, or when the shells cover the whole grid. A query still
-// open after kMaxShell shells scans every reference point. Either way the
-// result is the minimum over all reference points of
+// beyond the block of visited cells on some axis, so the search ends when the
+// best squared distance is at most the squared gap between the query and the
+// nearest side of the block (less a rounding margin; at least r h), or when
+// the shells cover the whole grid. A query still open after kFineShells
+// shells continues on a second grid of cells kCoarse times wider (its nearest
+// point is far, and fine shells would be many). Either way the result is the
+// minimum over all reference points of
 // ((qx - rx)^2 + (qy - ry)^2) + (qz - rz)^2 in fp64 (one operation at a time,
 // no contraction), the same value whatever the visiting order.
 //
-// Sums are taken per workgroup and then in workgroup order, so repeated
-// calls give the same bits.
+// The queries are bucketed by the same cells and taken in cell order, so
+// that the lanes of a wavefront walk the same cells. Sums are taken per
+// workgroup and then in workgroup order, so repeated calls give the same bits.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,9 +32,11 @@ namespace dbtsdf {
 namespace {
 
 constexpr int kMetThreads = 256;
-constexpr int kMaxShell = 6;
+constexpr int kFineShells = 3;   // fine shells (7^3 cells) before the coarse grid takes over
+constexpr double kCoarse = 8.0;  // coarse cell side, in fine cells
 constexpr uint32_t kScanItems = 1024;          // prefix: elements per workgroup (4 per thread)
-constexpr double kMaxCells = 16.0 * 1024 * 1024;
+constexpr double kMaxCells = 128.0 * 1024 * 1024;   // cell grid: at most ~2x this many cells
+constexpr double kCellsPerRef = 64.0;               // and about this many per reference point (min 2^20)
 
 typedef __attribute__((address_space(1))) const float mgf32;
 
@@ -184,28 +189,29 @@ __global__ __launch_bounds__(kMetThreads) void k_cell_fill(const float *p, uint6
     sorted[pos] = make_float4(q[0], q[1], q[2], 0.0f);
 }
 
+// the queries' indices in cell order (lanes of a wavefront then walk the same
+// cells and read the same reference points)
+__global__ __launch_bounds__(kMetThreads) void k_query_fill(uint64_t n, const uint32_t *cell, const uint32_t *start,
+                                                             uint32_t *cursor, uint32_t *perm) {
+    const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t c = cell[i];
+    perm[start[c] + atomicAdd(&cursor[c], 1u)] = (uint32_t)i;
+}
+
 __device__ __forceinline__ double sq_dist(double qx, double qy, double qz, float4 r) {
     const double dx = qx - (double)r.x, dy = qy - (double)r.y, dz = qz - (double)r.z;
     return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
 }
 
-__global__ __launch_bounds__(kMetThreads) void k_nearest(CellGrid cg, const float *qp, uint64_t nq,
-                                                          const uint32_t *start, const float4 *sorted,
-                                                          uint32_t n_ref, double *d2_out) {
-    const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-    if (i >= nq) return;
-    const mgf32 *q = (mgf32 *)qp + 3 * i;
-    const float fx = q[0], fy = q[1], fz = q[2];
-    const double qx = fx, qy = fy, qz = fz;
-    int c[3];
-    cell_of(cg, fx, fy, fz, c);
-    double best = INFINITY;
-    // shells needed to cover the whole grid from this cell
-    int r_all = 0;
+// Shells 0 .. r_max of cells around the query's cell c (u: the query in cell
+// units) into best; true once nothing unvisited can be closer.
+__device__ bool shell_search(const CellGrid &cg, const int c[3], const double u[3], const uint32_t *start,
+                             const float4 *sorted, double qx, double qy, double qz, int r_max, double &best) {
+    int r_all = 0;   // shells that cover the whole grid from this cell
 #pragma unroll
     for (int a = 0; a < 3; ++a) r_all = max(r_all, max(c[a], cg.dims[a] - 1 - c[a]));
-    bool done = false;
-    for (int r = 0; r <= min(r_all, kMaxShell); ++r) {
+    for (int r = 0; r <= min(r_all, r_max); ++r) {
         const int z0 = max(c[2] - r, 0), z1 = min(c[2] + r, cg.dims[2] - 1);
         const int y0 = max(c[1] - r, 0), y1 = min(c[1] + r, cg.dims[1] - 1);
         for (int z = z0; z <= z1; ++z) {
@@ -221,21 +227,49 @@ __global__ __launch_bounds__(kMetThreads) void k_nearest(CellGrid cg, const floa
                 }
             }
         }
-        if (r == r_all) {
-            done = true;
-            break;
+        if (r == r_all) return true;
+        // after shell r every unvisited point lies in a cell outside the block
+        // [c - r, c + r] on some axis, so at least the query's gap to that
+        // side of the block away (less a margin for the rounding of the cell
+        // indices); sides at the grid's edge have nothing beyond them
+        double gap = INFINITY;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (c[a] - r > 0) gap = fmin(gap, u[a] - (double)(c[a] - r));
+            if (c[a] + r + 1 < cg.dims[a]) gap = fmin(gap, (double)(c[a] + r + 1) - u[a]);
         }
-        // after shell r every unvisited point lies more than r h away (less a
-        // margin for the rounding of the cell indices)
-        const double bound = ((double)r - 1e-6) * cg.h;
-        if (r > 0 && best <= bound * bound) {
-            done = true;
-            break;
-        }
+        const double bound = (gap - 1e-9) * cg.h;
+        if (bound > 0.0 && best <= bound * bound) return true;
     }
-    if (!done) {
-        best = INFINITY;
-        for (uint32_t k = 0; k < n_ref; ++k) best = fmin(best, sq_dist(qx, qy, qz, sorted[k]));
+    return false;
+}
+
+// One query per lane, in cell order: a few shells of the fine grid, then, for
+// a query still open (its nearest point is far), shells of the coarse grid
+// (cells kCoarse times wider) until nothing unvisited can be closer or the
+// whole grid is covered.
+__global__ __launch_bounds__(kMetThreads) void k_nearest(CellGrid cg, CellGrid cg2, const float *qp, uint64_t nq,
+                                                          const uint32_t *perm, const uint32_t *start,
+                                                          const float4 *sorted, const uint32_t *start2,
+                                                          const float4 *sorted2, double *d2_out) {
+    const uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (t >= nq) return;
+    const uint64_t i = perm[t];
+    const mgf32 *q = (mgf32 *)qp + 3 * i;
+    const float fx = q[0], fy = q[1], fz = q[2];
+    const double qx = fx, qy = fy, qz = fz;
+    const float fq[3] = {fx, fy, fz};
+    double best = INFINITY;
+    int c[3];
+    double u[3];   // the query in cell units (as cell_of computes it)
+    cell_of(cg, fx, fy, fz, c);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) u[a] = ((double)fq[a] - cg.lo[a]) * cg.inv_h;
+    if (!shell_search(cg, c, u, start, sorted, qx, qy, qz, kFineShells, best)) {
+        cell_of(cg2, fx, fy, fz, c);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) u[a] = ((double)fq[a] - cg2.lo[a]) * cg2.inv_h;
+        (void)shell_search(cg2, c, u, start2, sorted2, qx, qy, qz, 1 << 20, best);   // ends by covering the grid
     }
     d2_out[i] = best;
 }
@@ -330,11 +364,12 @@ dbtsdf_status nearest_sq(const float *qp, uint64_t nq, const float *rp, uint64_t
         emax = std::max(emax, ext[a]);
         vol *= std::max(ext[a], 1e-30);
     }
-    double h = std::max({cell_hint, std::cbrt(vol / kMaxCells), emax / 1024.0, 1e-6});
+    const double target = std::min(kMaxCells, std::max(1048576.0, kCellsPerRef * (double)nr));
+    double h = std::max({cell_hint, std::cbrt(vol / target), emax / 4096.0, 1e-6});
     for (;;) {
         double cells = 1.0;
         for (int a = 0; a < 3; ++a) cells *= std::floor(ext[a] / h) + 1.0;
-        if (cells <= 2.0 * kMaxCells) break;
+        if (cells <= 2.0 * target) break;
         h *= 1.25;
     }
     cg.h = h;
@@ -344,31 +379,64 @@ dbtsdf_status nearest_sq(const float *qp, uint64_t nq, const float *rp, uint64_t
         cg.dims[a] = (int)(std::floor(ext[a] / h) + 1.0);
         n_cells *= (uint64_t)cg.dims[a];
     }
-    if (nr > 0xFFFFFFF0ull) {
-        set_error("at most 2^32 - 16 reference points");
+    if (nr > 0xFFFFFFF0ull || nq > 0xFFFFFFF0ull) {
+        set_error("at most 2^32 - 16 points per set");
         return DBTSDF_ERR_OUT_OF_RANGE;
     }
-    DevBuf start, cursor, cell, sorted, sums;
+    CellGrid cg2 = cg;
+    cg2.h = kCoarse * h;
+    cg2.inv_h = 1.0 / cg2.h;
+    uint64_t n_cells2 = 1;
+    for (int a = 0; a < 3; ++a) {
+        cg2.dims[a] = (int)(std::floor(ext[a] / cg2.h) + 1.0);
+        n_cells2 *= (uint64_t)cg2.dims[a];
+    }
+    DevBuf start, qstart, cursor, cell, qcell, perm, sorted, sums, start2, sorted2;
     const uint64_t n_start = n_cells + 1;
     const uint64_t n_sums = (n_start + kScanItems - 1) / kScanItems;
     e = start.alloc(n_start * 4);
+    if (e == hipSuccess) e = qstart.alloc(n_start * 4);
     if (e == hipSuccess) e = cursor.alloc(n_cells * 4);
     if (e == hipSuccess) e = cell.alloc(nr * 4);
+    if (e == hipSuccess) e = qcell.alloc(nq * 4);
+    if (e == hipSuccess) e = perm.alloc(nq * 4);
     if (e == hipSuccess) e = sorted.alloc(nr * sizeof(float4));
     if (e == hipSuccess) e = sums.alloc(n_sums * 4);
+    if (e == hipSuccess) e = start2.alloc((n_cells2 + 1) * 4);
+    if (e == hipSuccess) e = sorted2.alloc(nr * sizeof(float4));
     if (e != hipSuccess) return check_hip(e, "allocating the cell grid");
-    e = launch_fill_u32(start.as<uint32_t>(), 0u, n_start, st);
-    if (e == hipSuccess) e = launch_fill_u32(cursor.as<uint32_t>(), 0u, n_cells, st);
+    // counts of the points of p per cell of g into cnt (n_c + 1 words), then their exclusive prefix
+    auto bucket = [&](const CellGrid &g, uint64_t n_c, const float *p, uint64_t n, uint32_t *cnt, uint32_t *cl) {
+        const uint64_t ns = (n_c + 1 + kScanItems - 1) / kScanItems;
+        hipError_t r = launch_fill_u32(cnt, 0u, n_c + 1, st);
+        if (r == hipSuccess) r = launch_fill_u32(cursor.as<uint32_t>(), 0u, n_c, st);
+        if (r != hipSuccess) return r;
+        k_cell_count<<<(unsigned)((n + kMetThreads - 1) / kMetThreads), kMetThreads, 0, st>>>(g, p, n, cnt, cl);
+        k_scan_local<<<(unsigned)ns, kMetThreads, 0, st>>>(cnt, n_c + 1, sums.as<uint32_t>());
+        k_scan_sums<<<1, kMetThreads, 0, st>>>(sums.as<uint32_t>(), (uint32_t)ns);
+        k_scan_add<<<(unsigned)ns, kMetThreads, 0, st>>>(cnt, n_c + 1, sums.as<uint32_t>());
+        return hipGetLastError();
+    };
+    const unsigned gr = (unsigned)((nr + kMetThreads - 1) / kMetThreads);
+    const unsigned gq = (unsigned)((nq + kMetThreads - 1) / kMetThreads);
+    e = bucket(cg, n_cells, rp, nr, start.as<uint32_t>(), cell.as<uint32_t>());
     if (e == hipSuccess) {
-        k_cell_count<<<(unsigned)((nr + kMetThreads - 1) / kMetThreads), kMetThreads, 0, st>>>(
-            cg, rp, nr, start.as<uint32_t>(), cell.as<uint32_t>());
-        k_scan_local<<<(unsigned)n_sums, kMetThreads, 0, st>>>(start.as<uint32_t>(), n_start, sums.as<uint32_t>());
-        k_scan_sums<<<1, kMetThreads, 0, st>>>(sums.as<uint32_t>(), (uint32_t)n_sums);
-        k_scan_add<<<(unsigned)n_sums, kMetThreads, 0, st>>>(start.as<uint32_t>(), n_start, sums.as<uint32_t>());
-        k_cell_fill<<<(unsigned)((nr + kMetThreads - 1) / kMetThreads), kMetThreads, 0, st>>>(
-            rp, nr, cell.as<uint32_t>(), start.as<uint32_t>(), cursor.as<uint32_t>(), sorted.as<float4>());
-        k_nearest<<<(unsigned)((nq + kMetThreads - 1) / kMetThreads), kMetThreads, 0, st>>>(
-            cg, qp, nq, start.as<uint32_t>(), sorted.as<float4>(), (uint32_t)nr, d2);
+        k_cell_fill<<<gr, kMetThreads, 0, st>>>(rp, nr, cell.as<uint32_t>(), start.as<uint32_t>(),
+                                                cursor.as<uint32_t>(), sorted.as<float4>());
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = bucket(cg2, n_cells2, rp, nr, start2.as<uint32_t>(), cell.as<uint32_t>());
+    if (e == hipSuccess) {
+        k_cell_fill<<<gr, kMetThreads, 0, st>>>(rp, nr, cell.as<uint32_t>(), start2.as<uint32_t>(),
+                                                cursor.as<uint32_t>(), sorted2.as<float4>());
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = bucket(cg, n_cells, qp, nq, qstart.as<uint32_t>(), qcell.as<uint32_t>());
+    if (e == hipSuccess) {
+        k_query_fill<<<gq, kMetThreads, 0, st>>>(nq, qcell.as<uint32_t>(), qstart.as<uint32_t>(),
+                                                 cursor.as<uint32_t>(), perm.as<uint32_t>());
+        k_nearest<<<gq, kMetThreads, 0, st>>>(cg, cg2, qp, nq, perm.as<uint32_t>(), start.as<uint32_t>(),
+                                              sorted.as<float4>(), start2.as<uint32_t>(), sorted2.as<float4>(), d2);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -440,9 +508,8 @@ extern "C" dbtsdf_status dbtsdf_surface_metrics(int device, const float *pred_de
     e = dp.alloc(n_pred * sizeof(double));
     if (e == hipSuccess) e = dgt.alloc(n_gt * sizeof(double));
     if (e != hipSuccess) return check_hip(e, "allocating the distances");
-    const double hint = tolerance > 0.0 ? tolerance : 0.0;
-    dbtsdf_status s = nearest_sq(pred_dev, n_pred, gt_dev, n_gt, dp.as<double>(), hint, nullptr);
-    if (s == DBTSDF_OK) s = nearest_sq(gt_dev, n_gt, pred_dev, n_pred, dgt.as<double>(), hint, nullptr);
+    dbtsdf_status s = nearest_sq(pred_dev, n_pred, gt_dev, n_gt, dp.as<double>(), 0.0, nullptr);
+    if (s == DBTSDF_OK) s = nearest_sq(gt_dev, n_gt, pred_dev, n_pred, dgt.as<double>(), 0.0, nullptr);
     if (s != DBTSDF_OK) return s;
     const double t2 = tolerance * tolerance;
     double sp = 0.0, sg = 0.0;

@@ -350,3 +350,83 @@ def resolution_grid(s: float) -> dict:
     centre = np.array(base["origin"], np.float64) + ext / 2.0
     origin = (centre - np.array(dims, np.float64) * np.float32(s) / 2.0).astype(np.float32)
     return dict(dims=dims, voxel_size=float(np.float32(s)), origin=tuple(float(v) for v in origin))
+
+
+# ----------------------------------------------------------------------------
+# the served form's scan streams, generated on the GPU (torch)
+# ----------------------------------------------------------------------------
+def _cast_rays_torch(torch, scene: Scene, origins, dirs):
+    """``cast_rays`` for a batch on the GPU: origins (S, 3), unit dirs (S, R, 3), fp64; distance (S, R)."""
+    o = origins[:, None, :]
+    tiny = 1e-12
+    ds = torch.where(dirs.abs() < tiny, torch.where(dirs < 0, torch.full_like(dirs, -tiny),
+                                                     torch.full_like(dirs, tiny)), dirs)
+    inv = 1.0 / ds
+    lo = torch.tensor(scene.room_lo, dtype=dirs.dtype, device=dirs.device)
+    hi = torch.tensor(scene.room_hi, dtype=dirs.dtype, device=dirs.device)
+    bound = torch.where(ds > 0, hi, lo)
+    t = ((bound - o) * inv).amin(dim=-1)
+    for b in scene.boxes:
+        blo = torch.tensor([b[0], b[2], b[4]], dtype=dirs.dtype, device=dirs.device)
+        bhi = torch.tensor([b[1], b[3], b[5]], dtype=dirs.dtype, device=dirs.device)
+        t1 = (blo - o) * inv
+        t2 = (bhi - o) * inv
+        tn = torch.minimum(t1, t2).amax(dim=-1)
+        tf = torch.maximum(t1, t2).amin(dim=-1)
+        hit = (tn <= tf) & (tn > 0) & (tn < t)
+        t = torch.where(hit, tn, t)
+    for cx, cy, r, h in scene.cylinders:
+        ox, oy, oz = o[..., 0] - cx, o[..., 1] - cy, o[..., 2]
+        dx, dy, dz = dirs[..., 0], dirs[..., 1], dirs[..., 2]
+        a = dx * dx + dy * dy
+        bq = 2.0 * (ox * dx + oy * dy)
+        c = ox * ox + oy * oy - r * r
+        disc = bq * bq - 4.0 * a * c
+        ok = (a > 1e-18) & (disc >= 0)
+        sq = torch.sqrt(torch.where(ok, disc, torch.zeros_like(disc)))
+        t0 = torch.where(ok, (-bq - sq) / torch.where(ok, 2.0 * a, torch.ones_like(a)),
+                         torch.full_like(a, float("inf")))
+        z0 = oz + t0 * dz
+        side = ok & (t0 > 0) & (z0 >= 0) & (z0 <= h) & (t0 < t)
+        t = torch.where(side, t0, t)
+        tc = (h - oz) * inv[..., 2]
+        xc = ox + tc * dx
+        yc = oy + tc * dy
+        cap = (tc > 0) & (xc * xc + yc * yc <= r * r) & (tc < t)
+        t = torch.where(cap, tc, t)
+    return t
+
+
+def served_scans(map_id: int, n_scans: int, torch, device="cuda", seed_stream: int = 7):
+    """Robot ``map_id``'s stream for the served form: ``n_scans`` distinct scans along its own trajectory
+    in its own room (the fifth configuration's rooms, sensors and 10 Hz trajectory sampling), ray cast on
+    the GPU in fp64 with Gaussian range noise from a seeded device generator. Returns
+    ``[(pose_f32[4,4] numpy, points_f32[N,3] CUDA tensor in the sensor frame)]`` in scan order."""
+    poses = config_poses(5, map_id, n_scans)
+    room_w, room_h, _ = _room_and_sensor(5, map_id, 0)
+    scene = make_scene(_rng(5, map_id, _S_SCENE), room_w=room_w, room_h=room_h, path_xy=poses[:, :2, 3])
+    sensors = [_room_and_sensor(5, map_id, k)[2] for k in range(n_scans)]
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(_rng(5, map_id, seed_stream).integers(0, 2 ** 62)))
+    out = [None] * n_scans
+    by_rows = {}
+    for k, s in enumerate(sensors):
+        by_rows.setdefault(s.rows, []).append(k)
+    for rows in sorted(by_rows):
+        ks = by_rows[rows]
+        sensor = sensors[ks[0]]
+        dirs_s = torch.from_numpy(sensor_directions(sensor)).to(device)                 # (R, 3)
+        for c0 in range(0, len(ks), 64):
+            idx = ks[c0:c0 + 64]
+            P = torch.from_numpy(poses[idx]).to(device)                                  # (S, 4, 4)
+            rot_t = P[:, :3, :3].transpose(1, 2).contiguous()
+            dirs_w = torch.matmul(dirs_s[None, :, :].expand(len(idx), -1, -1).contiguous(), rot_t)
+            t = _cast_rays_torch(torch, scene, P[:, :3, 3].contiguous(), dirs_w)
+            noise = torch.randn(t.shape, generator=gen, device=device, dtype=torch.float64) * sensor.sigma
+            keep = torch.isfinite(t) & (t <= sensor.max_range)
+            rng_m = t + noise
+            for j, k in enumerate(idx):
+                kk = keep[j]
+                pts = (dirs_s[kk] * rng_m[j][kk][:, None]).to(torch.float32).contiguous()
+                out[k] = (poses[k].astype(np.float32), pts)
+    return out

@@ -107,8 +107,12 @@ def test_metrics_of_fused_map_chain(db):
     sets = {
         "mesh": (db.mesh_vertices(g.extract_mesh()), omesh.extract_mesh(m, p, origin, vs).reshape(-1, 3)),
         "points": (g.extract_points(), omesh.occupied_points(m, p, origin, vs)),
+        "centroids": (db.mesh_centroids(g.extract_mesh()), None),
     }
     res = {}
+    rt = omesh.extract_mesh(m, p, origin, vs).reshape(-1, 3, 3)
+    rt = rt.astype(np.float64)
+    sets["centroids"] = (sets["centroids"][0], ((rt[:, 0] + rt[:, 1] + rt[:, 2]) / 3.0).astype(np.float32))
     for name, (pred_dev, pred_ref) in sets.items():
         got = db.surface_metrics(pred_dev, gt_dev, 0.2)
         ref = om.surface_metrics(pred_ref, gt, 0.2)
