@@ -1704,10 +1704,9 @@ __global__ __launch_bounds__(kSelThreads) void k_select_fill(PipeArgs a, const C
 //      phase), and, where the row lies in the shadow ball, adds the row's
 //      hits (bits of the bin's shadow row) with one 64-bit add per 8-word
 //      pair of count words;
-//   3. the round is merged, four 16-byte quads per thread: right after the
-//      rows, the stamps and counts go to registers and the loads of the words
-//      they touch are issued; the stores follow after the next round's rows
-//      (or the next item's): mask &= the stamp (stored when changed); h =
+//   3. the round is merged, four 16-byte quads per thread: the stamps and
+//      counts go to registers, the loads of the words they touch are issued
+//      together, then (one wait) mask &= the stamp (stored when changed); h =
 //      min(h + c, H_max) with the sign cleared on the crossing h < T <= h + c
 //      (eqs. 5-6 for c unit steps). A tile of several rounds merges each in
 //      turn (AND is idempotent and c then d steps are c + d steps).
@@ -1734,12 +1733,11 @@ __device__ __forceinline__ uint32_t spread4(uint32_t b4) {   // bit j -> byte j
     return (b4 * 0x00204081u) & 0x01010101u;
 }
 
-__global__ __launch_bounds__(kTileThreads, 3) void k_apply_tile(PipeArgs a) {
+__global__ __launch_bounds__(kTileThreads, 4) void k_apply_tile(PipeArgs a) {
     __shared__ __align__(16) uint2 stamp[kTileSlots];      // 4 x 16-bit masks per quad
     __shared__ __align__(16) uint32_t cnt[kCntSlots];      // 4 x 8-bit hit counts per word of counts
-    // masks by (phase, window row, quad); rows padded to 5 quads (40 bytes:
-    // lanes on consecutive window rows fall in different banks)
-    __shared__ __align__(16) unsigned long long mt[4][kMtRows][5];
+    // masks by (phase, window row, quad)
+    __shared__ __align__(16) unsigned long long mt[4][kMtRows][4];
     __shared__ uint8_t smask[kRowBins * kShadowRows];               // shadow x bits (dx + 3) per (bin, dy, dz)
     // per entry with rows, in round order: box and point (tile-local), row
     // magic and bin, first row
@@ -1806,15 +1804,13 @@ __global__ __launch_bounds__(kTileThreads, 3) void k_apply_tile(PipeArgs a) {
     // the grid of the last item (loaded again only when it changes)
     uint32_t cur_gi = 0u;
     DevGrid g = uniform_grid(a.grids[0]);
-    // The merge of a round is split: right after its rows, each thread takes
-    // the stamps and counts of its quads into registers and issues the loads
-    // of the words they touch (issue); the stores follow after the next
-    // round's set-up and rows (finish), so that the loads' latency is spent
-    // on that work.
+    // The merge of a round: each thread takes the stamps and counts of its
+    // quads into registers and issues the loads of the words they touch
+    // (issue), then updates and stores them (finish). Other workgroups on the
+    // CU cover the loads' latency.
     uint2 sq[kTileQuadsPerThread];
     uint32_t cq[kTileQuadsPerThread];
     u32x4 om[kTileQuadsPerThread], op[kTileQuadsPerThread];
-    bool pend = false;
     // A thread's quads: x 4 (tid mod 8), y (tid / 8) mod 16 and z tid / 128
     // + kQz k for its k-th; the same in every tile.
     constexpr uint32_t kQz = kTileThreads / (kTileQx * kTileY);
@@ -1823,8 +1819,8 @@ __global__ __launch_bounds__(kTileThreads, 3) void k_apply_tile(PipeArgs a) {
                    q_z = threadIdx.x / (kTileQx * kTileY);
     const uint32_t s_off = q_x / 4u + kTilePq * q_y + kTileLayer * q_z;   // stamp slot of quad 0 (+ kTileLayer kQz k)
     const uint32_t c_off = q_x / 4u + kCntPitch * q_y + kCntLayer * q_z;  // count slot of quad 0 (+ kCntLayer kQz k)
-    // the pending merge: grid, first word, word step between quads, the
-    // quad's cells and which quads lie inside the grid with 16-byte aligned rows
+    // the merge: grid, first word, word step between quads, the quad's cells
+    // and which quads lie inside the grid with 16-byte aligned rows
     DevGrid pg = g;
     size_t plin = 0, pstep = 0;
     uint32_t pgx = 0, pgy = 0, pgz = 0;
@@ -1847,10 +1843,8 @@ __global__ __launch_bounds__(kTileThreads, 3) void k_apply_tile(PipeArgs a) {
                 if (cq[k] != 0u) op[k] = *reinterpret_cast<const gu32x4 *>(glob(gi.packed) + lin);
             }
         }
-        pend = true;
     };
     auto finish = [&]() {
-        pend = false;
         // All the loaded words taken into registers first: one wait for the
         // loads, issued a round ago. (Vector stores count against the same
         // counter, so a wait between this thread's stores would also wait
@@ -1986,29 +1980,12 @@ __global__ __launch_bounds__(kTileThreads, 3) void k_apply_tile(PipeArgs a) {
             // The rows, 64 to a wavefront. A lane's entry is the last one
             // starting at or before its row: block c's entries before it plus
             // the start bits up to the lane (block 0 starts with entry 0; a
-            // later block has a nonzero base). The look-ups run ahead of the
-            // rows: the start bits and base two blocks ahead, the entry one.
-            auto entry_of = [&](unsigned long long seg, uint32_t bb) {
-                return bb + (uint32_t)__popcll(seg & ((2ull << l) - 1ull)) - 1u;
-            };
-            uint32_t c = w;
-            uint4 in_next = make_uint4(0u, 0u, 0u, 0u);
-            unsigned long long seg2 = 0ull;
-            uint32_t bb2 = 0u;
-            if (c < n_blocks) in_next = info[entry_of(starts[c], block_base[c])];
-            if (c + kWaves < n_blocks) {
-                seg2 = starts[c + kWaves];
-                bb2 = block_base[c + kWaves];
-            }
-            for (; c < n_blocks; c += kWaves) {
-                const uint4 in = in_next;
-                if (c + kWaves < n_blocks) in_next = info[entry_of(seg2, bb2)];
-                if (c + 2u * kWaves < n_blocks) {
-                    seg2 = starts[c + 2u * kWaves];
-                    bb2 = block_base[c + 2u * kWaves];
-                }
+            // later block has a nonzero base).
+            for (uint32_t c = w; c < n_blocks; c += kWaves) {
                 const uint32_t rho = 64u * c + l;
                 if (rho >= n_rows) continue;
+                const unsigned long long seg = starts[c];
+                const uint4 in = info[block_base[c] + (uint32_t)__popcll(seg & ((2ull << l) - 1ull)) - 1u];
                 const uint32_t rr = rho - in.z;
                 const int ya = (int)(in.x & 15u), za = (int)((in.x >> 4) & 15u), wy = (int)((in.x >> 8) & 15u);
                 const int lx = (int)((in.x >> 12) & 63u) - 16, ly = (int)((in.x >> 18) & 63u) - 16,
@@ -2061,18 +2038,16 @@ __global__ __launch_bounds__(kTileThreads, 3) void k_apply_tile(PipeArgs a) {
             ent_cur = pe;
             asm volatile("" : "+v"(ent_cur.x), "+v"(ent_cur.y), "+v"(ent_cur.z), "+v"(ent_cur.w), "+v"(wk_nn.x),
                               "+v"(wk_nn.y), "+v"(wk_nn.z), "+v"(wk_nn.w));
-            // the previous round's merge: its plane loads have had this
-            // round's set-up and rows to land. A thread merges the same quads
-            // of a tile in every round, so the next round of the same tile
-            // loads what this thread stored (program order).
-            if (pend) finish();
+            // the round's merge (a thread merges the same quads of a tile in
+            // every round, so the next round of the same tile loads what this
+            // thread stored: program order)
             issue(X0, Y0, Z0, g);
+            finish();
         }
         wi += G;
         wk = wk_next;
         wk_next = wk_nn;
     }
-    if (pend) finish();
 }
 
 // ========================================================== mesh export ===
