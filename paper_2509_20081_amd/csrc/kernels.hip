@@ -1583,9 +1583,9 @@ __global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const C
 
 // Survivor test, statistics and list fill of the tile strategy (one thread
 // per return). Only the slot's winner releases a dedup slot (as in
-// k_select_atomic). The last workgroup writes the statistics into the ring
-// slot; workgroup 0 clears the work-item counter the next call's front pass
-// counts on (every reader of it, the offsets pass, is done).
+// k_select_atomic). The apply pass writes the statistics into the ring slot;
+// workgroup 0 clears the work-item counter the next call's front pass counts
+// on (every reader of it, the offsets pass, is done).
 __global__ __launch_bounds__(kSelThreads) void k_select_fill(PipeArgs a, const CallInfo *info) {
     __shared__ uint32_t s_red[SC_N][kSelThreads / 64];
     const uint32_t n = info->n_points;
@@ -1662,25 +1662,10 @@ __global__ __launch_bounds__(kSelThreads) void k_select_fill(PipeArgs a, const C
             for (int f = 0; f < SC_N; ++f) wave_add(a.scan_ctr, s, (uint32_t)f, c[f]);
         }
     }
-    // the statistics out, by the last workgroup to finish (as k_select_atomic)
-    __shared__ uint32_t s_last;
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
-    if (threadIdx.x == 0)
-        s_last = __hip_atomic_fetch_add(&a.ctrl->select_done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
-                         gridDim.x - 1u
-                     ? 1u
-                     : 0u;
-    __syncthreads();
-    if (s_last) {
-        const uint32_t n_s = info->n_scans * SC_N, n_t = info->n_grids * TC_N;
-        for (uint32_t i = threadIdx.x; i < n_s + n_t; i += blockDim.x) {
-            unsigned long long *src = i < n_s ? &a.scan_ctr[i] : &a.traffic_ctr[i - n_s];
-            a.host_ctr[i < n_s ? (size_t)i : (size_t)a.scans_cap * SC_N + (i - n_s)] =
-                __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");  // system scope: the host reads them
-    }
+    // The statistics go out from the apply pass (its workgroup 0), which the
+    // stream starts after this pass has finished: a last-workgroup count here
+    // would put one returning atomic per workgroup on one address, and those
+    // queue behind each other at the coherence point.
 }
 
 // One workgroup per tile work item (persistent: items dealt round-robin over
@@ -1733,7 +1718,20 @@ __device__ __forceinline__ uint32_t spread4(uint32_t b4) {   // bit j -> byte j
     return (b4 * 0x00204081u) & 0x01010101u;
 }
 
+// The call's statistics into the ring slot's pinned host buffer (the counters
+// are complete: the passes that count have finished).
+__device__ void stats_out(const PipeArgs &a, const CallInfo *info) {
+    const uint32_t n_s = info->n_scans * SC_N, n_t = info->n_grids * TC_N;
+    for (uint32_t i = threadIdx.x; i < n_s + n_t; i += blockDim.x) {
+        unsigned long long *src = i < n_s ? &a.scan_ctr[i] : &a.traffic_ctr[i - n_s];
+        a.host_ctr[i < n_s ? (size_t)i : (size_t)a.scans_cap * SC_N + (i - n_s)] =
+            __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");  // system scope: the host reads them
+}
+
 __global__ __launch_bounds__(kTileThreads, 4) void k_apply_tile(PipeArgs a) {
+    if (blockIdx.x == 0) stats_out(a, reinterpret_cast<const CallInfo *>(a.ctrl + 1));
     __shared__ __align__(16) uint2 stamp[kTileSlots];      // 4 x 16-bit masks per quad
     __shared__ __align__(16) uint32_t cnt[kCntSlots];      // 4 x 8-bit hit counts per word of counts
     // masks by (phase, window row, quad)
