@@ -226,6 +226,8 @@ bool tuning_supported(const Tuning &t, int K);
 
 // Kernel launchers (kernels.hip). Return hipSuccess or the first launch error.
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t st);
+// the call's statistics into its ring slot (for apply passes that do not write them)
+hipError_t launch_stats_out(const PipeArgs &a, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, uint64_t n, hipStream_t st);
 hipError_t launch_grid_init(uint32_t *mask, uint32_t *packed, uint64_t n, hipStream_t st);
 // The pass sequence of one call: all of it, or the passes before the apply,

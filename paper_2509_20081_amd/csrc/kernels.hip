@@ -11,11 +11,11 @@
 //              first-return-per-voxel rule (Sec. IV-B) by an atomicMin of the
 //              point index into a hash table keyed by (scan, voxel)
 //   then one of two strategies, with identical results:
-//   per point (default; a one-scan call folds k_upload and k_reset into
-//   k_front, and k_download into k_select_atomic: three passes in all)
+//   per point (a one-scan call folds k_upload and k_reset into k_front, and
+//   k_download into the apply pass: three passes in all)
 //     k_select_atomic  survivor test, compacted survivor records, per-scan
-//                      statistics, release of the hash slots; its last
-//                      workgroup writes the statistics into the ring slot
+//                      statistics, release of the hash slots (the apply
+//                      pass's workgroup 0 writes the statistics out)
 //     k_apply_points   one wavefront per survivor: the K^3 window in aligned
 //                      16-byte rows, eq. 4 by read-first atomicAnd, eqs. 5-6
 //                      by guard-bit counter atomics (k_apply_atomic: any K)
@@ -1130,6 +1130,22 @@ __global__ __launch_bounds__(THREADS) void k_apply_brick(PipeArgs a) {
     }
 }
 
+// The call's statistics into the ring slot's pinned host buffer, by
+// workgroup 0 of the apply pass: the counting passes have finished (stream
+// order), and their counters are touched only by device-scope atomics. (A
+// last-workgroup count in the counting pass instead would put one returning
+// atomic per workgroup on one address, and those queue behind each other at
+// the coherence point: 50-60 us for 1024 workgroups.)
+__device__ void stats_out(const PipeArgs &a, const CallInfo *info) {
+    const uint32_t n_s = info->n_scans * SC_N, n_t = info->n_grids * TC_N;
+    for (uint32_t i = threadIdx.x; i < n_s + n_t; i += blockDim.x) {
+        unsigned long long *src = i < n_s ? &a.scan_ctr[i] : &a.traffic_ctr[i - n_s];
+        a.host_ctr[i < n_s ? (size_t)i : (size_t)a.scans_cap * SC_N + (i - n_s)] =
+            __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");  // system scope: the host reads them
+}
+
 // ------------------------------------------------------ atomic strategy ---
 // Per-point strategy, one pass per point before the apply: survivor test,
 // compaction of the survivors into a list, the per-scan statistics, and the
@@ -1220,33 +1236,8 @@ __global__ __launch_bounds__(kSelThreads) void k_select_atomic(PipeArgs a, const
         }
         __syncthreads();  // s_red and s_base are reused by the next round
     }
-    // The pass that copies the statistics out is folded in here: they are
-    // final once every workgroup's counter atomics are done (the apply does
-    // not touch them), so the last workgroup to finish writes them into the
-    // ring slot's pinned host buffer.
-    // Counters are touched only by device-scope atomics, performed at one
-    // coherence point; a wave's atomics are acknowledged once its vector
-    // memory count drains, so after the drain and the barrier the workgroup's
-    // updates are all in place before it counts itself done. (A device-scope
-    // fence here would write back and invalidate the XCD's L2 in every wave.)
-    __shared__ uint32_t s_last;
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
-    if (threadIdx.x == 0)
-        s_last = __hip_atomic_fetch_add(&a.ctrl->select_done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
-                         gridDim.x - 1u
-                     ? 1u
-                     : 0u;
-    __syncthreads();
-    if (s_last) {
-        const uint32_t n_s = info->n_scans * SC_N, n_t = info->n_grids * TC_N;
-        for (uint32_t i = threadIdx.x; i < n_s + n_t; i += blockDim.x) {
-            unsigned long long *src = i < n_s ? &a.scan_ctr[i] : &a.traffic_ctr[i - n_s];
-            a.host_ctr[i < n_s ? (size_t)i : (size_t)a.scans_cap * SC_N + (i - n_s)] =
-                __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");  // system scope: the host reads them
-    }
+    // The statistics go out from the apply pass (its workgroup 0), which
+    // starts after this pass has finished (see stats_out).
 }
 
 // One wavefront per surviving point, straight into HBM (any kernel size,
@@ -1261,6 +1252,7 @@ constexpr int kShadowBatch = 4;
 constexpr uint32_t kXcds = 8;           // accelerator complex dies of the MI355X
 
 __global__ __launch_bounds__(kPtThreads) void k_apply_atomic(PipeArgs a, const CallInfo *info) {
+    if (blockIdx.x == 0) stats_out(a, info);
     __shared__ uint32_t lut[kLutMax];
     const DevTables &t = a.tab;
     for (uint32_t q = threadIdx.x; q < t.n_q; q += blockDim.x) lut[q] = t.mask_by_q[q];
@@ -1365,6 +1357,7 @@ constexpr uint32_t kImgCopies = (kImgQuads + kPtThreads - 1) / kPtThreads;
 // ONE: the call holds a single scan (every point in grid 0)
 template <bool ONE>
 __global__ __launch_bounds__(kPtThreads) void k_apply_points(PipeArgs a, const CallInfo *info) {
+    if (blockIdx.x == 0) stats_out(a, info);
     // the kernel set's tables (layout in internal.h), copied in whole: every
     // thread's 16-byte loads are in flight together
     __shared__ uint4 s_img[kImgQuads];
@@ -1716,18 +1709,6 @@ static_assert(kTileRound < kTileThreads, "one entry per thread in the set-up");
 
 __device__ __forceinline__ uint32_t spread4(uint32_t b4) {   // bit j -> byte j
     return (b4 * 0x00204081u) & 0x01010101u;
-}
-
-// The call's statistics into the ring slot's pinned host buffer (the counters
-// are complete: the passes that count have finished).
-__device__ void stats_out(const PipeArgs &a, const CallInfo *info) {
-    const uint32_t n_s = info->n_scans * SC_N, n_t = info->n_grids * TC_N;
-    for (uint32_t i = threadIdx.x; i < n_s + n_t; i += blockDim.x) {
-        unsigned long long *src = i < n_s ? &a.scan_ctr[i] : &a.traffic_ctr[i - n_s];
-        a.host_ctr[i < n_s ? (size_t)i : (size_t)a.scans_cap * SC_N + (i - n_s)] =
-            __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");  // system scope: the host reads them
 }
 
 __global__ __launch_bounds__(kTileThreads, 4) void k_apply_tile(PipeArgs a) {
@@ -2369,6 +2350,13 @@ static uint32_t blocks_for(uint64_t n, uint32_t threads, uint32_t cap) {
     return (uint32_t)(b > cap ? cap : b);
 }
 
+__global__ __launch_bounds__(256) void k_stats_out(PipeArgs a) {
+    stats_out(a, reinterpret_cast<const CallInfo *>(a.ctrl + 1));
+}
+hipError_t launch_stats_out(const PipeArgs &a, hipStream_t st) {
+    k_stats_out<<<1, 256, 0, st>>>(a);
+    return hipGetLastError();
+}
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t st) {
     if (!n) return hipSuccess;
     k_fill_u32<<<blocks_for(n, 256, 8192), 256, 0, st>>>(p, v, n);

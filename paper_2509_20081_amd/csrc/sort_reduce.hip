@@ -384,7 +384,9 @@ void free_sort_buffers(SortBuffers &b) {
 hipError_t sort_apply(Workspace &ws, const PipeArgs &a, const SortPlan &plan, hipStream_t st) {
     SortBuffers &b = ws.sorter;
     uint32_t n_surv = 0;
-    hipError_t e = hipMemcpyAsync(&n_surv, &a.ctrl->n_survivors, sizeof(n_surv), hipMemcpyDeviceToHost, st);
+    // the select pass has counted everything: the statistics go out first
+    hipError_t e = launch_stats_out(a, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&n_surv, &a.ctrl->n_survivors, sizeof(n_surv), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess || n_surv == 0) return e;
     unsigned long long per_round = std::max(1ull, kSortMaxPairs / plan.pairs_per_point);
