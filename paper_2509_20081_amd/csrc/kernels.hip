@@ -479,7 +479,6 @@ __global__ __launch_bounds__(kPtThreads) void k_front(PipeArgs a, const CallInfo
     const uint32_t n = info->n_points, n_scans = info->n_scans;
     const int R = a.tab.R;
     const int rs = TILE ? shadow_extent(a.tab) : 0;
-    const uint32_t F = a.span[0] * a.span[1] * a.span[2];
     // block-uniform rounds (the tile claims synchronise the workgroup)
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
         const uint32_t i = base + threadIdx.x;
@@ -533,7 +532,8 @@ __global__ __launch_bounds__(kPtThreads) void k_front(PipeArgs a, const CallInfo
 #pragma unroll
                         for (int u = 0; u < kFrontUnroll; ++u) {
                             if (j0 + u >= np) continue;
-                            a.rank[(size_t)i * F + j0 + u] = rk[u];
+                            // list j's rank at j n + i (a wavefront's stores contiguous)
+                            a.rank[(size_t)(j0 + u) * n + i] = rk[u];
                             if (rk[u] == 0u) {
                                 ++n_open;
                                 opened |= 1ull << (j0 + u);
@@ -1584,7 +1584,6 @@ __global__ __launch_bounds__(kSelThreads) void k_select_fill(PipeArgs a, const C
     const uint32_t n = info->n_points;
     const int R = a.tab.R;
     const int rs = shadow_extent(a.tab);
-    const uint32_t F = a.span[0] * a.span[1] * a.span[2];
     if (blockIdx.x == 0 && threadIdx.x == 0) a.ctrl->n_active = 0u;
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
         const uint32_t i = base + threadIdx.x;
@@ -1619,7 +1618,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_fill(PipeArgs a, const C
                     for (int u = 0; u < kSelUnroll; ++u) {  // independent loads, all in flight
                         const bool v = j0 + u < np;
                         slot[u] = v ? glob(g.brick_slot)[tile_ctr(g, span_tile(sp, j0 + u, g))] : 0u;
-                        rk[u] = v ? a.rank[(size_t)i * F + j0 + u] : 0u;
+                        rk[u] = v ? a.rank[(size_t)(j0 + u) * n + i] : 0u;   // as the front pass stores them
                     }
 #pragma unroll
                     for (int u = 0; u < kSelUnroll; ++u)
