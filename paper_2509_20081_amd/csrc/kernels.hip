@@ -445,11 +445,25 @@ __device__ __forceinline__ uint32_t span_tile(const TileSpan &sp, uint32_t j, co
     return (sp.x0 + jx) + g.nbx * ((sp.y0 + jy) + g.nby * (sp.z0 + jz));
 }
 
+// The tile strategy's list counts, aggregated per workgroup: a table in LDS
+// keyed by (grid, tile counter) counts the workgroup's lists of each tile
+// (the add's old value is the list's rank within the workgroup), then one
+// global atomic per distinct tile reserves the workgroup's run of ranks.
+// Global atomics are the scarce resource (some 25 G/s over the whole device
+// for scattered addresses); a list whose key does not find a slot within the
+// probe limit, or whose grid index is 15 or more, takes its rank from the
+// global counter directly (every rank is still a distinct reservation).
+constexpr uint32_t kTileAggSlots = 2048;   // >= 2/3 of a workgroup's at most 256 x 12 lists
+constexpr uint32_t kTileAggProbes = 16;
+static_assert(kTileAggSlots == 1u << 11, "the slot hash takes the top 11 bits");
+
 template <bool ONE, bool TILE>
 __global__ __launch_bounds__(kPtThreads) void k_front(PipeArgs a, const CallInfo *info_dev) {
     __shared__ uint4 s_desc[ONE ? 1 + kGridPieces + kScanPieces : 1];
     __shared__ uint32_t s_tmp[kPtThreads / 64];
     __shared__ uint32_t s_base;
+    __shared__ uint32_t s_akey[TILE ? kTileAggSlots : 1];   // (grid << 28 | counter) + 1; 0: empty
+    __shared__ uint32_t s_acnt[TILE ? kTileAggSlots : 1];   // lists of the workgroup, then the reserved base
     const CallInfo *info = info_dev;
     const DevScan *scans = a.scans;
     const DevGrid *grids = a.grids;
@@ -482,9 +496,16 @@ __global__ __launch_bounds__(kPtThreads) void k_front(PipeArgs a, const CallInfo
     // block-uniform rounds (the tile claims synchronise the workgroup)
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
         const uint32_t i = base + threadIdx.x;
-        uint32_t n_open = 0, gi = 0;
+        uint32_t n_open = 0, gi = 0, np = 0;
         unsigned long long opened = 0;   // list j of the return opened its tile
         TileSpan sp{0u, 0u, 0u, 0u, 0u, 0u};
+        if constexpr (TILE) {
+            for (uint32_t q = threadIdx.x; q < kTileAggSlots; q += kPtThreads) {
+                s_akey[q] = 0u;
+                s_acnt[q] = 0u;
+            }
+            __syncthreads();
+        }
         if (i < n) {
             const uint32_t s = ONE ? 0u : find_scan(scans, n_scans, i);
             const DevScan &sc = scans[s];
@@ -523,27 +544,60 @@ __global__ __launch_bounds__(kPtThreads) void k_front(PipeArgs a, const CallInfo
                     const bool rv = a.revisit_ok && g.revisit_skip && glob(g.mask)[lin] == 0u;
                     if (rv) w |= kRecTileRevisit;
                     sp = tile_span((uint32_t)vx, (uint32_t)vy, (uint32_t)vz, rv ? rs : R);
-                    const uint32_t np = sp.nx * sp.ny * sp.nz;
-                    for (uint32_t j0 = 0; j0 < np; j0 += kFrontUnroll) {
-                        uint32_t rk[kFrontUnroll];
-#pragma unroll
-                        for (int u = 0; u < kFrontUnroll; ++u)
-                            rk[u] = j0 + u < np ? g_add(glob(g.brick_cnt) + tile_ctr(g, span_tile(sp, j0 + u, g)), 1u) : 1u;
-#pragma unroll
-                        for (int u = 0; u < kFrontUnroll; ++u) {
-                            if (j0 + u >= np) continue;
-                            // list j's rank at j n + i (a wavefront's stores contiguous)
-                            a.rank[(size_t)(j0 + u) * n + i] = rk[u];
-                            if (rk[u] == 0u) {
-                                ++n_open;
-                                opened |= 1ull << (j0 + u);
-                            }
-                        }
-                    }
+                    np = sp.nx * sp.ny * sp.nz;   // at most 2 x 2 x 3 for K <= 11
                 }
             }
             a.rec[i] = make_uint4((uint32_t)vx, (uint32_t)vy, (uint32_t)vz, w);
             a.pslot[i] = slot;
+        }
+        if constexpr (TILE) {
+            // each list: its slot in the workgroup's table and its rank among
+            // the workgroup's lists of the tile, or (no slot) its global rank
+            const DevGrid &g = grids[gi];
+            uint32_t ctr[kFrontUnroll], loc[kFrontUnroll];
+#pragma unroll
+            for (int u = 0; u < kFrontUnroll; ++u) {
+                ctr[u] = 0u;
+                loc[u] = 0u;
+                if ((uint32_t)u >= np) continue;
+                ctr[u] = tile_ctr(g, span_tile(sp, (uint32_t)u, g));
+                bool placed = false;
+                if (gi < 15u && ctr[u] < (1u << 28)) {
+                    const uint32_t key = ((gi << 28) | ctr[u]) + 1u;
+                    uint32_t h = (key * 0x9E3779B1u) >> (32 - 11);   // 11 bits: kTileAggSlots
+                    for (uint32_t p = 0; p < kTileAggProbes; ++p, h = (h + 1u) & (kTileAggSlots - 1u)) {
+                        const uint32_t prev = atomicCAS(&s_akey[h], 0u, key);
+                        if (prev == 0u || prev == key) {
+                            loc[u] = (h << 16) | atomicAdd(&s_acnt[h], 1u);   // at most 3072 lists: 12 bits
+                            placed = true;
+                            break;
+                        }
+                    }
+                }
+                if (!placed) loc[u] = 0x80000000u | g_add(glob(g.brick_cnt) + ctr[u], 1u);
+            }
+            __syncthreads();
+            // one global atomic per distinct tile of the workgroup
+            for (uint32_t q = threadIdx.x; q < kTileAggSlots; q += kPtThreads) {
+                const uint32_t key = s_akey[q];
+                if (key) {
+                    const uint32_t kk = key - 1u, kg = kk >> 28;
+                    s_acnt[q] = g_add(glob(grids[kg].brick_cnt) + (kk & 0x0FFFFFFFu), s_acnt[q]);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < kFrontUnroll; ++u) {
+                if ((uint32_t)u >= np) continue;
+                const uint32_t rk = (loc[u] & 0x80000000u) ? (loc[u] & 0x7FFFFFFFu)
+                                                           : s_acnt[loc[u] >> 16] + (loc[u] & 0xFFFFu);
+                // list j's rank at j n + i (a wavefront's stores contiguous)
+                a.rank[(size_t)u * n + i] = rk;
+                if (rk == 0u) {
+                    ++n_open;
+                    opened |= 1ull << u;
+                }
+            }
         }
         if constexpr (TILE) {
             uint32_t total;
