@@ -781,6 +781,8 @@ __global__ __launch_bounds__(kPtThreads) void k_stats(PipeArgs a, const CallInfo
 // its apply work units (bricks with more than `chunk` listed points are split).
 // Resets the brick counters for the next call.
 __global__ __launch_bounds__(kPtThreads) void k_offsets(PipeArgs a) {
+    __shared__ uint32_t s_tmp[kPtThreads / 64];
+    __shared__ uint32_t s_bases[2];
     const uint32_t n = a.ctrl->n_active;
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
         const uint32_t t = base + threadIdx.x;
@@ -792,18 +794,23 @@ __global__ __launch_bounds__(kPtThreads) void k_offsets(PipeArgs a) {
             cnt = *bc;
             *bc = 0u;
         }
-        const uint32_t incl = wave_incl_scan_u32(cnt);
-        uint32_t wbase = 0;
-        if (lane() == 63u) wbase = atomicAdd(&a.ctrl->total_entries, incl);
-        wbase = __shfl(wbase, 63, 64);
+        // entry and work-unit offsets: one scan and one atomic per counter
+        // per workgroup (same-address atomics queue at the coherence point)
         const uint32_t nsub = t < n ? (a.chunk ? (cnt + a.chunk - 1u) / a.chunk : 1u) : 0u;
-        const uint32_t sincl = wave_incl_scan_u32(nsub);
-        uint32_t sbase = 0;
-        if (lane() == 63u) sbase = atomicAdd(&a.ctrl->n_work, sincl);
-        sbase = __shfl(sbase, 63, 64);
+        uint32_t tot_e, tot_s;
+        const uint32_t ex = block_excl_scan<kPtThreads>(cnt, s_tmp, tot_e);
+        const uint32_t sex = block_excl_scan<kPtThreads>(nsub, s_tmp, tot_s);
+        if (threadIdx.x == 0) {
+            s_bases[0] = tot_e ? atomicAdd(&a.ctrl->total_entries, tot_e) : 0u;
+            s_bases[1] = tot_s ? atomicAdd(&a.ctrl->n_work, tot_s) : 0u;
+        }
+        __syncthreads();
+        const uint32_t wbase = s_bases[0], sbase = s_bases[1];
+        __syncthreads();   // s_bases is reused by the next round
         if (t < n) {
             const unsigned long long it = a.items[t];
-            const uint32_t first = wbase + incl - cnt;
+            const uint32_t first = wbase + ex;
+            const uint32_t sincl = sex + nsub;
             a.item_off[t] = first;
             a.item_cnt[t] = cnt;
             // the tile strategy's fill finds the list's first entry beside the counter
