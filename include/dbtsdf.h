@@ -464,8 +464,8 @@ typedef struct dbtsdf_metrics {
  * the caller. Runs on that device's null stream and synchronises it;
  * allocates scratch (a cell grid of the reference points) for the call.
  * Errors: INVALID_ARG (NULL pointer with a nonzero count, n_ref 0 with
- * queries, a non-finite coordinate), OUT_OF_RANGE (n_ref >= 2^32 - 16),
- * OUT_OF_MEMORY, DEVICE.
+ * queries, a non-finite coordinate), OUT_OF_RANGE (n_query or n_ref above
+ * 2^32 - 16), OUT_OF_MEMORY, DEVICE.
  */
 dbtsdf_status dbtsdf_nearest_sq(int device, const float *query_dev, uint64_t n_query, const float *ref_dev,
                                 uint64_t n_ref, double *d2_dev);
