@@ -1724,48 +1724,60 @@ __global__ __launch_bounds__(kSelThreads) void k_select_fill(PipeArgs a, const C
 // One workgroup per tile work item (persistent: items dealt round-robin over
 // the workgroups). LDS holds, per word of the tile, the eq. 3 stamp as a
 // 16-bit mask (2^n - 1; 0xFFFF where no window reaches, the identity of the
-// AND), four words to a 64-bit quad, rows of 8 quads padded to 9 and z layers
-// to 145 quads so that lanes on neighbouring rows fall in different banks;
-// and the shadow hit count as a byte, four to a 32-bit word (rows of 8 count
-// words padded to 10, layers to 162). The tile's list is taken in rounds of
-// at most 255 entries (a count byte cannot overflow: an entry adds at most one
-// hit to a word):
-//   1. stamps and counts cleared; one thread per entry: the rows it walks,
-//      clipped to the tile (the window's (y, z) rows for a return that
-//      applies its window, the shadow ball's for one whose voxel an earlier
-//      call integrated), and one scan of the row counts over the round, with
-//      a bitmap of the rows where an entry starts;
+// AND), four words to a 64-bit quad, and the shadow hit count as a byte, four
+// to a 32-bit word. Each LDS row carries halo cells on both sides of the
+// tile's 32 (written to, never merged, never cleared), wide enough for every
+// window and shadow row of a listed return, so that a row's writes need no
+// bounds test. The tile's list is taken in rounds of at most 255 entries (a
+// count byte cannot overflow: an entry adds at most one hit to a word):
+//   1. one thread per entry: the rows it walks, clipped to the tile in y and
+//      z (the window's (y, z) rows for a return that applies its window, the
+//      shadow ball's for one whose voxel an earlier call integrated), its
+//      first row's stamp quad and count word, and one scan of the row counts
+//      over the round, with a bitmap of the rows where an entry starts;
 //   2. the rows of all entries are dealt to the lanes, 64 consecutive rows a
 //      wavefront: a lane finds its entry by counting the starts below its row
-//      in the bitmap, ANDs its window row's masks in with one ds_and_b64 per
-//      quad (the masks of the row kernel's table for the window's alignment
-//      phase), and, where the row lies in the shadow ball, adds the row's
-//      hits (bits of the bin's shadow row) with one 64-bit add per 8-word
-//      pair of count words;
+//      in the bitmap, ANDs its window row's masks in with four ds_and_b64 (the
+//      masks of the row kernel's table for the window's alignment phase, by
+//      |dy| and |dz|: eq. 3 is even in both), and, where the row lies in the
+//      shadow ball, adds the row's hits (bits of the bin's shadow row) with
+//      two 64-bit adds, each on an 8-word pair of count words;
 //   3. the round is merged, four 16-byte quads per thread: the stamps and
-//      counts go to registers, the loads of the words they touch are issued
-//      together, then (one wait) mask &= the stamp (stored when changed); h =
-//      min(h + c, H_max) with the sign cleared on the crossing h < T <= h + c
-//      (eqs. 5-6 for c unit steps). A tile of several rounds merges each in
-//      turn (AND is idempotent and c then d steps are c + d steps).
+//      counts go to registers (their LDS words reset for the next round), the
+//      loads of the words they touch are issued together, then (one wait)
+//      mask &= the stamp (stored when changed); h = min(h + c, H_max) with the
+//      sign cleared on the crossing h < T <= h + c (eqs. 5-6 for c unit
+//      steps). A tile of several rounds merges each in turn (AND is idempotent
+//      and c then d steps are c + d steps).
 // Needs the row kernel's tables (K <= 11, at most 31 bins, r_s^2 <= 9).
 constexpr int kTileThreads = 256;
 constexpr uint32_t kTileRound = 255;                    // entries per round
 constexpr uint32_t kTileRows = kTileY * kTileZ;         // (y, z) rows of a tile
 constexpr uint32_t kTileQx = kTileX / 4;                // quads per row
-constexpr uint32_t kTilePq = kTileQx + 1;               // LDS row pitch in quads (odd: rows spread over banks)
-constexpr uint32_t kTileLayer = kTilePq * kTileY + 1;   // LDS z-layer pitch in quads (layers spread over banks)
+// A window row, cells lx - R .. lx + R with lx in [-R, 31 + R], takes the four
+// quads from (lx - R) >> 2, in [-3, 10]: LDS rows hold three halo quads on
+// either side of the tile's eight and are padded to 15 quads (odd: lanes on
+// neighbouring rows fall in different banks), z layers to 241 quads.
+constexpr uint32_t kHaloQ = 3;
+constexpr uint32_t kTilePq = kTileQx + 2 * kHaloQ + 1;
+constexpr uint32_t kTileLayer = kTilePq * kTileY + 1;
 constexpr uint32_t kTileSlots = kTileLayer * kTileZ;
-// the hit counts: a byte per word, rows of 8 count words padded to 10 (8-byte
-// pairs at an odd pitch), z layers to 162 words
-constexpr uint32_t kCntPitch = 10, kCntLayer = kCntPitch * kTileY + 2, kCntSlots = kCntLayer * kTileZ;
+// The hit counts: a shadow row, cells lx - 3 .. lx + 3, adds to the two 8-cell
+// pairs of count words from (lx - 3) >> 3, in [-1, 5]: rows hold one halo pair
+// before the tile's four and two after (14 words), z layers padded to 226.
+constexpr uint32_t kHaloC = 2;   // count words before the tile's first
+constexpr uint32_t kCntPitch = kTileQx + 3u * 2u, kCntLayer = kCntPitch * kTileY + 2, kCntSlots = kCntLayer * kTileZ;
 constexpr uint32_t kTileQuadsPerThread = kTileRows * kTileQx / kTileThreads;
 constexpr uint32_t kShadowRows = 49;                    // (dy, dz) in [-3, 3]^2
 constexpr uint32_t kRowsMax = kTileRound * 11u * kTileZ;   // rows of a round (windows of 11 rows, clipped z)
 constexpr uint32_t kRowBlocks = (kRowsMax + 63) / 64;
-constexpr uint32_t kMtRows = 11u * 11u;                 // window rows of K <= 11
+constexpr uint32_t kMtRows = 6u * 6u;                   // window rows by (|dy|, |dz|), K <= 11
 static_assert(kTileRows * kTileQx % kTileThreads == 0, "whole quads per thread");
 static_assert(kTileRound < kTileThreads, "one entry per thread in the set-up");
+static_assert(kTileLayer * (kTileZ - 1) + kTilePq * (kTileY - 1) + 2 * kHaloQ + kTileQx - 1 < kTileSlots &&
+                  kCntLayer * (kTileZ - 1) + kCntPitch * (kTileY - 1) + kCntPitch - 1 < kCntSlots &&
+                  kTileSlots < 2048 && kCntSlots < 2048, "row bases fit 11 bits");
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ uint32_t spread4(uint32_t b4) {   // bit j -> byte j
     return (b4 * 0x00204081u) & 0x01010101u;
@@ -1775,7 +1787,7 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_apply_tile(PipeArgs a) {
     if (blockIdx.x == 0) stats_out(a, reinterpret_cast<const CallInfo *>(a.ctrl + 1));
     __shared__ __align__(16) uint2 stamp[kTileSlots];      // 4 x 16-bit masks per quad
     __shared__ __align__(16) uint32_t cnt[kCntSlots];      // 4 x 8-bit hit counts per word of counts
-    // masks by (phase, window row, quad)
+    // masks by (phase, |dy| + 6 |dz|, quad)
     __shared__ __align__(16) unsigned long long mt[4][kMtRows][4];
     __shared__ uint8_t smask[kRowBins * kShadowRows];               // shadow x bits (dx + 3) per (bin, dy, dz)
     // per entry with rows, in round order: box and point (tile-local), row
@@ -1790,14 +1802,21 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_apply_tile(PipeArgs a) {
     const int R = t.R, K = t.K;
     const int rs = shadow_extent(t);
     {
-        // the row kernel's table mtab[sel][row] (sel = 4 qd + 3 - phase) laid
-        // out by (phase, row) so that a row's four quads are contiguous
+        // the row kernel's table mtab[sel][row] (sel = 4 qd + 3 - phase, row
+        // (dy + R) + K (dz + R)) for dy, dz >= 0, laid out by (phase, row) so
+        // that a row's four quads are contiguous
         const uint2 *mtab = reinterpret_cast<const uint2 *>(t.row_image) + kImgMtab / 2;
         for (uint32_t i = threadIdx.x; i < 4u * kMtRows * 4u; i += kTileThreads) {
             const uint32_t ph = i / (kMtRows * 4u), row = (i / 4u) % kMtRows, qd = i % 4u;
-            const uint2 m = (int)row < K * K ? mtab[(4u * qd + 3u - ph) * kRowPad + row] : make_uint2(~0u, ~0u);
+            const int ady = (int)(row % 6u), adz = (int)(row / 6u);
+            const uint2 m = ady <= R && adz <= R ? mtab[(4u * qd + 3u - ph) * kRowPad + (uint32_t)(ady + R + K * (adz + R))]
+                                                 : make_uint2(~0u, ~0u);
             mt[ph][row][qd] = (unsigned long long)m.x | ((unsigned long long)m.y << 32);
         }
+        // stamps and counts start at the identity; the merge resets the
+        // words it reads (the halo cells are never read)
+        for (uint32_t q = threadIdx.x; q < kTileSlots; q += kTileThreads) stamp[q] = make_uint2(~0u, ~0u);
+        for (uint32_t q = threadIdx.x; q < kCntSlots; q += kTileThreads) cnt[q] = 0u;
         // each bin's shadow set as 7-bit x rows, from its 343-bit set (bits
         // (dx + 3) + 7 (dy + 3) + 49 (dz + 3))
         const uint32_t *bits = reinterpret_cast<const uint32_t *>(t.row_image) + kImgShBits;
@@ -1856,8 +1875,8 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_apply_tile(PipeArgs a) {
     static_assert(kTileThreads % (kTileQx * kTileY) == 0 && kQz * kTileQuadsPerThread == kTileZ, "quads per thread");
     const uint32_t q_x = 4u * (threadIdx.x % kTileQx), q_y = (threadIdx.x / kTileQx) % kTileY,
                    q_z = threadIdx.x / (kTileQx * kTileY);
-    const uint32_t s_off = q_x / 4u + kTilePq * q_y + kTileLayer * q_z;   // stamp slot of quad 0 (+ kTileLayer kQz k)
-    const uint32_t c_off = q_x / 4u + kCntPitch * q_y + kCntLayer * q_z;  // count slot of quad 0 (+ kCntLayer kQz k)
+    const uint32_t s_off = kHaloQ + q_x / 4u + kTilePq * q_y + kTileLayer * q_z;   // stamp slot of quad 0 (+ kTileLayer kQz k)
+    const uint32_t c_off = kHaloC + q_x / 4u + kCntPitch * q_y + kCntLayer * q_z;  // count slot of quad 0 (+ kCntLayer kQz k)
     // the merge: grid, first word, word step between quads, the quad's cells
     // and which quads lie inside the grid with 16-byte aligned rows
     DevGrid pg = g;
@@ -1876,6 +1895,8 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_apply_tile(PipeArgs a) {
         for (uint32_t k = 0; k < kTileQuadsPerThread; ++k) {
             sq[k] = stamp[s_off + kTileLayer * kQz * k];
             cq[k] = cnt[c_off + kCntLayer * kQz * k];
+            stamp[s_off + kTileLayer * kQz * k] = make_uint2(~0u, ~0u);
+            cnt[c_off + kCntLayer * kQz * k] = 0u;
             if (pxy && pgz + kQz * k < gi.nz) {
                 const size_t lin = plin + (size_t)k * pstep;
                 if ((sq[k].x & sq[k].y) != ~0u) om[k] = *reinterpret_cast<const gu32x4 *>(glob(gi.mask) + lin);
@@ -1967,8 +1988,6 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_apply_tile(PipeArgs a) {
         for (uint32_t b0 = 0; b0 < total; b0 += kTileRound) {
             const uint32_t nb = min(total - b0, kTileRound);
             lds_barrier();   // the previous round's (or item's) merge is done with the arrays
-            for (uint32_t q = threadIdx.x; q < kTileSlots; q += kTileThreads) stamp[q] = make_uint2(~0u, ~0u);
-            for (uint32_t q = threadIdx.x; q < kCntSlots; q += kTileThreads) cnt[q] = 0u;
             const uint4 r = ent_cur;
             // the next round's entries: this item's next round, else the next item's first
             const bool more = b0 + kTileRound < total;
@@ -1989,11 +2008,19 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_apply_tile(PipeArgs a) {
                     const int wy = yb - ya + 1, wz = zb - za + 1;
                     if (wy > 0 && wz > 0 && lx + ext >= 0 && lx - ext < (int)kTileX) {
                         rows = (uint32_t)(wy * wz);
-                        const uint32_t magic = s_magic[wy];   // r / wy = (r * magic) >> 16 for r < 256
-                        inf = make_uint4((uint32_t)ya | ((uint32_t)za << 4) | ((uint32_t)wy << 8) |
-                                             ((uint32_t)(lx + 16) << 12) | ((uint32_t)(ly + 16) << 18) |
-                                             ((uint32_t)(lz + 16) << 24) | (rv ? 1u << 30 : 0u),
-                                         magic | (bin << 17), 0u, 0u);   // magic: up to 2^16, 17 bits
+                        // the first row's stamp quad (the window's quads from
+                        // (lx - R) >> 2) and count word (the shadow's pairs
+                        // from (lx - 3) >> 3), halo included; its (dy, dz)
+                        const int xs = lx - R, sx = lx - 3;
+                        const uint32_t qb = (uint32_t)((xs >> 2) + (int)kHaloQ) + kTilePq * (uint32_t)ya +
+                                            kTileLayer * (uint32_t)za;
+                        const uint32_t cb = (uint32_t)(2 * (sx >> 3) + (int)kHaloC) + kCntPitch * (uint32_t)ya +
+                                            kCntLayer * (uint32_t)za;
+                        inf = make_uint4(0u, s_magic[wy],   // r / wy = (r * magic) >> 16 for r < 256
+                                         qb | (cb << 11) | ((bin & 31u) << 22) | (rv ? 1u << 27 : 0u) |
+                                             ((uint32_t)(xs & 3) << 28),
+                                         (uint32_t)wy | ((uint32_t)(sx & 7) << 4) | ((uint32_t)(ya - ly + 8) << 8) |
+                                             ((uint32_t)(za - lz + 8) << 12));
                     }
                 }
             }
@@ -2005,7 +2032,7 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_apply_tile(PipeArgs a) {
             const uint32_t n_blocks = (n_rows + 63u) / 64u;
             if (rows) {
                 const uint32_t k_e = ex & 511u, r0 = ex >> 9;
-                inf.z = r0;
+                inf.x = r0;
                 info[k_e] = inf;
                 atomicOr(&starts[r0 >> 6], 1ull << (r0 & 63u));
                 // blocks whose first row lies after this entry's first row and
@@ -2025,49 +2052,37 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_apply_tile(PipeArgs a) {
                 if (rho >= n_rows) continue;
                 const unsigned long long seg = starts[c];
                 const uint4 in = info[block_base[c] + (uint32_t)__popcll(seg & ((2ull << l) - 1ull)) - 1u];
-                const uint32_t rr = rho - in.z;
-                const int ya = (int)(in.x & 15u), za = (int)((in.x >> 4) & 15u), wy = (int)((in.x >> 8) & 15u);
-                const int lx = (int)((in.x >> 12) & 63u) - 16, ly = (int)((in.x >> 18) & 63u) - 16,
-                          lz = (int)((in.x >> 24) & 63u) - 16;
-                const bool rv = (in.x >> 30) & 1u;
-                const int rz = (int)((rr * (in.y & 0x1FFFFu)) >> 16);
-                const int yy = ya + ((int)rr - rz * wy), zz = za + rz;
-                const int dy = yy - ly, dz = zz - lz;
-                const uint32_t rowq = kTilePq * (uint32_t)yy + kTileLayer * (uint32_t)zz;
-                const uint32_t crow = kCntPitch * (uint32_t)yy + kCntLayer * (uint32_t)zz;
-                if (!rv) {
-                    // the window row: cells lx - R .. lx + R in the quads from x0 = (lx - R) rounded down
-                    const int xs = lx - R;
-                    const int q0 = xs >> 2;
-                    const uint32_t tr = (uint32_t)(dy + R) + (uint32_t)K * (uint32_t)(dz + R);
-                    const unsigned long long *mrow = mt[xs & 3][tr];
-                    const unsigned long long mq[4] = {mrow[0], mrow[1], mrow[2], mrow[3]};
-#pragma unroll
-                    for (int qd = 0; qd < 4; ++qd) {
-                        const int qx = q0 + qd;
-                        if (qx >= 0 && qx < (int)kTileQx && 4 * qx <= lx + R)
-                            atomicAnd(reinterpret_cast<unsigned long long *>(&stamp[rowq + (uint32_t)qx]), mq[qd]);
-                    }
+                const uint32_t rr = rho - in.x;
+                const uint32_t rz = __umul24(rr, in.y) >> 16, ry = rr - __umul24(rz, in.w & 15u);   // rr < 256
+                const int dy = (int)((in.w >> 8) & 15u) - 8 + (int)ry, dz = (int)((in.w >> 12) & 15u) - 8 + (int)rz;
+                const uint32_t ady = (uint32_t)abs(dy), adz = (uint32_t)abs(dz);
+                if (!(in.z & (1u << 27))) {
+                    // the window row: four quads (what falls outside the tile
+                    // goes to the halo; the table is the identity past the
+                    // window's end)
+                    const u64x2 *mrow = reinterpret_cast<const u64x2 *>(mt[(in.z >> 28) & 3u][ady + 6u * adz]);
+                    const u64x2 m01 = mrow[0], m23 = mrow[1];
+                    unsigned long long *sp =
+                        reinterpret_cast<unsigned long long *>(&stamp[(in.z & 0x7FFu) + __umul24(kTilePq, ry) + __umul24(kTileLayer, rz)]);
+                    atomicAnd(sp, m01.x);
+                    atomicAnd(sp + 1, m01.y);
+                    atomicAnd(sp + 2, m23.x);
+                    atomicAnd(sp + 3, m23.y);
                 }
-                if (rs >= 0 && dy >= -rs && dy <= rs && dz >= -rs && dz <= rs) {
-                    // the shadow row: cells lx - 3 .. lx + 3, in 8-cell count
-                    // pairs (two words, one 64-bit add; a byte cannot carry:
-                    // at most 255 hits a round) from (lx - 3) rounded down to 8
-                    const uint32_t bin = in.y >> 17;
-                    const uint32_t m7 = smask[bin * kShadowRows + (uint32_t)(dy + 3) + 7u * (uint32_t)(dz + 3)];
-                    const int xs = lx - 3;
-                    const uint32_t bits = m7 << (xs & 7);
-                    const int p0 = xs >> 3;
-#pragma unroll
-                    for (int i = 0; i < 2; ++i) {
-                        const uint32_t oct = (bits >> (8 * i)) & 0xFFu;
-                        const int pq = p0 + i;   // 8-cell pair of words
-                        if (oct && pq >= 0 && pq < (int)(kTileQx / 2)) {
-                            const unsigned long long v = (unsigned long long)spread4(oct & 0xFu) |
-                                                         ((unsigned long long)spread4(oct >> 4) << 32);
-                            atomicAdd(reinterpret_cast<unsigned long long *>(&cnt[crow + 2u * (uint32_t)pq]), v);
-                        }
-                    }
+                if ((int)ady <= rs && (int)adz <= rs) {
+                    // the shadow row: its 7 cells from lx - 3 as bits from
+                    // the pair's first cell, one count byte each, added to two
+                    // pairs of count words (a byte cannot carry: at most 255
+                    // hits a round)
+                    const uint32_t m7 =
+                        smask[((in.z >> 22) & 31u) * kShadowRows + (uint32_t)(dy + 3) + 7u * (uint32_t)(dz + 3)];
+                    const uint32_t bits = m7 << ((in.w >> 4) & 7u);
+                    unsigned long long *cp = reinterpret_cast<unsigned long long *>(
+                        &cnt[((in.z >> 11) & 0x7FFu) + __umul24(kCntPitch, ry) + __umul24(kCntLayer, rz)]);
+                    atomicAdd(cp, (unsigned long long)spread4(bits & 15u) |
+                                      ((unsigned long long)spread4((bits >> 4) & 15u) << 32));
+                    atomicAdd(cp + 1, (unsigned long long)spread4((bits >> 8) & 15u) |
+                                          ((unsigned long long)spread4(bits >> 12) << 32));
                 }
             }
             lds_barrier();
