@@ -1834,10 +1834,13 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_apply_tile(PipeArgs a) {
     const uint32_t n_work = a.ctrl->n_work;
     // Work items are dealt round-robin. The next item's descriptor and first
     // round of entries (a thread holds at most one of them) are loaded one
-    // item ahead, the descriptor of the item after it two ahead; each is taken
-    // into registers before the plane loads of a round are issued, so that
-    // no wait for them also waits for those (vector loads complete in order),
-    // and every barrier here orders LDS only.
+    // item ahead, the descriptor of the item after it two ahead. A wait for a
+    // vector load also waits for every vector load and store issued before it
+    // (they complete in order), so each is taken into registers where that
+    // costs nothing: the entries before the plane loads of a round are
+    // issued, the descriptor with those plane loads (it is loaded right after
+    // them); no wait comes right after a merge's stores, and every barrier
+    // here orders LDS only.
     const uint32_t G = gridDim.x;
     // Loads of a work item's descriptor (uniform, but loaded per lane so that
     // it is waited for with the vector loads) and of one entry per lane; zero
@@ -1858,6 +1861,7 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_apply_tile(PipeArgs a) {
     uint4 wk = vload(a.work, wi, wi < n_work);
     uint4 ent_cur = eload(wk.z + threadIdx.x, wi < n_work && threadIdx.x < min(wk.w & 0x7FFFFFFFu, kTileRound));
     uint4 wk_next = vload(a.work, wi + G, wi + G < n_work);
+    uint4 wk_nn = make_uint4(0u, 0u, 0u, 0u);   // the descriptor of the item after next
     for (uint32_t c = threadIdx.x; c < kRowBlocks; c += kTileThreads) starts[c] = 0ull;
     // the grid of the last item (loaded again only when it changes)
     uint32_t cur_gi = 0u;
@@ -1911,6 +1915,7 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_apply_tile(PipeArgs a) {
         // for the stores before it.)
 #pragma unroll
         for (uint32_t k = 0; k < kTileQuadsPerThread; ++k) asm volatile("" : "+v"(om[k]), "+v"(op[k]));
+        asm volatile("" : "+v"(wk_nn.x), "+v"(wk_nn.y), "+v"(wk_nn.z), "+v"(wk_nn.w));
 #pragma unroll
         for (uint32_t k = 0; k < kTileQuadsPerThread; ++k) {
             const bool nm = (sq[k].x & sq[k].y) != ~0u, nh = cq[k] != 0u;
@@ -1971,20 +1976,29 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_apply_tile(PipeArgs a) {
         }
     };
     while (wi < n_work) {
-        if (wk.y != cur_gi) {
-            cur_gi = wk.y;
+        // the item's descriptor, uniform: into scalar registers
+        const uint32_t brick = __builtin_amdgcn_readfirstlane(wk.x), gi = __builtin_amdgcn_readfirstlane(wk.y);
+        const uint32_t first = __builtin_amdgcn_readfirstlane(wk.z);
+        const uint32_t total = __builtin_amdgcn_readfirstlane(wk.w) & 0x7FFFFFFFu;
+        if (gi != cur_gi) {
+            cur_gi = gi;
             g = uniform_grid(a.grids[cur_gi]);
+            g.nbx = __builtin_amdgcn_readfirstlane(g.nbx);   // (waited for here, not at every item)
+            g.nby = __builtin_amdgcn_readfirstlane(g.nby);
         }
-        const uint32_t brick = wk.x;
         const uint32_t tx = brick % g.nbx, ty = (brick / g.nbx) % g.nby, tz = brick / (g.nbx * g.nby);
         const int X0 = (int)(tx * kTileX), Y0 = (int)(ty * kTileY), Z0 = (int)(tz * kTileZ);
-        const uint32_t first = wk.z, total = wk.w & 0x7FFFFFFFu;
         // the next item's first round of entries, where this item's last
         // round is its first
-        const uint32_t next_first = wk_next.z;
-        const uint32_t next_nb = wi + G < n_work ? min(wk_next.w & 0x7FFFFFFFu, kTileRound) : 0u;
-        uint4 wk_nn = vload(a.work, wi + 2u * G, wi + 2u * G < n_work);   // the descriptor of the item after next
-        if (total == 0u) ent_cur = eload(next_first + threadIdx.x, threadIdx.x < next_nb);
+        const uint32_t next_first = __builtin_amdgcn_readfirstlane(wk_next.z);
+        const uint32_t next_nb =
+            wi + G < n_work ? min(__builtin_amdgcn_readfirstlane(wk_next.w) & 0x7FFFFFFFu, kTileRound) : 0u;
+        if (total == 0u) {   // (an item without entries: waited for at once)
+            ent_cur = eload(next_first + threadIdx.x, threadIdx.x < next_nb);
+            wk_nn = vload(a.work, wi + 2u * G, wi + 2u * G < n_work);
+            asm volatile("" : "+v"(ent_cur.x), "+v"(ent_cur.y), "+v"(ent_cur.z), "+v"(ent_cur.w), "+v"(wk_nn.x),
+                              "+v"(wk_nn.y), "+v"(wk_nn.z), "+v"(wk_nn.w));
+        }
         for (uint32_t b0 = 0; b0 < total; b0 += kTileRound) {
             const uint32_t nb = min(total - b0, kTileRound);
             lds_barrier();   // the previous round's (or item's) merge is done with the arrays
@@ -2090,12 +2104,12 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_apply_tile(PipeArgs a) {
             // the prefetched values taken into registers now, before the
             // plane loads below are issued
             ent_cur = pe;
-            asm volatile("" : "+v"(ent_cur.x), "+v"(ent_cur.y), "+v"(ent_cur.z), "+v"(ent_cur.w), "+v"(wk_nn.x),
-                              "+v"(wk_nn.y), "+v"(wk_nn.z), "+v"(wk_nn.w));
+            asm volatile("" : "+v"(ent_cur.x), "+v"(ent_cur.y), "+v"(ent_cur.z), "+v"(ent_cur.w));
             // the round's merge (a thread merges the same quads of a tile in
             // every round, so the next round of the same tile loads what this
             // thread stored: program order)
             issue(X0, Y0, Z0, g);
+            if (!more) wk_nn = vload(a.work, wi + 2u * G, wi + 2u * G < n_work);
             finish();
         }
         wi += G;
