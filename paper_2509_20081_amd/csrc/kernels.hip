@@ -2057,46 +2057,72 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_apply_tile(PipeArgs a) {
             }
             if (threadIdx.x == 0) block_base[0] = 0;
             lds_barrier();
-            // The rows, 64 to a wavefront. A lane's entry is the last one
-            // starting at or before its row: block c's entries before it plus
-            // the start bits up to the lane (block 0 starts with entry 0; a
-            // later block has a nonzero base).
-            for (uint32_t c = w; c < n_blocks; c += kWaves) {
-                const uint32_t rho = 64u * c + l;
-                if (rho >= n_rows) continue;
-                const unsigned long long seg = starts[c];
-                const uint4 in = info[block_base[c] + (uint32_t)__popcll(seg & ((2ull << l) - 1ull)) - 1u];
-                const uint32_t rr = rho - in.x;
-                const uint32_t rz = __umul24(rr, in.y) >> 16, ry = rr - __umul24(rz, in.w & 15u);   // rr < 256
-                const int dy = (int)((in.w >> 8) & 15u) - 8 + (int)ry, dz = (int)((in.w >> 12) & 15u) - 8 + (int)rz;
-                const uint32_t ady = (uint32_t)abs(dy), adz = (uint32_t)abs(dz);
-                if (!(in.z & (1u << 27))) {
+            // The rows, 64 to a wavefront, two blocks of rows at a time: the
+            // look-ups of both are issued before the first write (the writes
+            // are ANDs and adds, so their order does not matter). A lane's
+            // entry is the last one starting at or before its row: block c's
+            // entries before it plus the start bits up to the lane (block 0
+            // starts with entry 0; a later block has a nonzero base); a lane
+            // past the last row reads a valid entry and writes nothing.
+            for (uint32_t c0 = w; c0 < n_blocks; c0 += 2u * kWaves) {
+                bool win[2], sh[2];
+                uint32_t qa[2], ca[2], m7[2], shf[2], bb[2];
+                u64x2 m01[2], m23[2];
+                unsigned long long seg[2];
+                uint4 ine[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const uint32_t c = min(c0 + (uint32_t)u * kWaves, n_blocks - 1u);
+                    seg[u] = starts[c];
+                    bb[u] = block_base[c];
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+                    ine[u] = info[bb[u] + (uint32_t)__popcll(seg[u] & ((2ull << l) - 1ull)) - 1u];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const uint32_t rho = 64u * (c0 + (uint32_t)u * kWaves) + l;
+                    const bool on = rho < n_rows;
+                    const uint4 in = ine[u];
+                    const uint32_t rr = rho - in.x;
+                    const uint32_t rz = __umul24(rr & 255u, in.y) >> 16, ry = rr - __umul24(rz, in.w & 15u);
+                    const int dy = (int)((in.w >> 8) & 15u) - 8 + (int)ry, dz = (int)((in.w >> 12) & 15u) - 8 + (int)rz;
+                    const uint32_t ady = min((uint32_t)abs(dy), 5u), adz = min((uint32_t)abs(dz), 5u);
+                    win[u] = on && !(in.z & (1u << 27));
+                    sh[u] = on && (int)ady <= rs && (int)adz <= rs;
                     // the window row: four quads (what falls outside the tile
                     // goes to the halo; the table is the identity past the
                     // window's end)
                     const u64x2 *mrow = reinterpret_cast<const u64x2 *>(mt[(in.z >> 28) & 3u][ady + 6u * adz]);
-                    const u64x2 m01 = mrow[0], m23 = mrow[1];
-                    unsigned long long *sp =
-                        reinterpret_cast<unsigned long long *>(&stamp[(in.z & 0x7FFu) + __umul24(kTilePq, ry) + __umul24(kTileLayer, rz)]);
-                    atomicAnd(sp, m01.x);
-                    atomicAnd(sp + 1, m01.y);
-                    atomicAnd(sp + 2, m23.x);
-                    atomicAnd(sp + 3, m23.y);
-                }
-                if ((int)ady <= rs && (int)adz <= rs) {
+                    m01[u] = mrow[0];
+                    m23[u] = mrow[1];
+                    qa[u] = (in.z & 0x7FFu) + __umul24(kTilePq, ry) + __umul24(kTileLayer, rz);
                     // the shadow row: its 7 cells from lx - 3 as bits from
-                    // the pair's first cell, one count byte each, added to two
-                    // pairs of count words (a byte cannot carry: at most 255
-                    // hits a round)
-                    const uint32_t m7 =
-                        smask[((in.z >> 22) & 31u) * kShadowRows + (uint32_t)(dy + 3) + 7u * (uint32_t)(dz + 3)];
-                    const uint32_t bits = m7 << ((in.w >> 4) & 7u);
-                    unsigned long long *cp = reinterpret_cast<unsigned long long *>(
-                        &cnt[((in.z >> 11) & 0x7FFu) + __umul24(kCntPitch, ry) + __umul24(kCntLayer, rz)]);
-                    atomicAdd(cp, (unsigned long long)spread4(bits & 15u) |
-                                      ((unsigned long long)spread4((bits >> 4) & 15u) << 32));
-                    atomicAdd(cp + 1, (unsigned long long)spread4((bits >> 8) & 15u) |
-                                          ((unsigned long long)spread4(bits >> 12) << 32));
+                    // the pair's first cell
+                    m7[u] = smask[sh[u] ? ((in.z >> 22) & 31u) * kShadowRows + (uint32_t)(dy + 3) + 7u * (uint32_t)(dz + 3)
+                                        : 0u];
+                    shf[u] = (in.w >> 4) & 7u;
+                    ca[u] = ((in.z >> 11) & 0x7FFu) + __umul24(kCntPitch, ry) + __umul24(kCntLayer, rz);
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    if (win[u]) {
+                        unsigned long long *sp = reinterpret_cast<unsigned long long *>(&stamp[qa[u]]);
+                        atomicAnd(sp, m01[u].x);
+                        atomicAnd(sp + 1, m01[u].y);
+                        atomicAnd(sp + 2, m23[u].x);
+                        atomicAnd(sp + 3, m23[u].y);
+                    }
+                    if (sh[u]) {
+                        // one count byte a cell, added to two pairs of count
+                        // words (a byte cannot carry: at most 255 hits a round)
+                        const uint32_t bits = m7[u] << shf[u];
+                        unsigned long long *cp = reinterpret_cast<unsigned long long *>(&cnt[ca[u]]);
+                        atomicAdd(cp, (unsigned long long)spread4(bits & 15u) |
+                                          ((unsigned long long)spread4((bits >> 4) & 15u) << 32));
+                        atomicAdd(cp + 1, (unsigned long long)spread4((bits >> 8) & 15u) |
+                                              ((unsigned long long)spread4(bits >> 12) << 32));
+                    }
                 }
             }
             lds_barrier();
