@@ -1920,9 +1920,10 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_apply_tile(PipeArgs a) {
         for (uint32_t k = 0; k < kTileQuadsPerThread; ++k) {
             const bool nm = (sq[k].x & sq[k].y) != ~0u, nh = cq[k] != 0u;
             if (!nm && !nh) continue;
-            uint32_t mm[4] = {sq[k].x & 0xFFFFu, sq[k].x >> 16, sq[k].y & 0xFFFFu, sq[k].y >> 16};
-#pragma unroll
-            for (int j = 0; j < 4; ++j) mm[j] = mm[j] == 0xFFFFu ? ~0u : mm[j];
+            // the 16-bit stamps sign-extended: the identity 0xFFFF becomes
+            // ~0, and every eq. 3 mask (below 2^15) stays as it is
+            const uint32_t mm[4] = {(uint32_t)(int32_t)(int16_t)(sq[k].x & 0xFFFFu), (uint32_t)((int32_t)sq[k].x >> 16),
+                                    (uint32_t)(int32_t)(int16_t)(sq[k].y & 0xFFFFu), (uint32_t)((int32_t)sq[k].y >> 16)};
             const uint32_t gz = pgz + kQz * k;
             const size_t lin = plin + (size_t)k * pstep;
             if (pxy && gz < pg.nz) {
@@ -1938,6 +1939,9 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_apply_tile(PipeArgs a) {
                     if (ch) gstore4(pg.mask + lin, nw[0], nw[1], nw[2], nw[3]);
                 }
                 if (nh) {
+                    // (a word without hits comes out unchanged: its bits 16-30
+                    // are clear and its counter is at most H_max, invariants
+                    // of the planes)
                     const uint32_t o[4] = {op[k][0], op[k][1], op[k][2], op[k][3]};
                     uint32_t nw[4];
 #pragma unroll
@@ -1946,7 +1950,7 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_apply_tile(PipeArgs a) {
                         const uint32_t h0 = o[j] & 0xFFFFu;
                         const uint32_t h1 = min(h0 + c, pg.hmax);
                         const uint32_t sign = (h0 < pg.T && h1 >= pg.T) ? 0u : (o[j] & 0x80000000u);
-                        nw[j] = c ? (sign | h1) : o[j];
+                        nw[j] = sign | h1;
                     }
                     gstore4(pg.packed + lin, nw[0], nw[1], nw[2], nw[3]);
                 }
