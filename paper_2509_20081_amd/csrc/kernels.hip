@@ -1779,6 +1779,26 @@ static_assert(kTileLayer * (kTileZ - 1) + kTilePq * (kTileY - 1) + 2 * kHaloQ + 
                   kTileSlots < 2048 && kCntSlots < 2048, "row bases fit 11 bits");
 typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 
+// Division of a 32-bit n by a divisor d >= 1 fixed for many divisions, as a
+// multiply-high and shifts (Granlund and Montgomery's round-up method with a
+// 33-bit multiplier: l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1,
+// t = mulhi(m, n), n / d = (t + ((n - t) >> 1)) >> (l - 1); for d = 1 the
+// shifts are 0 and t = 0). Exact for every n and d.
+struct FastDiv {
+    uint32_t m, s1, s2;
+};
+__device__ __forceinline__ FastDiv fastdiv_of(uint32_t d) {
+    const uint32_t l = d > 1u ? 32u - (uint32_t)__clz(d - 1u) : 0u;
+    const uint64_t m = ((((uint64_t)1 << l) - d) << 32) / d + 1u;
+    // (d is uniform where this is used: the fields go to scalar registers)
+    return FastDiv{(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)m), l ? 1u : 0u,
+                   (uint32_t)__builtin_amdgcn_readfirstlane(l ? l - 1u : 0u)};
+}
+__device__ __forceinline__ uint32_t fastdiv(uint32_t n, const FastDiv &f) {
+    const uint32_t t = __umulhi(n, f.m);
+    return (t + ((n - t) >> f.s1)) >> f.s2;
+}
+
 __device__ __forceinline__ uint32_t spread4(uint32_t b4) {   // bit j -> byte j
     return (b4 * 0x00204081u) & 0x01010101u;
 }
@@ -1863,9 +1883,13 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_apply_tile(PipeArgs a) {
     uint4 wk_next = vload(a.work, wi + G, wi + G < n_work);
     uint4 wk_nn = make_uint4(0u, 0u, 0u, 0u);   // the descriptor of the item after next
     for (uint32_t c = threadIdx.x; c < kRowBlocks; c += kTileThreads) starts[c] = 0ull;
-    // the grid of the last item (loaded again only when it changes)
+    // the grid of the last item (loaded again only when it changes), and its
+    // tile counts per row and layer as divisors
     uint32_t cur_gi = 0u;
     DevGrid g = uniform_grid(a.grids[0]);
+    g.nbx = __builtin_amdgcn_readfirstlane(g.nbx);
+    g.nby = __builtin_amdgcn_readfirstlane(g.nby);
+    FastDiv div_x = fastdiv_of(g.nbx), div_y = fastdiv_of(g.nby);
     // The merge of a round: each thread takes the stamps and counts of its
     // quads into registers and issues the loads of the words they touch
     // (issue), then updates and stores them (finish). Other workgroups on the
@@ -1989,8 +2013,11 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_apply_tile(PipeArgs a) {
             g = uniform_grid(a.grids[cur_gi]);
             g.nbx = __builtin_amdgcn_readfirstlane(g.nbx);   // (waited for here, not at every item)
             g.nby = __builtin_amdgcn_readfirstlane(g.nby);
+            div_x = fastdiv_of(g.nbx);
+            div_y = fastdiv_of(g.nby);
         }
-        const uint32_t tx = brick % g.nbx, ty = (brick / g.nbx) % g.nby, tz = brick / (g.nbx * g.nby);
+        const uint32_t bq = fastdiv(brick, div_x), tz = fastdiv(bq, div_y);
+        const uint32_t tx = brick - bq * g.nbx, ty = bq - tz * g.nby;
         const int X0 = (int)(tx * kTileX), Y0 = (int)(ty * kTileY), Z0 = (int)(tz * kTileZ);
         // the next item's first round of entries, where this item's last
         // round is its first
