@@ -2070,11 +2070,21 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_apply_tile(PipeArgs a) {
                 }
             }
             // one scan over the round: the rows before the entry (high bits)
-            // and the entries with rows before it (low 9 bits)
-            uint32_t tot;
-            const uint32_t ex = block_excl_scan<kTileThreads, true>((rows << 9) | (rows ? 1u : 0u), s_scan, tot);
-            const uint32_t n_rows = tot >> 9;
-            const uint32_t n_blocks = (n_rows + 63u) / 64u;
+            // and the entries with rows before it (low 9 bits); a round of at
+            // most 64 entries has them all in wavefront 0, whose own scan
+            // needs no barrier (the others take its total after the next one)
+            const uint32_t sv = (rows << 9) | (rows ? 1u : 0u);
+            uint32_t ex, tot;
+            if (nb <= 64u) {
+                const uint32_t incl = wave_incl_scan_u32(sv);
+                ex = incl - sv;
+                tot = __shfl(incl, 63);
+                if (threadIdx.x == 63u) s_scan[kWaves] = incl;
+            } else {
+                ex = block_excl_scan<kTileThreads, true>(sv, s_scan, tot);
+            }
+            uint32_t n_rows = tot >> 9;
+            uint32_t n_blocks = (n_rows + 63u) / 64u;
             if (rows) {
                 const uint32_t k_e = ex & 511u, r0 = ex >> 9;
                 inf.x = r0;
@@ -2088,6 +2098,10 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_apply_tile(PipeArgs a) {
             }
             if (threadIdx.x == 0) block_base[0] = 0;
             lds_barrier();
+            if (nb <= 64u) {
+                n_rows = s_scan[kWaves] >> 9;
+                n_blocks = (n_rows + 63u) / 64u;
+            }
             // The rows, 64 to a wavefront, two blocks of rows at a time: the
             // look-ups of both are issued before the first write (the writes
             // are ANDs and adds, so their order does not matter). A lane's
