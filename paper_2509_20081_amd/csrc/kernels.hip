@@ -2386,11 +2386,13 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh(MeshArgs m) {
 
 // Point export: the centres of the occupied contact voxels (a return landed
 // there, mask 0, and the hit counter confirmed it, sign 0). A wavefront takes
-// kPointRows consecutive rows of the box: a counting pass (four 64-voxel
-// pieces of a row loaded together, ballots counted), one atomic to reserve
-// the group's room, then the writing pass with the lanes' ranks from the
-// ballots (its loads mostly hit the caches the counting pass filled).
+// kPointRows consecutive rows of the box: a counting pass (kPointPieces
+// 64-voxel pieces of a row at a time: all their mask loads, then the counter
+// loads where a mask is 0, then one wait and the ballots), one atomic to
+// reserve the group's room, then the writing pass with the lanes' ranks from
+// the ballots (its loads mostly hit the caches the counting pass filled).
 constexpr uint32_t kPointRows = 8;
+constexpr int kPointPieces = 8;
 __global__ __launch_bounds__(kMeshThreads) void k_points(MeshArgs m) {
     const uint32_t l = lane();
     const uint64_t n_rows = (uint64_t)m.nc[1] * m.nc[2];
@@ -2399,32 +2401,38 @@ __global__ __launch_bounds__(kMeshThreads) void k_points(MeshArgs m) {
     const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const unsigned long long below = l ? ((1ull << l) - 1ull) : 0ull;
     const uint32_t W = m.nc[0];
-    // ballots of the occupied voxels of row r, pieces x0 .. x0 + 255
-    auto ballots = [&](uint64_t r, uint32_t x0, unsigned long long bal[4]) {
+    // ballots of the occupied voxels of row r, pieces x0 .. x0 + 64 kPointPieces - 1
+    auto ballots = [&](uint64_t r, uint32_t x0, unsigned long long bal[kPointPieces]) {
         const uint32_t j = m.lo[1] + (uint32_t)(r % m.nc[1]), k = m.lo[2] + (uint32_t)(r / m.nc[1]);
         const uint64_t base = m.lo[0] + (uint64_t)m.nx * (j + (uint64_t)m.ny * k);
-        uint32_t mk[4];
+        uint32_t mk[kPointPieces], pk[kPointPieces];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kPointPieces; ++u) {   // (every lane loads: past the row's end, its last voxel)
             const uint32_t x = x0 + 64u * (uint32_t)u + l;
-            mk[u] = x < W ? m.mask[base + x] : 1u;
+            const uint32_t v = m.mask[base + min(x, W - 1u)];
+            mk[u] = x < W ? v : 1u;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kPointPieces; ++u) {   // the counter only where the mask is 0
             const uint32_t x = x0 + 64u * (uint32_t)u + l;
-            const bool occ = mk[u] == 0u && (m.packed[base + x] >> 31) == 0u;   // packed read only where mask is 0
-            bal[u] = __ballot(occ);
+            pk[u] = 0x80000000u;
+            if (mk[u] == 0u) pk[u] = m.packed[base + x];
         }
+        // (all the counter loads are issued before the first is used)
+#pragma unroll
+        for (int u = 0; u < kPointPieces; ++u) asm volatile("" : "+v"(pk[u]));
+#pragma unroll
+        for (int u = 0; u < kPointPieces; ++u) bal[u] = __ballot(mk[u] == 0u && (pk[u] >> 31) == 0u);
     };
     for (uint64_t grp = (uint64_t)blockIdx.x * wpb + wid; grp < n_groups; grp += (uint64_t)gridDim.x * wpb) {
         const uint64_t r0 = grp * kPointRows, r1 = min(r0 + kPointRows, n_rows);
         uint32_t cnt = 0;
         for (uint64_t r = r0; r < r1; ++r)
-            for (uint32_t x0 = 0; x0 < W; x0 += 256u) {
-                unsigned long long bal[4];
+            for (uint32_t x0 = 0; x0 < W; x0 += 64u * kPointPieces) {
+                unsigned long long bal[kPointPieces];
                 ballots(r, x0, bal);
 #pragma unroll
-                for (int u = 0; u < 4; ++u) cnt += (uint32_t)__popcll(bal[u]);
+                for (int u = 0; u < kPointPieces; ++u) cnt += (uint32_t)__popcll(bal[u]);
             }
         if (cnt == 0u) continue;
         unsigned long long first = 0;
@@ -2433,11 +2441,11 @@ __global__ __launch_bounds__(kMeshThreads) void k_points(MeshArgs m) {
         if (!m.out) continue;   // counting only
         for (uint64_t r = r0; r < r1; ++r) {
             const uint32_t j = m.lo[1] + (uint32_t)(r % m.nc[1]), k = m.lo[2] + (uint32_t)(r / m.nc[1]);
-            for (uint32_t x0 = 0; x0 < W; x0 += 256u) {
-                unsigned long long bal[4];
+            for (uint32_t x0 = 0; x0 < W; x0 += 64u * kPointPieces) {
+                unsigned long long bal[kPointPieces];
                 ballots(r, x0, bal);
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < kPointPieces; ++u) {
                     if ((bal[u] >> l) & 1ull) {
                         const unsigned long long slot = first + (unsigned long long)__popcll(bal[u] & below);
                         if (slot < m.cap) {
