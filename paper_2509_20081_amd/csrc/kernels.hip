@@ -2392,7 +2392,7 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh(MeshArgs m) {
 // reserve the group's room, then the writing pass with the lanes' ranks from
 // the ballots (its loads mostly hit the caches the counting pass filled).
 constexpr uint32_t kPointRows = 8;
-constexpr int kPointPieces = 8;
+constexpr int kPointPieces = 16;
 __global__ __launch_bounds__(kMeshThreads) void k_points(MeshArgs m) {
     const uint32_t l = lane();
     const uint64_t n_rows = (uint64_t)m.nc[1] * m.nc[2];
