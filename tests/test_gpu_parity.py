@@ -58,6 +58,10 @@ TINY_CASES = [
          cone_deg=35.0),
     dict(seed=11, K=7, dims=(44, 40, 36), binning="azel", bins_az=8, bins_el=5, shadow_r2=9, shadow_model="cone",
          cone_deg=50.0),
+    # within the tile strategy's limits: the L1 metric (its mask table is even in dy and dz too), K = 9 with a
+    # small counter ceiling, grid sides that are not multiples of the 32 x 16 x 8 tile
+    dict(seed=12, K=7, dims=(45, 38, 27), binning="cube26", shadow_r2=4, hit_threshold=2, metric="l1"),
+    dict(seed=13, K=9, dims=(53, 35, 41), binning="cube26", shadow_r2=9, hit_threshold=3, hit_max=7),
 ]
 
 TUNINGS = [
