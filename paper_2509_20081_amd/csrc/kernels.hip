@@ -2390,9 +2390,11 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh(MeshArgs m) {
 // 64-voxel pieces of a row at a time: all their mask loads, then the counter
 // loads where a mask is 0, then one wait and the ballots), one atomic to
 // reserve the group's room, then the writing pass with the lanes' ranks from
-// the ballots (its loads mostly hit the caches the counting pass filled).
+// the ballots: kept in LDS by the counting pass where the group's rows have
+// at most kPointKeep pieces (rows of up to 2048 voxels), else loaded again.
 constexpr uint32_t kPointRows = 8;
 constexpr int kPointPieces = 16;
+constexpr uint32_t kPointKeep = 256;
 __global__ __launch_bounds__(kMeshThreads) void k_points(MeshArgs m) {
     const uint32_t l = lane();
     const uint64_t n_rows = (uint64_t)m.nc[1] * m.nc[2];
@@ -2401,6 +2403,9 @@ __global__ __launch_bounds__(kMeshThreads) void k_points(MeshArgs m) {
     const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const unsigned long long below = l ? ((1ull << l) - 1ull) : 0ull;
     const uint32_t W = m.nc[0];
+    __shared__ unsigned long long s_bal[kMeshThreads / 64][kPointKeep];   // a wavefront's ballots, in order
+    // pieces of a row, in whole steps
+    const uint32_t row_pieces = (W + 64u * kPointPieces - 1u) / (64u * kPointPieces) * kPointPieces;
     // ballots of the occupied voxels of row r, pieces x0 .. x0 + 64 kPointPieces - 1
     auto ballots = [&](uint64_t r, uint32_t x0, unsigned long long bal[kPointPieces]) {
         const uint32_t j = m.lo[1] + (uint32_t)(r % m.nc[1]), k = m.lo[2] + (uint32_t)(r / m.nc[1]);
@@ -2426,13 +2431,18 @@ __global__ __launch_bounds__(kMeshThreads) void k_points(MeshArgs m) {
     };
     for (uint64_t grp = (uint64_t)blockIdx.x * wpb + wid; grp < n_groups; grp += (uint64_t)gridDim.x * wpb) {
         const uint64_t r0 = grp * kPointRows, r1 = min(r0 + kPointRows, n_rows);
+        const bool keep = (uint64_t)(r1 - r0) * row_pieces <= kPointKeep;
         uint32_t cnt = 0;
         for (uint64_t r = r0; r < r1; ++r)
             for (uint32_t x0 = 0; x0 < W; x0 += 64u * kPointPieces) {
                 unsigned long long bal[kPointPieces];
                 ballots(r, x0, bal);
+                const uint32_t p0 = (uint32_t)(r - r0) * row_pieces + x0 / 64u;
 #pragma unroll
-                for (int u = 0; u < kPointPieces; ++u) cnt += (uint32_t)__popcll(bal[u]);
+                for (int u = 0; u < kPointPieces; ++u) {
+                    cnt += (uint32_t)__popcll(bal[u]);
+                    if (keep && l == (uint32_t)u) s_bal[wid][p0 + (uint32_t)u] = bal[u];
+                }
             }
         if (cnt == 0u) continue;
         unsigned long long first = 0;
@@ -2443,7 +2453,13 @@ __global__ __launch_bounds__(kMeshThreads) void k_points(MeshArgs m) {
             const uint32_t j = m.lo[1] + (uint32_t)(r % m.nc[1]), k = m.lo[2] + (uint32_t)(r / m.nc[1]);
             for (uint32_t x0 = 0; x0 < W; x0 += 64u * kPointPieces) {
                 unsigned long long bal[kPointPieces];
-                ballots(r, x0, bal);
+                if (keep) {   // (this wavefront's own LDS writes, in program order)
+                    const uint32_t p0 = (uint32_t)(r - r0) * row_pieces + x0 / 64u;
+#pragma unroll
+                    for (int u = 0; u < kPointPieces; ++u) bal[u] = s_bal[wid][p0 + (uint32_t)u];
+                } else {
+                    ballots(r, x0, bal);
+                }
 #pragma unroll
                 for (int u = 0; u < kPointPieces; ++u) {
                     if ((bal[u] >> l) & 1ull) {
