@@ -2055,7 +2055,12 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_apply_tile(PipeArgs a) {
                         rows = (uint32_t)(wy * wz);
                         // the first row's stamp quad (the window's quads from
                         // (lx - R) >> 2) and count word (the shadow's pairs
-                        // from (lx - 3) >> 3), halo included; its (dy, dz)
+                        // from (lx - 3) >> 3), halo included, and its (dy, dz).
+                        // info: x first row of the round (set below), y the
+                        // magic of wy; z stamp quad (bits 0-10), count word
+                        // (11-21), bin (22-26), revisit (27), window phase
+                        // (28-29); w wy (0-3), the shadow row's shift (4-6),
+                        // dy + 8 (8-11), dz + 8 (12-15)
                         const int xs = lx - R, sx = lx - 3;
                         const uint32_t qb = (uint32_t)((xs >> 2) + (int)kHaloQ) + kTilePq * (uint32_t)ya +
                                             kTileLayer * (uint32_t)za;
